@@ -1,0 +1,192 @@
+"""CPU FP64 oracle for PTP: ctypes wrapper around ``ptp_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares nothing with
+the HIP library; the shared library it loads is built from ``ptp_oracle.c``
+alone by ``oracle.build_oracle()`` (plain gcc).
+
+All functions take numpy arrays: V float32 [n, 3] (promoted exactly to
+float64 here), F int32 [f, 3], S int32 [m].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ptp_oracle.c")
+_LIB = os.path.join(_HERE, "libptp_oracle.so")
+
+OK, EINVAL, ENOMEM, ENOCONV = 0, -1, -2, -4
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile ptp_oracle.c into libptp_oracle.so next to it (gcc -O3)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("band_rule", C.c_int),
+                ("window", C.c_int), ("advance_all", C.c_int)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("rho", C.c_int), ("reachable", C.c_int),
+                ("updates", C.c_longlong)]
+
+
+_lib = None
+
+
+def load_library(path: str) -> C.CDLL:
+    """Load an oracle build (the default one, or a variant compiled by a test)
+    and declare its signatures."""
+    lib = C.CDLL(path)
+    _declare(lib)
+    return lib
+
+
+def build_variant(c_source: str, out_path: str) -> str:
+    """Compile a modified copy of the oracle source (used by the tests that
+    plant a mistake in the oracle to show the pins catch it)."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(c_source)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", out_path, src, "-lm"])
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+def _L(lib=None):
+    global _lib
+    if lib is not None:
+        return lib
+    if _lib is None:
+        build_oracle()
+        _lib = load_library(_LIB)
+    return _lib
+
+
+def _declare(lib):
+    P = np.ctypeslib.ndpointer
+    dptr = P(np.float64, flags="C")
+    iptr = P(np.int32, flags="C")
+    lib.ptpo_toplesets.argtypes = [C.c_int, C.c_int, iptr, C.c_int, iptr, iptr, iptr, iptr,
+                                   C.POINTER(C.c_int)]
+    lib.ptpo_local_update.argtypes = [dptr, dptr, dptr, C.c_double, C.c_double,
+                                      C.POINTER(C.c_int)]
+    lib.ptpo_local_update.restype = C.c_double
+    lib.ptpo_run.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
+                             dptr, iptr, C.POINTER(_Stats), iptr, iptr, dptr, C.c_int]
+    lib.ptpo_fixed_point.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.c_int,
+                                     dptr, iptr, C.POINTER(C.c_int)]
+    lib.ptpo_fast_marching.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, dptr]
+
+
+def _prep(V, F, S):
+    X = np.ascontiguousarray(np.asarray(V, dtype=np.float32), dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    return X, F, S
+
+
+def local_update(x0, x1, x2, d1, d2, lib=None):
+    """Planar update of x0 from (x1, d1), (x2, d2).  Returns (value, who):
+    who = 1 or 2 when the result is the edge update through x1 / x2 (or a
+    planar solution whose smaller input is that vertex), -1 when both inputs
+    are infinite."""
+    lab = C.c_int(0)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (x0, x1, x2)]
+    p = _L(lib).ptpo_local_update(a[0], a[1], a[2], float(d1), float(d2), C.byref(lab))
+    return p, lab.value
+
+
+def toplesets(V, F, S, lib=None):
+    """Returns (level[n], order[n], offsets[rho + 1], rho)."""
+    _, F, S = _prep(V, F, S)
+    n = int(np.asarray(V).shape[0])
+    level = np.empty(n, np.int32)
+    order = np.empty(n, np.int32)
+    offsets = np.empty(n + 2, np.int32)
+    rho = C.c_int(0)
+    rc = _L(lib).ptpo_toplesets(n, F.shape[0], F, S.shape[0], S, level, order, offsets,
+                             C.byref(rho))
+    if rc != OK:
+        raise ValueError(f"ptpo_toplesets failed: {rc}")
+    return level, order, offsets[: rho.value + 1].copy(), rho.value
+
+
+@dataclass
+class Result:
+    dist: np.ndarray
+    label: np.ndarray
+    status: int
+    iterations: int
+    rho: int
+    reachable: int
+    updates: int
+    retire_k: np.ndarray
+    trace_lo: np.ndarray
+    trace_maxrel: np.ndarray
+
+
+def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, advance_all=False,
+        trace_len=None, lib=None) -> Result:
+    """PTP with the paper's band rule (band_rule=0) or the fixed half band
+    (band_rule=1).  Returns distances and labels in the caller's order."""
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    dist = np.empty(n, np.float64)
+    label = np.empty(n, np.int32)
+    retire = np.empty(n, np.int32)
+    if trace_len is None:
+        trace_len = (max_iters if max_iters > 0 else 4 * n + 16) + 1
+        trace_len = min(trace_len, 1 << 22)
+    tlo = np.full(trace_len, -1, np.int32)
+    tmr = np.full(trace_len, np.nan, np.float64)
+    st = _Stats()
+    opts = _Opts(float(tol), int(max_iters), int(band_rule), int(window), int(bool(advance_all)))
+    rc = _L(lib).ptpo_run(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), dist, label,
+                       C.byref(st), retire, tlo, tmr, trace_len)
+    if rc not in (OK, ENOCONV):
+        raise ValueError(f"ptpo_run failed: {rc}")
+    K = st.iterations
+    return Result(dist, label, rc, K, st.rho, st.reachable, int(st.updates),
+                  retire[: st.rho].copy(), tlo[: K + 1].copy(), tmr[: K + 1].copy())
+
+
+def fixed_point(V, F, S, max_sweeps=100000, lib=None):
+    """Jacobi from +inf until no value changes.  Returns (dist, label, sweeps)."""
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    dist = np.empty(n, np.float64)
+    label = np.empty(n, np.int32)
+    sw = C.c_int(0)
+    rc = _L(lib).ptpo_fixed_point(n, F.shape[0], X, F, S.shape[0], S, int(max_sweeps), dist,
+                               label, C.byref(sw))
+    if rc != OK:
+        raise ValueError(f"ptpo_fixed_point failed: {rc}")
+    return dist, label, sw.value
+
+
+def fast_marching(V, F, S, lib=None):
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    dist = np.empty(n, np.float64)
+    rc = _L(lib).ptpo_fast_marching(n, F.shape[0], X, F, S.shape[0], S, dist)
+    if rc != OK:
+        raise ValueError(f"ptpo_fast_marching failed: {rc}")
+    return dist

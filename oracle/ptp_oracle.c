@@ -1,0 +1,606 @@
+/*
+ * CPU FP64 oracle for Parallel Toplesets Propagation (PTP), written from the
+ * paper (Romero Calla, Fuentes Perez, Montenegro, "A minimalistic approach for
+ * fast computation of geodesic distances on triangular meshes").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the HIP
+ * library: it is a plain, slow, sequential restatement of the method.
+ *
+ * Contents
+ *   ptpo_toplesets      topological level sets by BFS (Sec. 4.1, Definition of
+ *                       V_r) and their canonical order (Sec. 4.3 reorder; the
+ *                       order inside a topleset is ascending vertex id).
+ *   ptpo_local_update   the planar (Kimmel-Sethian) update of a vertex from one
+ *                       incident triangle, in the matrix form with the
+ *                       monotonicity test Q X^T n < 0 (Sec. 3.2).
+ *   ptpo_run            the PTP iteration: Jacobi update of the band
+ *                       B_{i_k}^{j_k} (Sec. 4.2), band ends from Eq. upper_band
+ *                       and Eq. lower_band; optionally the fixed half band of
+ *                       the complexity analysis (Sec. 6).
+ *   ptpo_fixed_point    plain Jacobi over all vertices until nothing changes:
+ *                       the fixed point d* that PTP approximates.
+ *   ptpo_fast_marching  sequential Fast Marching (Sec. 3.2) with the same
+ *                       local update and accepted-only inputs.
+ *
+ * Precision: all arithmetic in double.  Coordinates arrive as doubles that
+ * the caller promoted exactly from the float32 mesh.
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   - V_0 = S is converged from the start; the band starts at i = 1.
+ *   - a value that was still infinite at the previous iteration is not
+ *     converged; an unchanged value counts as converged (avoids 0/0).
+ *   - the band of iteration k is [i_{k-1}, j_k]; V_{i_{k-1}} is then tested
+ *     to obtain i_k; at most one topleset retires per iteration.
+ *   - new value = min(old value, min over incident triangles of the update).
+ *   - unreachable vertices keep +inf and label -1 and are ordered last.
+ *   - degenerate triangle (det G <= 1e-12 a c): edge updates only.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PTPO_OK 0
+#define PTPO_EINVAL (-1)
+#define PTPO_ENOMEM (-2)
+#define PTPO_ENOCONV (-4)
+
+/* ------------------------------------------------------------------ */
+/* vertex -> incident faces                                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int n, nf;
+    int *start; /* n + 1 */
+    int *face;  /* 3 nf */
+} incidence;
+
+static int build_incidence(int n, int nf, const int *F, incidence *inc)
+{
+    inc->n = n;
+    inc->nf = nf;
+    inc->start = (int *)calloc((size_t)n + 1, sizeof(int));
+    inc->face = (int *)malloc(sizeof(int) * (size_t)(3 * (size_t)nf + 1));
+    int *fill = (int *)calloc((size_t)n + 1, sizeof(int));
+    if (!inc->start || !inc->face || !fill) {
+        free(inc->start); free(inc->face); free(fill);
+        return PTPO_ENOMEM;
+    }
+    for (size_t t = 0; t < 3 * (size_t)nf; ++t)
+        inc->start[F[t] + 1] += 1;
+    for (int v = 0; v < n; ++v)
+        inc->start[v + 1] += inc->start[v];
+    for (int t = 0; t < nf; ++t)
+        for (int c = 0; c < 3; ++c) {
+            int v = F[3 * t + c];
+            inc->face[inc->start[v] + fill[v]++] = t;
+        }
+    free(fill);
+    return PTPO_OK;
+}
+
+static void free_incidence(incidence *inc)
+{
+    free(inc->start);
+    free(inc->face);
+}
+
+static int check_mesh(int n, int nf, const int *F, int m, const int *S)
+{
+    if (n <= 0 || nf < 0 || m <= 0) return PTPO_EINVAL;
+    for (size_t t = 0; t < 3 * (size_t)nf; ++t)
+        if (F[t] < 0 || F[t] >= n) return PTPO_EINVAL;
+    for (int a = 0; a < m; ++a) {
+        if (S[a] < 0 || S[a] >= n) return PTPO_EINVAL;
+        for (int b = 0; b < a; ++b)
+            if (S[a] == S[b]) return PTPO_EINVAL;
+    }
+    return PTPO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* toplesets: BFS hop distance from S over the edges of the faces      */
+/* ------------------------------------------------------------------ */
+
+static int toplesets_with(const incidence *inc, const int *F, int m, const int *S,
+                          int *level, int *order, int *offsets, int *rho_out)
+{
+    int n = inc->n;
+    int *queue = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!queue) return PTPO_ENOMEM;
+    for (int v = 0; v < n; ++v) level[v] = -1;
+    int head = 0, tail = 0;
+    for (int a = 0; a < m; ++a) {
+        level[S[a]] = 0;
+        queue[tail++] = S[a];
+    }
+    int maxlev = 0;
+    while (head < tail) {
+        int v = queue[head++];
+        for (int e = inc->start[v]; e < inc->start[v + 1]; ++e) {
+            const int *f = F + 3 * inc->face[e];
+            for (int c = 0; c < 3; ++c) {
+                int u = f[c];
+                if (level[u] < 0) {
+                    level[u] = level[v] + 1;
+                    if (level[u] > maxlev) maxlev = level[u];
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    free(queue);
+    int rho = maxlev + 1;
+    /* canonical order: by level, ascending id inside a level; unreachable last */
+    int *count = (int *)calloc((size_t)rho + 2, sizeof(int));
+    if (!count) return PTPO_ENOMEM;
+    for (int v = 0; v < n; ++v) {
+        int b = level[v] < 0 ? rho : level[v];
+        count[b + 1] += 1;
+    }
+    for (int r = 0; r <= rho; ++r) count[r + 1] += count[r];
+    if (offsets)
+        for (int r = 0; r <= rho; ++r) offsets[r] = count[r];
+    for (int v = 0; v < n; ++v) {
+        int b = level[v] < 0 ? rho : level[v];
+        order[count[b]++] = v;
+    }
+    free(count);
+    *rho_out = rho;
+    return PTPO_OK;
+}
+
+/* level[n]: hop distance (-1 unreachable); order[n]: vertex ids sorted by
+ * (level, id) with unreachable vertices last; offsets[rho + 1]: V_r is
+ * order[offsets[r] .. offsets[r+1]); caller sizes offsets for n + 1.     */
+int ptpo_toplesets(int n, int nf, const int *F, int m, const int *S,
+                   int *level, int *order, int *offsets, int *rho)
+{
+    int rc = check_mesh(n, nf, F, m, S);
+    if (rc) return rc;
+    incidence inc;
+    rc = build_incidence(n, nf, F, &inc);
+    if (rc) return rc;
+    rc = toplesets_with(&inc, F, m, S, level, order, offsets, rho);
+    free_incidence(&inc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* local update (Sec. 3.2, update_step)                                */
+/* ------------------------------------------------------------------ */
+
+/* The distance is modelled on the triangle (x0, x1, x2) as a plane front
+ * phi(x) = n . x + c with |n| = 1 and n in the triangle's plane, through
+ * (x1, d1) and (x2, d2).  With X = [x1 - x0, x2 - x0], Q = (X^T X)^{-1} and
+ * t = (d1, d2) the unknown p = phi(x0) satisfies
+ *     (t - p 1)^T Q (t - p 1) = 1,
+ * a quadratic in p whose larger root is taken.  The solution is accepted only
+ * when Q X^T n = Q (t - p 1) < 0 in both components (the monotonicity
+ * condition); otherwise, and when either input is missing, the update comes
+ * from the edges, min_i (d_i + |x_i - x0|).
+ *
+ * Labels: an edge update takes the label of its vertex; the planar solution
+ * the label of its smaller input (a tie takes the smaller label).        */
+static double local_update(const double *x0, const double *x1, const double *x2,
+                           double d1, double d2, int l1, int l2, int *lab_out)
+{
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) {
+        e1[c] = x1[c] - x0[c];
+        e2[c] = x2[c] - x0[c];
+    }
+    double a = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    double b = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+    double c = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    int f1 = isfinite(d1), f2 = isfinite(d2);
+    if (!f1 && !f2) {
+        *lab_out = -1;
+        return INFINITY;
+    }
+    if (!f2) {
+        *lab_out = l1;
+        return d1 + sqrt(a);
+    }
+    if (!f1) {
+        *lab_out = l2;
+        return d2 + sqrt(c);
+    }
+    double p1 = d1 + sqrt(a), p2 = d2 + sqrt(c);
+    double pedge;
+    int ledge;
+    if (p1 < p2) { pedge = p1; ledge = l1; }
+    else if (p2 < p1) { pedge = p2; ledge = l2; }
+    else { pedge = p1; ledge = l1 < l2 ? l1 : l2; }
+
+    double det = a * c - b * b;
+    if (!(det > 1e-12 * a * c)) {
+        *lab_out = ledge;
+        return pedge;
+    }
+    /* Q = G^{-1} = [[c, -b], [-b, a]] / det */
+    double q11 = c / det, q12 = -b / det, q22 = a / det;
+    double s11 = q11 + 2.0 * q12 + q22;                    /* 1^T Q 1 */
+    double s1t = (q11 + q12) * d1 + (q12 + q22) * d2;      /* 1^T Q t */
+    double stt = q11 * d1 * d1 + 2.0 * q12 * d1 * d2 + q22 * d2 * d2; /* t^T Q t */
+    double disc = s1t * s1t - s11 * (stt - 1.0);
+    if (disc < 0.0) {
+        *lab_out = ledge;
+        return pedge;
+    }
+    double p = (s1t + sqrt(disc)) / s11;
+    double r1 = d1 - p, r2 = d2 - p;                       /* t - p 1 = X^T n */
+    double al1 = q11 * r1 + q12 * r2;
+    double al2 = q12 * r1 + q22 * r2;
+    if (al1 < 0.0 && al2 < 0.0) {
+        if (d1 < d2) *lab_out = l1;
+        else if (d2 < d1) *lab_out = l2;
+        else *lab_out = l1 < l2 ? l1 : l2;
+        return p;
+    }
+    *lab_out = ledge;
+    return pedge;
+}
+
+double ptpo_local_update(const double *x0, const double *x1, const double *x2,
+                         double d1, double d2, int *lab_out)
+{
+    int lab;
+    double p = local_update(x0, x1, x2, d1, d2, 1, 2, &lab);
+    if (lab_out) *lab_out = lab;
+    return p;
+}
+
+/* Best update of vertex v over its incident triangles, reading dist/lab.
+ * Lexicographic (value, label) minimum. */
+static void best_update(int v, const incidence *inc, const int *F, const double *X,
+                        const double *dist, const int *lab, double *best, int *blab,
+                        const unsigned char *usable)
+{
+    double bu = INFINITY;
+    int bl = -1;
+    for (int e = inc->start[v]; e < inc->start[v + 1]; ++e) {
+        const int *f = F + 3 * inc->face[e];
+        int a, b;
+        if (f[0] == v) { a = f[1]; b = f[2]; }
+        else if (f[1] == v) { a = f[2]; b = f[0]; }
+        else { a = f[0]; b = f[1]; }
+        double da = dist[a], db = dist[b];
+        if (usable) {
+            if (!usable[a]) da = INFINITY;
+            if (!usable[b]) db = INFINITY;
+        }
+        int l;
+        double u = local_update(X + 3 * (size_t)v, X + 3 * (size_t)a, X + 3 * (size_t)b,
+                                da, db, lab[a], lab[b], &l);
+        if (u < bu || (u == bu && isfinite(u) && l < bl)) {
+            bu = u;
+            bl = l;
+        }
+    }
+    *best = bu;
+    *blab = bl;
+}
+
+/* ------------------------------------------------------------------ */
+/* PTP iteration (Sec. 4.2)                                            */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double tol;       /* epsilon of Eq. lower_band, > 0                     */
+    int max_iters;    /* iteration cap K_max; 0 -> 4 rho + 16               */
+    int band_rule;    /* 0: relative change (Eq. lower_band)                */
+                      /* 1: fixed band i_k = floor((k + 1) / 2) (Sec. 6)   */
+    int window;       /* > 0: band holds at most `window` toplesets; the    */
+                      /* ones pushed out below it retire.  0: unbounded     */
+    int advance_all;  /* 1: retire every leading converged topleset         */
+} ptpo_options;
+
+typedef struct {
+    int iterations;       /* K                                             */
+    int rho;              /* number of toplesets                           */
+    int reachable;        /* vertices with finite distance                 */
+    long long updates;    /* U = sum_k |B_k| (vertex updates)              */
+} ptpo_stats;
+
+/*
+ * dist[n], label[n] (may be NULL): results in the caller's vertex order.
+ * retire_k[n] (may be NULL): iteration at which V_r retired (V_0: 0; not
+ *   retired: -1).
+ * trace_lo[max_iters + 1], trace_maxrel[max_iters + 1] (may be NULL): for
+ *   each k, the first topleset of the band and the largest relative change
+ *   over V_{i_{k-1}} (inf when some value was still infinite).
+ * Returns PTPO_OK, PTPO_ENOCONV (cap reached; results so far written) or an
+ * error.
+ */
+int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
+             const ptpo_options *opt, double *dist, int *label, ptpo_stats *st,
+             int *retire_k, int *trace_lo, double *trace_maxrel, int trace_len)
+{
+    int rc = check_mesh(n, nf, F, m, S);
+    if (rc) return rc;
+    if (!(opt->tol > 0.0) || opt->window < 0 || opt->max_iters < 0) return PTPO_EINVAL;
+    incidence inc;
+    rc = build_incidence(n, nf, F, &inc);
+    if (rc) return rc;
+    int *level = (int *)malloc(sizeof(int) * (size_t)n);
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    int *offsets = (int *)malloc(sizeof(int) * ((size_t)n + 2));
+    double *dold = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dnew = (double *)malloc(sizeof(double) * (size_t)n);
+    int *lold = (int *)malloc(sizeof(int) * (size_t)n);
+    int *lnew = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!level || !order || !offsets || !dold || !dnew || !lold || !lnew) {
+        rc = PTPO_ENOMEM;
+        goto out;
+    }
+    int rho;
+    rc = toplesets_with(&inc, F, m, S, level, order, offsets, &rho);
+    if (rc) goto out;
+
+    for (int v = 0; v < n; ++v) {
+        dold[v] = INFINITY;
+        lold[v] = -1;
+    }
+    for (int a = 0; a < m; ++a) {
+        dold[S[a]] = 0.0;
+        lold[S[a]] = a;
+    }
+    if (retire_k) {
+        for (int r = 0; r < n; ++r) retire_k[r] = -1;
+        retire_k[0] = 0;
+    }
+    int kmax = opt->max_iters > 0 ? opt->max_iters : 4 * rho + 16;
+    int i = 1, k = 0;
+    long long U = 0;
+    memcpy(dnew, dold, sizeof(double) * (size_t)n);
+    memcpy(lnew, lold, sizeof(int) * (size_t)n);
+    while (i < rho && k < kmax) {
+        k += 1;
+        int j = k < rho ? k : rho - 1;                   /* Eq. upper_band */
+        int lo;
+        if (opt->band_rule == 1) {
+            lo = (k + 1) / 2;                            /* fixed half band */
+            if (lo < 1) lo = 1;
+            if (lo > j) lo = j;
+        } else {
+            lo = i;
+            if (opt->window > 0 && j - opt->window + 1 > lo) {
+                lo = j - opt->window + 1;
+                /* toplesets pushed below the window are no longer updated */
+                if (retire_k)
+                    for (int r = i; r < lo; ++r) retire_k[r] = k - 1;
+            }
+        }
+        /* Jacobi update of the band: d_k on B from d_{k-1}; d_k = d_{k-1}
+         * everywhere else */
+        for (int r = lo; r <= j; ++r) {
+            for (int q = offsets[r]; q < offsets[r + 1]; ++q) {
+                int v = order[q];
+                double bu;
+                int bl;
+                best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+                if (bu < dold[v]) {
+                    dnew[v] = bu;
+                    lnew[v] = bl;
+                } else {
+                    dnew[v] = dold[v];
+                    lnew[v] = lold[v];
+                }
+            }
+            U += offsets[r + 1] - offsets[r];
+        }
+        if (trace_lo && k < trace_len) trace_lo[k] = lo;
+        int inew;
+        if (opt->band_rule == 1) {
+            /* V_r is final after iteration 2r - 1 */
+            inew = (k + 1) / 2 + 1;
+            if (inew < i) inew = i;
+            if (retire_k)
+                for (int r = i; r < inew && r < rho; ++r) retire_k[r] = k;
+        } else {
+            /* Eq. lower_band: V_lo retires when every value in it was finite
+             * and changed by a relative amount below tol */
+            inew = lo;
+            for (;;) {
+                if (inew >= rho || inew > j) break;
+                double worst = 0.0;
+                int ok = 1;
+                for (int q = offsets[inew]; q < offsets[inew + 1]; ++q) {
+                    int v = order[q];
+                    if (!isfinite(dold[v])) {
+                        ok = 0;
+                        worst = INFINITY;
+                        break;
+                    }
+                    if (dnew[v] == dold[v]) continue;
+                    double rel = fabs(dnew[v] - dold[v]) / dold[v];
+                    if (rel > worst) worst = rel;
+                    if (!(rel < opt->tol)) ok = 0;
+                }
+                if (inew == lo && trace_maxrel && k < trace_len) trace_maxrel[k] = worst;
+                if (!ok) break;
+                if (retire_k) retire_k[inew] = k;
+                inew += 1;
+                if (!opt->advance_all) break;
+            }
+        }
+        i = inew;
+        /* d_{k-1} <- d_k */
+        for (int r = lo; r <= j; ++r)
+            for (int q = offsets[r]; q < offsets[r + 1]; ++q) {
+                int v = order[q];
+                dold[v] = dnew[v];
+                lold[v] = lnew[v];
+            }
+    }
+    if (i < rho) rc = PTPO_ENOCONV;
+    int reach = 0;
+    for (int v = 0; v < n; ++v) {
+        dist[v] = dold[v];
+        if (label) label[v] = lold[v];
+        if (isfinite(dold[v])) reach++;
+    }
+    if (st) {
+        st->iterations = k;
+        st->rho = rho;
+        st->reachable = reach;
+        st->updates = U;
+    }
+out:
+    free(level); free(order); free(offsets);
+    free(dold); free(dnew); free(lold); free(lnew);
+    free_incidence(&inc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* fixed point d* = min(d*, U(d*)), d*(S) = 0, by Jacobi from +inf       */
+/* ------------------------------------------------------------------ */
+
+int ptpo_fixed_point(int n, int nf, const double *X, const int *F, int m, const int *S,
+                     int max_sweeps, double *dist, int *label, int *sweeps_out)
+{
+    int rc = check_mesh(n, nf, F, m, S);
+    if (rc) return rc;
+    incidence inc;
+    rc = build_incidence(n, nf, F, &inc);
+    if (rc) return rc;
+    double *dold = (double *)malloc(sizeof(double) * (size_t)n);
+    int *lold = (int *)malloc(sizeof(int) * (size_t)n);
+    unsigned char *is_src = (unsigned char *)calloc((size_t)n, 1);
+    int *lab = label ? label : (int *)malloc(sizeof(int) * (size_t)n);
+    if (!dold || !lold || !is_src || !lab) {
+        rc = PTPO_ENOMEM;
+        goto out;
+    }
+    for (int v = 0; v < n; ++v) {
+        dist[v] = INFINITY;
+        lab[v] = -1;
+    }
+    for (int a = 0; a < m; ++a) {
+        dist[S[a]] = 0.0;
+        lab[S[a]] = a;
+        is_src[S[a]] = 1;
+    }
+    int sweeps = 0;
+    rc = PTPO_ENOCONV;
+    while (sweeps < max_sweeps) {
+        sweeps++;
+        memcpy(dold, dist, sizeof(double) * (size_t)n);
+        memcpy(lold, lab, sizeof(int) * (size_t)n);
+        int changed = 0;
+        for (int v = 0; v < n; ++v) {
+            if (is_src[v]) continue;
+            double bu;
+            int bl;
+            best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+            if (bu < dold[v]) {
+                dist[v] = bu;
+                lab[v] = bl;
+                changed = 1;
+            }
+        }
+        if (!changed) {
+            rc = PTPO_OK;
+            break;
+        }
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+out:
+    free(dold); free(lold); free(is_src);
+    if (!label) free(lab);
+    free_incidence(&inc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fast Marching (Sec. 3.2): accept the smallest trial vertex, then     */
+/* update every triangle around each of its neighbours from accepted    */
+/* values only.                                                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double key; int v; } heap_item;
+
+static void heap_push(heap_item *h, int *size, double key, int v)
+{
+    int i = (*size)++;
+    h[i].key = key;
+    h[i].v = v;
+    while (i > 0) {
+        int p = (i - 1) / 2;
+        if (h[p].key <= h[i].key) break;
+        heap_item t = h[p]; h[p] = h[i]; h[i] = t;
+        i = p;
+    }
+}
+
+static heap_item heap_pop(heap_item *h, int *size)
+{
+    heap_item top = h[0];
+    h[0] = h[--(*size)];
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, s = i;
+        if (l < *size && h[l].key < h[s].key) s = l;
+        if (r < *size && h[r].key < h[s].key) s = r;
+        if (s == i) break;
+        heap_item t = h[s]; h[s] = h[i]; h[i] = t;
+        i = s;
+    }
+    return top;
+}
+
+int ptpo_fast_marching(int n, int nf, const double *X, const int *F, int m, const int *S,
+                       double *dist)
+{
+    int rc = check_mesh(n, nf, F, m, S);
+    if (rc) return rc;
+    incidence inc;
+    rc = build_incidence(n, nf, F, &inc);
+    if (rc) return rc;
+    size_t cap = (size_t)n + 6 * (size_t)nf + 16;
+    heap_item *h = (heap_item *)malloc(sizeof(heap_item) * cap);
+    unsigned char *acc = (unsigned char *)calloc((size_t)n, 1);
+    int *lab = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!h || !acc || !lab) {
+        rc = PTPO_ENOMEM;
+        goto out;
+    }
+    for (int v = 0; v < n; ++v) {
+        dist[v] = INFINITY;
+        lab[v] = 0;
+    }
+    int size = 0;
+    for (int a = 0; a < m; ++a) {
+        dist[S[a]] = 0.0;
+        heap_push(h, &size, 0.0, S[a]);
+    }
+    while (size > 0) {
+        heap_item it = heap_pop(h, &size);
+        int v = it.v;
+        if (acc[v] || it.key > dist[v]) continue;
+        acc[v] = 1;
+        for (int e = inc.start[v]; e < inc.start[v + 1]; ++e) {
+            const int *f = F + 3 * inc.face[e];
+            for (int c = 0; c < 3; ++c) {
+                int u = f[c];
+                if (acc[u]) continue;
+                double bu;
+                int bl;
+                best_update(u, &inc, F, X, dist, lab, &bu, &bl, acc);
+                if (bu < dist[u]) {
+                    dist[u] = bu;
+                    if ((size_t)size >= cap) { rc = PTPO_ENOMEM; goto out; }
+                    heap_push(h, &size, bu, u);
+                }
+            }
+        }
+    }
+out:
+    free(h); free(acc); free(lab);
+    free_incidence(&inc);
+    return rc;
+}
