@@ -1,0 +1,141 @@
+/*
+ * ptp.h: C ABI of the MI355X Parallel Toplesets Propagation library.
+ *
+ * The problem (paper Sec. 3.1): a triangle mesh T = (V, E, F) and a source set
+ * S of vertices; compute for every vertex v the geodesic distance d_S(v) to S.
+ * The method (Sec. 4): group the vertices into topological level sets V_r
+ * (BFS hop distance r from S, Sec. 4.1), then repeatedly recompute, for every
+ * vertex of the update band B_{i_k}^{j_k} (the toplesets i_k .. j_k), its
+ * distance from the previous iteration's map with the planar Fast-Marching
+ * update over its incident triangles (Sec. 3.2 update_step, Sec. 4.2); the
+ * band grows by one topleset per iteration (Eq. upper_band) and drops its
+ * first topleset once every value there changed by a relative amount below
+ * the tolerance (Eq. lower_band).
+ *
+ * Conventions for every entry point
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns them (typically torch tensors) and keeps them alive until
+ *     the work enqueued on `stream` has finished.  The library never frees
+ *     caller memory.  `stream` is a hipStream_t passed as void* (NULL = the
+ *     null stream).
+ *   - Inputs are read only.  Outputs are fully overwritten on PTP_OK and on
+ *     PTP_ENOCONV; on any other status their contents are undefined.
+ *   - Errors are reported by status code only; nothing throws or aborts
+ *     across this boundary.  ptp_last_error() gives a message per plan.
+ *   - A plan may be used by one host thread at a time.
+ *
+ * Layouts
+ *   V      float32 [n][3]   vertex coordinates, row-major (x, y, z).
+ *   F      int32   [f][3]   triangle vertex ids, 0 <= id < n.
+ *   S      int32   [m]      source vertex ids, distinct, 0 <= id < n, m >= 1.
+ *   dist   float32 [n]      distance to S; +inf where no path exists.
+ *   label  int32   [n]      index into S of the source whose front reached
+ *                           the vertex (Voronoi label); -1 where unreachable.
+ */
+#ifndef PTP_MI355X_H
+#define PTP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PTP_OK = 0,
+    PTP_EINVAL = -1,        /* bad argument, index out of range, non-finite
+                               coordinate, duplicate or missing source, tol <= 0 */
+    PTP_ENOMEM = -2,        /* workspace too small                            */
+    PTP_EDEVICE = -3,       /* a HIP call failed or a kernel reported a fault  */
+    PTP_ENOCONV = -4,       /* iteration cap reached before every topleset
+                               retired; the distances so far are written       */
+    PTP_EUNSUPPORTED = -5   /* sizes beyond what the library handles          */
+} ptp_status;
+
+typedef struct {
+    float tol;              /* epsilon of Eq. lower_band, > 0                   */
+    int32_t max_iters;      /* iteration cap; 0 -> 4 * rho + 16                 */
+    int32_t window;         /* > 0: the band holds at most `window` toplesets
+                               and the ones pushed below it stop updating;
+                               0: unbounded, the paper's rule                  */
+    int32_t want_labels;    /* nonzero: compute Voronoi labels                  */
+    int32_t workgroups;     /* persistent grid size; 0 -> chosen by the library */
+} ptp_options;
+
+typedef struct {
+    int32_t iterations;     /* K: iterations run                               */
+    int32_t n_toplesets;    /* rho: number of toplesets (reachable levels)     */
+    int32_t reachable;      /* vertices in some topleset                        */
+    int32_t workgroups;     /* persistent grid size used                        */
+    int64_t vertex_updates; /* U = sum over k of |B_{i_k}^{j_k}|  (Eq.
+                               n_operations without the constant)             */
+} ptp_stats;
+
+typedef struct ptp_plan ptp_plan;
+
+/* Create a plan for a mesh with n_vertices, n_faces and n_sources.  `opt` is
+ * copied; NULL means tol = 1e-3 (the paper's epsilon) and defaults elsewhere.
+ * Sizes: 1 <= n_vertices < 2^31 / 4, 0 <= n_faces, 3 * n_faces < 2^31,
+ * 1 <= n_sources <= n_vertices.  Returns PTP_EINVAL / PTP_EUNSUPPORTED on
+ * bad sizes or options; *out is NULL then. */
+ptp_status ptp_plan_create(ptp_plan **out, int32_t n_vertices, int32_t n_faces,
+                           int32_t n_sources, const ptp_options *opt);
+
+/* Device workspace the plan needs, in bytes.  The caller allocates it (any
+ * 256-byte aligned device buffer) and passes the same buffer to
+ * ptp_prepare and every later ptp_run of this plan. */
+ptp_status ptp_workspace_bytes(const ptp_plan *plan, size_t *bytes);
+
+/* Validate the mesh and build, on the device: the vertex-triangle incidence,
+ * the toplesets by BFS from S (Sec. 4.1) and the reorder of coordinates and
+ * incidence into topleset order (Sec. 4.3).  Synchronises `stream` once to
+ * read the validation result and the number of toplesets.  Returns
+ * PTP_EINVAL for out-of-range face or source ids, non-finite coordinates or
+ * duplicate sources; PTP_ENOMEM if work_bytes is too small. */
+ptp_status ptp_prepare(ptp_plan *plan, const float *dV, const int32_t *dF,
+                       const int32_t *dS, void *dWork, size_t work_bytes, void *stream);
+
+/* Run the PTP iteration on a prepared plan and write dist (and label when
+ * dLabel is non-NULL and the plan wants labels) in the caller's vertex
+ * order.  Enqueues work only: no host synchronisation, no allocation.  The
+ * outcome (PTP_OK / PTP_ENOCONV / device fault) is read by ptp_get_stats or
+ * ptp_run_status after the stream has drained. */
+ptp_status ptp_run(ptp_plan *plan, float *dDist, int32_t *dLabel, void *stream);
+
+/* ptp_prepare + ptp_run + synchronise; fills *stats when non-NULL.  Returns
+ * the run's outcome (PTP_OK, PTP_ENOCONV, ...). */
+ptp_status ptp_solve(ptp_plan *plan, const float *dV, const int32_t *dF, const int32_t *dS,
+                     void *dWork, size_t work_bytes, float *dDist, int32_t *dLabel,
+                     ptp_stats *stats, void *stream);
+
+/* Synchronise the plan's last stream and report the last run: fills *stats
+ * and returns its outcome. */
+ptp_status ptp_get_stats(ptp_plan *plan, ptp_stats *stats);
+
+/* Copy the topleset order of the last prepare into caller DEVICE buffers:
+ * perm[n] = caller vertex id at each position of the order (by topleset, then
+ * ascending id; unreachable vertices last), offsets[rho + 1] = start of each
+ * topleset in that order.  Either pointer may be NULL.  Asynchronous on
+ * `stream`. */
+ptp_status ptp_get_order(ptp_plan *plan, int32_t *dPerm, int32_t *dOffsets, void *stream);
+
+/* Copy the retirement iteration of each topleset of the last run into a
+ * HOST buffer retire[rho]: the last iteration that updated V_r (0 for V_0,
+ * -1 if it never retired).  Synchronises. */
+ptp_status ptp_get_schedule(ptp_plan *plan, int32_t *hRetire);
+
+/* Number of toplesets found by the last prepare (host value). */
+int32_t ptp_n_toplesets(const ptp_plan *plan);
+
+const char *ptp_last_error(const ptp_plan *plan);
+void ptp_plan_destroy(ptp_plan *plan);
+
+/* Library version string. */
+const char *ptp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTP_MI355X_H */

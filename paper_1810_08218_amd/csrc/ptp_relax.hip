@@ -1,0 +1,278 @@
+// The PTP iteration (Sec. 4.2) as one persistent, cooperative kernel:
+//   init (d = +inf, d(S) = 0, labels),
+//   for k = 1, 2, ...: Jacobi update of the band B_{i_k}^{j_k} from the
+//     previous map with the planar update (Sec. 3.2) in increment form,
+//     relative-change test of the band's first topleset (Eq. lower_band),
+//     band ends advanced on the device (Eq. upper_band / lower_band),
+//   unpermute of distances and labels to the caller's order.
+// One grid barrier per iteration; the controller state (i, j, k) is kept in
+// registers, identical in every workgroup, and the only cross-workgroup datum
+// per iteration is the "not converged" word of the tested topleset.
+#include "ptp_device.h"
+#include "ptp_kernels.h"
+
+namespace ptp {
+
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+
+__device__ inline float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+    return ax * bx + ay * by + az * bz;
+}
+
+// Planar update of x0 from (x1, d1), (x2, d2), at least one of d1, d2 finite.
+//
+// With e_i = x_i - x0, a = e1.e1, b = e1.e2, c = e2.e2, det = |e1 x e2|^2,
+// A = |x1 - x2|^2, delta = d2 - d1, the plane front through (x1, d1), (x2, d2)
+// with unit in-plane gradient gives x0 the value d1 + q where
+//     A q^2 - 2 delta (a - b) q + a delta^2 - det = 0,
+// whose larger root is q = (delta (a - b) + sqrt(det (A - delta^2))) / A.
+// Working with q = p - d1 keeps every term at the scale of the triangle, so
+// float32 does not lose the digits that the textbook form in p cancels.
+// The root is used when the front reaches x0 through the opposite edge
+// (Q X^T n < 0, both components):  q (c - b) + b delta > 0  and
+// q (a - b) > a delta; otherwise the edge updates d_i + |e_i| give the value.
+// Label: edge update -> its vertex; planar value -> its smaller input.
+template <bool LABELS>
+__device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, float d2, int l1,
+                                     int l2, int& lab) {
+    const float e1x = x1.x - x0.x, e1y = x1.y - x0.y, e1z = x1.z - x0.z;
+    const float e2x = x2.x - x0.x, e2y = x2.y - x0.y, e2z = x2.z - x0.z;
+    const float a = dot3(e1x, e1y, e1z, e1x, e1y, e1z);
+    const float c = dot3(e2x, e2y, e2z, e2x, e2y, e2z);
+    if (!(d2 < kInf)) {
+        if (LABELS) lab = l1;
+        return d1 + sqrtf(a);
+    }
+    if (!(d1 < kInf)) {
+        if (LABELS) lab = l2;
+        return d2 + sqrtf(c);
+    }
+    const float p1 = d1 + sqrtf(a), p2 = d2 + sqrtf(c);
+    float pe;
+    int le = 0;
+    if (p1 < p2) {
+        pe = p1;
+        if (LABELS) le = l1;
+    } else if (p2 < p1) {
+        pe = p2;
+        if (LABELS) le = l2;
+    } else {
+        pe = p1;
+        if (LABELS) le = min(l1, l2);
+    }
+    const float b = dot3(e1x, e1y, e1z, e2x, e2y, e2z);
+    const float cx = e1y * e2z - e1z * e2y;
+    const float cy = e1z * e2x - e1x * e2z;
+    const float cz = e1x * e2y - e1y * e2x;
+    const float det = dot3(cx, cy, cz, cx, cy, cz);
+    const float fx = x1.x - x2.x, fy = x1.y - x2.y, fz = x1.z - x2.z;
+    const float A = dot3(fx, fy, fz, fx, fy, fz);
+    const float delta = d2 - d1;
+    const float disc = det * (A - delta * delta);
+    if (det > 1e-12f * a * c && disc >= 0.f) {
+        const float q = (delta * (a - b) + sqrtf(disc)) / A;
+        if (q * (c - b) + b * delta > 0.f && q * (a - b) > a * delta) {
+            if (LABELS) lab = d1 < d2 ? l1 : (d2 < d1 ? l2 : min(l1, l2));
+            return d1 + q;
+        }
+    }
+    if (LABELS) lab = le;
+    return pe;
+}
+
+struct RelaxArgs {
+    int n, m, rho, kmax, window;
+    float tol;
+    const int* S;
+    const int* perm;
+    const int* iperm;
+    const int* offsets;
+    const int* row;
+    const int2* wedge;
+    const float4* xyz;
+    float* dist;
+    int* lab;
+    int* retire;
+    int* ctrl;
+    float* out_d;
+    int* out_l;
+};
+
+template <bool LABELS>
+__global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
+    GridBarrier gb{reinterpret_cast<unsigned*>(a.ctrl + C_BAR_RUN), a.ctrl + C_ABORT, gridDim.x, 0};
+    const long long gsz = (long long)gridDim.x * kBlock;
+    const long long g0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const int n = a.n;
+    float* dA = a.dist;
+    float* dB = a.dist + n;
+    int* lA = a.lab;
+    int* lB = a.lab + n;
+    const int m0 = a.offsets[1];  // |V_0|: the sources occupy positions [0, m0)
+
+    for (long long v = g0; v < n; v += gsz) {
+        const float d = v < m0 ? 0.f : kInf;
+        dA[v] = d;
+        dB[v] = d;
+        if (LABELS && v >= m0) {
+            lA[v] = -1;
+            lB[v] = -1;
+        }
+    }
+    if (LABELS)
+        for (long long s = g0; s < a.m; s += gsz) {
+            const int p = a.iperm[a.S[s]];
+            lA[p] = (int)s;
+            lB[p] = (int)s;
+        }
+    for (long long r = g0; r < a.rho; r += gsz) a.retire[r] = r == 0 ? 0 : -1;
+    if (!gb.sync()) return;
+
+    int i = 1, lo_prev = 1, k = 0, runstat = 0;
+    long long upd = 0;
+    while (i < a.rho) {
+        if (k >= a.kmax) {
+            runstat = 1;
+            break;
+        }
+        ++k;
+        const int j = min(k, a.rho - 1);                       // Eq. upper_band
+        int lo = i;
+        if (a.window > 0) lo = max(lo, j - a.window + 1);
+        const float* dold = (k & 1) ? dA : dB;
+        float* dnew = (k & 1) ? dB : dA;
+        const int* lold = (k & 1) ? lA : lB;
+        int* lnew = (k & 1) ? lB : lA;
+        const int cb = a.offsets[lo_prev];   // retired since last iteration: copy
+        const int bb = a.offsets[lo];        // band
+        const int be = a.offsets[j + 1];
+        const int tb = a.offsets[lo + 1];    // tested topleset V_lo = [bb, tb)
+        int* flag = a.ctrl + C_FLAGS + (k % 3) * 32;
+        if (leader)
+            __hip_atomic_store(a.ctrl + C_FLAGS + ((k + 1) % 3) * 32, 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        bool notconv = false;
+        for (long long v = cb + g0; v < be; v += gsz) {
+            if (v < bb) {
+                dnew[v] = dold[v];
+                if (LABELS) lnew[v] = lold[v];
+                continue;
+            }
+            const float4 x0 = a.xyz[v];
+            const float dv = dold[v];
+            float best = kInf;
+            int bl = 0x7fffffff;
+            const int e0 = a.row[v], e1 = a.row[v + 1];
+            for (int e = e0; e < e1; ++e) {
+                const int2 wv = a.wedge[e];
+                const float da = dold[wv.x], db = dold[wv.y];
+                if (!(fminf(da, db) < kInf)) continue;
+                int la = 0, lb = 0, l = 0;
+                if (LABELS) {
+                    la = lold[wv.x];
+                    lb = lold[wv.y];
+                }
+                const float u = local_update<LABELS>(x0, a.xyz[wv.x], a.xyz[wv.y], da, db, la, lb, l);
+                if (u < best || (LABELS && u == best && l < bl)) {
+                    best = u;
+                    bl = l;
+                }
+            }
+            float dn = dv;
+            if (best < dv) {
+                dn = best;
+                if (LABELS) lnew[v] = bl;
+            } else if (LABELS) {
+                lnew[v] = lold[v];
+            }
+            dnew[v] = dn;
+            if (v < tb) {
+                const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
+                notconv |= !conv;
+            }
+        }
+        if (__ballot(notconv) != 0ull && (threadIdx.x & (kWave - 1)) == 0)
+            __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        upd += be - bb;
+        if (!gb.sync()) return;
+        const int f = load_agent(flag);
+        if (leader)
+            for (int r = i; r < lo; ++r) a.retire[r] = k - 1;    // pushed out by the window
+        if (f == 0) {                                             // Eq. lower_band
+            if (leader) a.retire[lo] = k;
+            i = lo + 1;
+        } else {
+            i = lo;
+        }
+        lo_prev = lo;
+    }
+    const float* dfin = (k & 1) ? dB : dA;
+    const int* lfin = (k & 1) ? lB : lA;
+    for (long long p = g0; p < n; p += gsz) {
+        const int v = a.perm[p];
+        a.out_d[v] = dfin[p];
+        if (LABELS) a.out_l[v] = lfin[p];
+    }
+    if (leader) {
+        a.ctrl[C_ITERS] = k;
+        a.ctrl[C_RUNSTAT] = runstat;
+        a.ctrl[C_UPD_LO] = (int)(upd & 0xffffffffll);
+        a.ctrl[C_UPD_HI] = (int)(upd >> 32);
+    }
+}
+
+__global__ void k_run_reset(int* ctrl) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ctrl[C_ITERS] = 0;
+        ctrl[C_RUNSTAT] = 0;
+        ctrl[C_UPD_LO] = 0;
+        ctrl[C_UPD_HI] = 0;
+        ctrl[C_ABORT] = 0;
+        ctrl[C_BAR_RUN] = 0;
+    }
+    if (t < 3) ctrl[C_FLAGS + 32 * t] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st) {
+    hipLaunchKernelGGL(k_run_reset, dim3(1), dim3(64), 0, st, w.ctrl);
+    RelaxArgs a;
+    a.n = p.n;
+    a.m = p.m;
+    a.rho = p.rho;
+    a.kmax = p.kmax;
+    a.window = p.window;
+    a.tol = p.tol;
+    a.S = p.S;
+    a.perm = w.perm;
+    a.iperm = w.iperm;
+    a.offsets = w.offsets;
+    a.row = w.rowN;
+    a.wedge = w.wedge;
+    a.xyz = w.xyz;
+    a.dist = w.dist;
+    a.lab = w.lab;
+    a.retire = w.retire;
+    a.ctrl = w.ctrl;
+    a.out_d = p.out_d;
+    a.out_l = p.out_l;
+    void* args[] = {&a};
+    const void* fn = labels ? reinterpret_cast<const void*>(&k_relax<true>)
+                            : reinterpret_cast<const void*>(&k_relax<false>);
+    return hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
+}
+
+int max_coop_blocks_run(int cus, bool labels) {
+    int nb = 0;
+    hipError_t e = labels ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true>, kBlock, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false>, kBlock, 0);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb * cus;
+}
+
+}  // namespace ptp

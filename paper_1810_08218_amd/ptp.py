@@ -1,0 +1,241 @@
+"""Python binding of the PTP C ABI (``include/ptp.h``), via ctypes.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libptp.so``.  PyTorch supplies device memory and the stream.  If the
+library is missing or fails to load, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libptp.so")
+
+PTP_OK = 0
+PTP_EINVAL = -1
+PTP_ENOMEM = -2
+PTP_EDEVICE = -3
+PTP_ENOCONV = -4
+PTP_EUNSUPPORTED = -5
+_NAMES = {0: "PTP_OK", -1: "PTP_EINVAL", -2: "PTP_ENOMEM", -3: "PTP_EDEVICE",
+          -4: "PTP_ENOCONV", -5: "PTP_EUNSUPPORTED"}
+
+# every symbol include/ptp.h declares
+EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "ptp_solve",
+           "ptp_get_stats", "ptp_get_order", "ptp_get_schedule", "ptp_n_toplesets",
+           "ptp_last_error", "ptp_plan_destroy", "ptp_version")
+
+
+class PTPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("tol", C.c_float), ("max_iters", C.c_int32), ("window", C.c_int32),
+                ("want_labels", C.c_int32), ("workgroups", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_toplesets", C.c_int32),
+                ("reachable", C.c_int32), ("workgroups", C.c_int32),
+                ("vertex_updates", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libptp.so; raises when it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1810_08218_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.ptp_plan_create.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(Options)]
+    lib.ptp_plan_create.restype = C.c_int
+    lib.ptp_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.ptp_workspace_bytes.restype = C.c_int
+    lib.ptp_prepare.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.ptp_prepare.restype = C.c_int
+    lib.ptp_run.argtypes = [vp, vp, vp, vp]
+    lib.ptp_run.restype = C.c_int
+    lib.ptp_solve.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, vp, vp, C.POINTER(Stats), vp]
+    lib.ptp_solve.restype = C.c_int
+    lib.ptp_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.ptp_get_stats.restype = C.c_int
+    lib.ptp_get_order.argtypes = [vp, vp, vp, vp]
+    lib.ptp_get_order.restype = C.c_int
+    lib.ptp_get_schedule.argtypes = [vp, vp]
+    lib.ptp_get_schedule.restype = C.c_int
+    lib.ptp_n_toplesets.argtypes = [vp]
+    lib.ptp_n_toplesets.restype = C.c_int32
+    lib.ptp_last_error.argtypes = [vp]
+    lib.ptp_last_error.restype = C.c_char_p
+    lib.ptp_plan_destroy.argtypes = [vp]
+    lib.ptp_plan_destroy.restype = None
+    lib.ptp_version.argtypes = []
+    lib.ptp_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, dtype, shape_tail, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} must have shape [*, {shape_tail}]")
+
+
+class Plan:
+    """One mesh size + options.  Owns the host plan and (by default) a torch
+    workspace tensor; all device memory is torch's."""
+
+    def __init__(self, n: int, f: int, m: int, tol: float, max_iters: int = 0, window: int = 0,
+                 want_labels: bool = False, workgroups: int = 0):
+        lib = load()
+        self._lib = lib
+        self.n, self.f, self.m = int(n), int(f), int(m)
+        self.want_labels = bool(want_labels)
+        opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)),
+                      int(workgroups))
+        h = C.c_void_p()
+        rc = lib.ptp_plan_create(C.byref(h), self.n, self.f, self.m, C.byref(opt))
+        if rc != PTP_OK:
+            raise PTPError(rc, "ptp_plan_create")
+        self._h = h
+        self._work = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ptp_plan_destroy(h)
+            self._h = None
+
+    def _err(self, rc, what):
+        msg = self._lib.ptp_last_error(self._h)
+        return PTPError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t(0)
+        rc = self._lib.ptp_workspace_bytes(self._h, C.byref(b))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, device=None):
+        import torch
+        need = self.workspace_bytes()
+        if self._work is None or self._work.numel() < need + 256:
+            self._work = torch.empty(need + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-self._work.data_ptr()) % 256
+        return self._work[off:off + need]
+
+    def prepare(self, V, F, S, work=None, stream=None):
+        import torch
+        _check_dev(V, torch.float32, (3,), "V")
+        _check_dev(F, torch.int32, (3,), "F")
+        _check_dev(S, torch.int32, None, "S")
+        if V.shape[0] != self.n or F.shape[0] != self.f or S.numel() != self.m:
+            raise ValueError("mesh sizes differ from the plan")
+        if work is None:
+            work = self.workspace(V.device)
+        rc = self._lib.ptp_prepare(self._h, _ptr(V), _ptr(F), _ptr(S), _ptr(work),
+                                   work.numel(), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_prepare")
+        self._keep = (V, F, S, work)
+
+    def run(self, dist, label=None, stream=None):
+        import torch
+        _check_dev(dist, torch.float32, None, "dist")
+        if dist.numel() != self.n:
+            raise ValueError("dist must have n elements")
+        if label is not None:
+            _check_dev(label, torch.int32, None, "label")
+            if label.numel() != self.n:
+                raise ValueError("label must have n elements")
+        rc = self._lib.ptp_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_run")
+
+    def stats(self, allow_noconv: bool = True) -> dict:
+        st = Stats()
+        rc = self._lib.ptp_get_stats(self._h, C.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if rc != PTP_OK and not (allow_noconv and rc == PTP_ENOCONV):
+            raise self._err(rc, "ptp_get_stats")
+        return d
+
+    def n_toplesets(self) -> int:
+        return int(self._lib.ptp_n_toplesets(self._h))
+
+    def order(self, stream=None):
+        """(perm[n], offsets[rho + 1]) as int32 device tensors."""
+        import torch
+        rho = self.n_toplesets()
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        offs = torch.empty(rho + 1, dtype=torch.int32, device="cuda")
+        rc = self._lib.ptp_get_order(self._h, _ptr(perm), _ptr(offs), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_get_order")
+        return perm, offs
+
+    def schedule(self) -> np.ndarray:
+        """Last iteration that updated each topleset (host int32 [rho])."""
+        rho = self.n_toplesets()
+        out = np.empty(rho, np.int32)
+        rc = self._lib.ptp_get_schedule(self._h, C.c_void_p(out.ctypes.data))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_get_schedule")
+        return out
+
+
+@dataclass
+class Solution:
+    dist: object       # torch float32 [n] (device)
+    label: object      # torch int32 [n] (device) or None
+    stats: dict
+    plan: Plan
+
+
+def solve(V, F, S, tol: float, labels: bool = False, max_iters: int = 0, window: int = 0,
+          workgroups: int = 0, stream=None) -> Solution:
+    """Geodesic distances from the source set S on mesh (V, F): prepare + run
+    + stats.  V float32 [n, 3], F int32 [f, 3], S int32 [m], all on the GPU."""
+    import torch
+    plan = Plan(V.shape[0], F.shape[0], S.numel(), tol, max_iters=max_iters, window=window,
+                want_labels=labels, workgroups=workgroups)
+    plan.prepare(V, F, S, stream=stream)
+    dist = torch.empty(V.shape[0], dtype=torch.float32, device=V.device)
+    lab = torch.empty(V.shape[0], dtype=torch.int32, device=V.device) if labels else None
+    plan.run(dist, lab, stream=stream)
+    st = plan.stats()
+    return Solution(dist, lab, st, plan)

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Bars:
+  * toplesets, canonical order and offsets: bit-exact;
+  * the band schedule (the iteration at which each topleset retired), K, rho
+    and the update count U: identical;
+  * distances: max relative error <= 1e-4 over non-source reachable vertices
+    (float32 arithmetic against the float64 oracle at the same iteration
+    rule); sources exactly 0, unreachable vertices +inf on both sides;
+  * labels: equal, except where the vertex lies on a Voronoi ridge (its
+    neighbourhood carries both labels) and the two fronts arrive within the
+    distance tolerance; the rate of such cases is reported and bounded.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1810_08218_amd as P
+from gpu_util import gpu_run, rel_errors, say
+from meshtools import edges, golden
+from paper_1810_08218_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+def _mesh_from_golden(name):
+    g = golden(name)
+    return I.Mesh(np.array(g["V"], np.float32), np.array(g["F"], np.int32),
+                  np.array(g["S"], np.int32), name=name), g
+
+
+def _label_mismatch_ok(mesh, g_lab, o_lab, o_dist):
+    """Mismatched labels must sit where two source regions meet: some
+    neighbour of the vertex carries the GPU's label in the oracle result."""
+    bad = np.nonzero(g_lab != o_lab)[0]
+    if bad.size == 0:
+        return 0
+    e = edges(mesh.F)
+    nb = {}
+    badset = set(bad.tolist())
+    for a, b in e:
+        if a in badset:
+            nb.setdefault(a, set()).add(b)
+        if b in badset:
+            nb.setdefault(b, set()).add(a)
+    for v in bad:
+        labs = {int(o_lab[u]) for u in nb.get(v, ())}
+        assert int(g_lab[v]) in labs, f"vertex {v}: label {g_lab[v]} not adjacent in the oracle map"
+    return bad.size
+
+
+def check_parity(cuda, mesh, tol, labels=False, workgroups=0, max_iters=0, window=0):
+    o = O.run(mesh.V, mesh.F, mesh.S, tol, max_iters=max_iters, window=window)
+    g = gpu_run(mesh, tol, labels=labels, workgroups=workgroups, max_iters=max_iters,
+                window=window)
+    level, order, offsets, rho = O.toplesets(mesh.V, mesh.F, mesh.S)
+    assert g.rho == rho
+    assert np.array_equal(g.perm, order)
+    assert np.array_equal(g.offsets, offsets)
+    S = mesh.S
+    assert (g.dist[S] == 0).all()
+    assert np.array_equal(np.isinf(g.dist), np.isinf(o.dist))
+    mx, mean = rel_errors(g.dist, o.dist, S)
+    same = np.array_equal(g.retire, o.retire_k)
+    say(f"  K gpu/oracle {g.iterations}/{o.iterations} rho {rho} U {g.updates}/{o.updates} "
+        f"same schedule {same} max rel {mx:.3e} mean rel {mean:.3e}")
+    if not same:
+        d = np.nonzero(g.retire != o.retire_k)[0]
+        r0 = int(d[0])
+        k0 = int(min(g.retire[r0], o.retire_k[r0]))
+        say(f"  first divergence topleset {r0}: gpu {g.retire[r0]} oracle {o.retire_k[r0]}; "
+            f"oracle max relative change there {o.trace_maxrel[k0]:.6e} vs tol {tol}")
+    assert same, "band schedule differs from the oracle's"
+    assert (g.iterations, g.updates) == (o.iterations, o.updates)
+    assert g.status == o.status
+    assert mx <= REL_TOL
+    if labels:
+        n_bad = _label_mismatch_ok(mesh, g.label, o.label, o.dist)
+        reach = np.isfinite(o.dist).sum()
+        say(f"  label mismatches {n_bad} of {reach}")
+        assert n_bad <= max(2, 1e-3 * reach)
+        assert (g.label[np.isinf(o.dist)] == -1).all()
+    return g, o
+
+
+@pytest.mark.parametrize("name", ["square_antidiagonal.json", "square_two_sources.json",
+                                  "triangle_two_sources.json"])
+def test_golden_examples(cuda, name):
+    mesh, gd = _mesh_from_golden(name)
+    labels = "expected_label" in gd
+    g = gpu_run(mesh, gd["tol"], labels=labels)
+    assert np.allclose(g.dist, gd["expected_dist"], rtol=2e-7, atol=0)
+    assert (g.rho, g.iterations, g.updates) == (gd["expected_rho"], gd["expected_K"], gd["expected_U"])
+    if "expected_retire" in gd:
+        assert g.retire.tolist() == gd["expected_retire"]
+    if labels:
+        assert g.label.tolist() == gd["expected_label"]
+
+
+def _order_cases():
+    out = [I.flat_grid(64), I.flat_grid(37, source=(20, 11)), I.sphere(4, seed=8, n_sources=9),
+           I.bumpy_icosphere(level=5, seed=4, n_sources=32), I.batch_mesh(300), I.batch_mesh(7)]
+    g = I.flat_grid(9)
+    V2 = np.concatenate([g.V, g.V + np.float32(3.0), np.zeros((1, 3), np.float32)])
+    F2 = np.concatenate([g.F, g.F + 81]).astype(np.int32)
+    out.append(I.Mesh(V2, F2, np.array([40, 5], np.int32), name="two_components_isolated"))
+    return out
+
+
+@pytest.mark.parametrize("mesh", _order_cases(), ids=lambda m: m.name)
+def test_toplesets_and_order_bit_exact(cuda, mesh):
+    g = gpu_run(mesh, 1e-3)
+    level, order, offsets, rho = O.toplesets(mesh.V, mesh.F, mesh.S)
+    assert g.rho == rho
+    assert np.array_equal(g.perm, order)
+    assert np.array_equal(g.offsets, offsets)
+
+
+def test_parity_flat_grid_64(cuda):
+    check_parity(cuda, I.flat_grid(64), 1e-6)
+
+
+def test_parity_noisy_icosphere_7(cuda):
+    check_parity(cuda, I.noisy_icosphere(level=7, seed=2), 1e-4)
+
+
+def test_parity_multisource_labels(cuda):
+    check_parity(cuda, I.bumpy_icosphere(level=6, seed=3, n_sources=32), 1e-4, labels=True)
+
+
+@pytest.mark.parametrize("t", [1, 260, 301])
+def test_parity_batch_meshes(cuda, t):
+    mesh = I.batch_mesh(t)
+    if mesh.n > 300000:
+        pytest.skip("mesh too large for the in-test oracle")
+    check_parity(cuda, mesh, 1e-4, labels=True)
+
+
+def test_parity_window_and_cap(cuda):
+    m = I.noisy_icosphere(level=5, seed=7)
+    check_parity(cuda, m, 1e-4, window=6)
+    g, o = check_parity(cuda, m, 1e-4, max_iters=20)
+    assert g.status == P.PTP_ENOCONV and g.iterations == 20
+
+
+@pytest.mark.parametrize("wg", [1, 3, 64, 1024])
+def test_result_independent_of_grid_size(cuda, wg):
+    m = I.noisy_icosphere(level=6, seed=5)
+    ref = gpu_run(m, 1e-4, labels=True, workgroups=0)
+    g = gpu_run(m, 1e-4, labels=True, workgroups=wg)
+    assert np.array_equal(g.dist, ref.dist) and np.array_equal(g.label, ref.label)
+    assert np.array_equal(g.retire, ref.retire)
+
+
+def test_repeat_runs_identical(cuda):
+    import torch
+    m = I.sphere(5, seed=1, n_sources=4)
+    g = gpu_run(m, 1e-4, labels=True)
+    d2 = torch.empty(m.n, dtype=torch.float32, device="cuda")
+    l2 = torch.empty(m.n, dtype=torch.int32, device="cuda")
+    g.plan.run(d2, l2)
+    g.plan.stats()
+    assert np.array_equal(d2.cpu().numpy(), g.dist) and np.array_equal(l2.cpu().numpy(), g.label)
+
+
+def test_edge_cases(cuda):
+    # one triangle, one source
+    tri = I.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32),
+                 np.array([[0, 1, 2]], np.int32), np.array([2], np.int32), name="one_triangle")
+    check_parity(cuda, tri, 1e-4, labels=True)
+    # every vertex a source: rho = 1, no iteration
+    g = gpu_run(I.Mesh(tri.V, tri.F, np.array([2, 0, 1], np.int32), name="all_sources"), 1e-4,
+                labels=True)
+    assert g.rho == 1 and g.iterations == 0 and (g.dist == 0).all()
+    assert g.label.tolist() == [1, 2, 0]
+    # unreachable component and an isolated vertex; sizes not multiples of 32
+    gm = I.flat_grid(9)
+    V2 = np.concatenate([gm.V, gm.V + np.float32(3.0), np.zeros((1, 3), np.float32)])
+    F2 = np.concatenate([gm.F, gm.F + 81]).astype(np.int32)
+    check_parity(cuda, I.Mesh(V2, F2, np.array([40, 5], np.int32), name="components"), 1e-5,
+                 labels=True)
+    # a mesh without faces: only the sources are reachable
+    nof = I.Mesh(np.zeros((5, 3), np.float32), np.zeros((0, 3), np.int32),
+                 np.array([3], np.int32), name="no_faces")
+    g = gpu_run(nof, 1e-4)
+    assert g.dist[3] == 0 and np.isinf(np.delete(g.dist, 3)).all()
+
+
+def test_invalid_inputs_are_rejected(cuda):
+    import torch
+    m = I.flat_grid(8)
+    V, F, S = (torch.from_numpy(x).cuda() for x in (m.V, m.F, m.S))
+    plan = P.Plan(m.n, m.f, 1, 1e-4)
+    badF = F.clone()
+    badF[3, 1] = m.n
+    with pytest.raises(P.PTPError) as e:
+        plan.prepare(V, badF, S)
+    assert e.value.status == P.PTP_EINVAL
+    badV = V.clone()
+    badV[5, 2] = float("nan")
+    with pytest.raises(P.PTPError) as e:
+        plan.prepare(badV, F, S)
+    assert e.value.status == P.PTP_EINVAL
+    with pytest.raises(P.PTPError) as e:
+        plan.prepare(V, F, torch.tensor([m.n], dtype=torch.int32, device="cuda"))
+    assert e.value.status == P.PTP_EINVAL
+    plan2 = P.Plan(m.n, m.f, 2, 1e-4)
+    with pytest.raises(P.PTPError) as e:
+        plan2.prepare(V, F, torch.tensor([4, 4], dtype=torch.int32, device="cuda"))
+    assert e.value.status == P.PTP_EINVAL
+    with pytest.raises(P.PTPError):
+        plan2.run(torch.empty(m.n, device="cuda"))
+    # the plan stays usable after an error
+    plan.prepare(V, F, S)
+    d = torch.empty(m.n, device="cuda")
+    plan.run(d)
+    assert plan.stats()["status"] == P.PTP_OK
+
+
+SAMPLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "bumpy_icosphere9_oracle_samples.npz")
+
+
+def test_parity_bumpy_icosphere_9_sampled(cuda):
+    """Full-size 32-source mesh in the benchmark's launch configuration,
+    against stored oracle values at 20,000 sampled vertices (written by
+    tests/golden/make_oracle_samples.py, which calls only the oracle)."""
+    ref = np.load(SAMPLES)
+    m = I.bumpy_icosphere(level=9, seed=3, n_sources=32)
+    g = gpu_run(m, float(ref["tol"]), labels=True, want_order=False)
+    same = np.array_equal(g.retire, ref["retire_k"])
+    idx = ref["idx"]
+    mx, mean = rel_errors(g.dist[idx], ref["dist"], np.nonzero(np.isin(idx, m.S))[0])
+    say(f"  K {g.iterations}/{int(ref['iterations'])} rho {g.rho}/{int(ref['rho'])} "
+        f"U {g.updates}/{int(ref['updates'])} same schedule {same} max rel {mx:.3e} mean {mean:.3e}")
+    assert g.rho == int(ref["rho"])
+    assert same and g.iterations == int(ref["iterations"]) and g.updates == int(ref["updates"])
+    assert mx <= REL_TOL
+    assert (g.dist[m.S] == 0).all() and np.isfinite(g.dist).all()
+    lab_bad = (g.label[idx] != ref["label"]).mean()
+    say(f"  sampled label mismatch rate {lab_bad:.2e}")
+    assert lab_bad <= 1e-3
