@@ -16,7 +16,8 @@ struct ptp_plan {
     int n = 0, f = 0, m = 0;
     ptp_options opt{};
     int device = 0, cus = 0;
-    int g_bfs = 0, g_run = 0, gmax = 0;
+    int g_bfs = 0, g_run = 0, gmax = 0, max_run = 0;
+    int g_used = 0;
     Layout layout{};
     Work work{};
     void* ws = nullptr;
@@ -51,7 +52,7 @@ size_t work_layout(int n, int f, int gmax, Layout* L) {
     const size_t N = (size_t)n, Fc = 3 * (size_t)f;
     const size_t nwords = (N + 31) / 32;
     const size_t scan_blocks = (N + 1 + 4095) / 4096 + 1;
-    const size_t sizes[17] = {
+    const size_t sizes[kLayoutParts] = {
         sizeof(int) * C_WORDS,      // ctrl
         sizeof(int) * N,            // level
         sizeof(int) * N,            // perm
@@ -69,9 +70,10 @@ size_t work_layout(int n, int f, int gmax, Layout* L) {
         sizeof(int) * 4 * (size_t)gmax,
         sizeof(int) * N,            // retire
         sizeof(int) * scan_blocks,  // scan_tmp
+        sizeof(unsigned) * kLine * ((size_t)gmax + 1),   // barrier lines
     };
     size_t off = 0;
-    for (int i = 0; i < 17; ++i) {
+    for (int i = 0; i < kLayoutParts; ++i) {
         L->off[i] = off;
         off += align_up(sizes[i]);
     }
@@ -99,6 +101,7 @@ Work carve(void* base, int, int, int, const Layout& L) {
     w.cnt = reinterpret_cast<int*>(b + L.off[14]);
     w.retire = reinterpret_cast<int*>(b + L.off[15]);
     w.scan_tmp = reinterpret_cast<int*>(b + L.off[16]);
+    w.bar = reinterpret_cast<unsigned*>(b + L.off[17]);
     return w;
 }
 
@@ -144,9 +147,11 @@ ptp_status ptp_plan_create(ptp_plan** out, int32_t n, int32_t f, int32_t m, cons
     const int max_bfs = max_coop_blocks_bfs(p->cus);
     const int max_run = max_coop_blocks_run(p->cus, labels);
     p->g_bfs = p->cus < max_bfs ? p->cus : max_bfs;
-    int want = o.workgroups > 0 ? o.workgroups : p->cus;
-    p->g_run = want < max_run ? want : max_run;
-    p->gmax = p->g_bfs;
+    p->max_run = max_run;
+    // an explicit grid is fixed here; the automatic one is chosen per prepared
+    // mesh in ptp_run, so the barrier lines cover the largest possible grid
+    p->g_run = o.workgroups > 0 ? (o.workgroups < max_run ? o.workgroups : max_run) : 0;
+    p->gmax = p->g_bfs > max_run ? p->g_bfs : max_run;
     work_layout(n, f, p->gmax, &p->layout);
     *out = p;
     return PTP_OK;
@@ -214,7 +219,19 @@ ptp_status ptp_run(ptp_plan* p, float* dDist, int32_t* dLabel, void* stream) {
     rp.S = p->S;
     rp.out_d = dDist;
     rp.out_l = labels ? dLabel : nullptr;
-    hipError_t e = launch_run(p->work, rp, labels, p->g_run, p->stream);
+    // Automatic grid: about one workgroup (256 threads) per 1024 reachable
+    // vertices, within [16, 512] and the co-residency limit.  Measured on the
+    // icosphere workloads: the per-iteration cost is flat from ~n/2048 to
+    // ~n/512 workgroups and rises outside.
+    int g = p->g_run;
+    if (g <= 0) {
+        g = p->reach / 1024;
+        if (g < 16) g = 16;
+        if (g > 512) g = 512;
+        if (g > p->max_run) g = p->max_run;
+    }
+    p->g_used = g;
+    hipError_t e = launch_run(p->work, rp, labels, g, p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "run launch");
     p->ran = true;
     return PTP_OK;
@@ -231,7 +248,7 @@ ptp_status ptp_get_stats(ptp_plan* p, ptp_stats* st) {
         st->iterations = p->h_ctrl[C_ITERS];
         st->n_toplesets = p->rho;
         st->reachable = p->reach;
-        st->workgroups = p->g_run;
+        st->workgroups = p->g_used;
         st->vertex_updates = ((int64_t)(uint32_t)p->h_ctrl[C_UPD_HI] << 32) |
                              (int64_t)(uint32_t)p->h_ctrl[C_UPD_LO];
     }

@@ -1,6 +1,6 @@
 // Device-side building blocks shared by the PTP kernels: control-block
-// layout, the grid-wide barrier of the persistent kernels, block scans and
-// the workspace carve.  Internal to the HIP library.
+// layout, coherent memory access, the grid barrier of the persistent
+// kernels and block scans.  Internal to the HIP library.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,9 +10,9 @@ namespace ptp {
 
 constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
 constexpr int kWave = 64;
+constexpr int kLine = 32;                   // ints per 128-byte line
 
 // ---- control block (int32 words in device memory) ----------------------
-// Hot words sit on their own 128-byte lines.
 enum CtrlWord : int {
     C_STATUS = 0,        // validation / fault bits (ST_*)
     C_RHO = 1,           // number of toplesets
@@ -22,10 +22,7 @@ enum CtrlWord : int {
     C_UPD_LO = 5,        // vertex updates, low / high 32 bits
     C_UPD_HI = 6,
     C_ABORT = 7,         // a barrier timed out
-    C_BAR_PREP = 32,     // barrier counter of the BFS kernel
-    C_BAR_RUN = 64,      // barrier counter of the relaxation kernel
-    C_FLAGS = 96,        // 3 rotating "not converged" words, one line each
-    C_WORDS = 256
+    C_WORDS = 64
 };
 
 enum StatusBits : int {
@@ -33,46 +30,97 @@ enum StatusBits : int {
     ST_BAD_COORD = 2,
     ST_BAD_SOURCE = 4,
     ST_DUP_SOURCE = 8,
-    ST_BARRIER_TIMEOUT = 16,
 };
 
-// ---- grid barrier ------------------------------------------------------
-// Every workgroup of a cooperative launch increments one counter; the
-// barrier of epoch e completes when it reaches e * nblocks.  Agent-scope
-// release before and acquire after make every store before the barrier
-// visible to every load after it, across XCDs.  A wall-clock limit turns a
-// barrier that can never complete into an abort flag instead of a hang.
-struct GridBarrier {
-    unsigned* counter;
-    int* abort_flag;
-    unsigned nblocks;
-    unsigned epoch;
-
-    __device__ bool sync() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            epoch += 1;
-            const unsigned target = epoch * nblocks;
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > 400000000ll) {   // seconds at the 100 MHz clock
-                    __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    }
-};
-
-__device__ inline int load_agent(const int* p) {
+// ---- coherent access ---------------------------------------------------
+// Each XCD has its own L2; plain stores may sit there unseen by the other
+// XCDs.  Data that one workgroup writes and another reads inside the same
+// persistent kernel (distances, labels, levels, frontier bitmaps, counters)
+// is therefore only touched with agent-scope accesses, which are coherent
+// across XCDs without L2 write-back or invalidation.  Read-only data (mesh,
+// incidence, offsets) keeps ordinary cached loads.
+template <typename T>
+__device__ inline T ld_c(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename T>
+__device__ inline void st_c(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wave's outstanding memory operations have completed.  Also
+// a compiler barrier: no access moves across it.
+__device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// ---- grid barrier ------------------------------------------------------
+// Flag-array barrier for cooperative launches.  Every workgroup publishes
+// (epoch << 1 | bit) in its own 128-byte line; workgroup 0 polls all lines
+// with its 256 threads, ORs the bits and publishes (epoch << 1 | any) in a
+// release line that everybody polls.  No counter is contended, so the cost
+// barely grows with the grid.  The bit carries the "not converged" vote of
+// the PTP iteration.  A wall-clock limit turns a barrier that can never
+// complete into an abort flag instead of a hang.
+//
+// Ordering: each wave waits for its own coherent stores to complete before
+// the workgroup arrives; loads after the barrier are coherent loads issued
+// after the release line was observed.
+struct FlagBarrier {
+    unsigned* flags;     // [G * kLine], zero at launch
+    unsigned* release;   // one line, zero at launch
+    int* abort_flag;
+    unsigned epoch;
+
+    static constexpr long long kTimeoutTicks = 400000000ll;   // seconds at 100 MHz
+
+    __device__ bool spin_ge(const unsigned* p, unsigned want, unsigned* seen) {
+        const long long t0 = wall_clock64();
+        unsigned v;
+        while (((v = ld_c(p)) >> 1) < want) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > kTimeoutTicks) {
+                __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *seen = 0;
+                return false;
+            }
+        }
+        *seen = v;
+        return true;
+    }
+
+    // Returns false when the barrier timed out (the kernel must exit);
+    // *any receives the OR of `bit` over all workgroups.
+    __device__ bool sync(unsigned bit, unsigned* any) {
+        __shared__ unsigned s_any;
+        __shared__ int s_ok;
+        const unsigned G = gridDim.x, w = blockIdx.x, tid = threadIdx.x;
+        wait_memory();
+        bit = __syncthreads_or(bit) ? 1u : 0u;
+        epoch += 1;
+        if (tid == 0) st_c(flags + (size_t)w * kLine, (epoch << 1) | bit);
+        if (w == 0) {
+            unsigned acc = 0;
+            int ok = 1;
+            for (unsigned x = tid; x < G; x += kBlock) {
+                unsigned v;
+                if (!spin_ge(flags + (size_t)x * kLine, epoch, &v)) {
+                    ok = 0;
+                    break;
+                }
+                acc |= v & 1u;
+            }
+            acc = __syncthreads_or(acc) ? 1u : 0u;
+            ok = __syncthreads_and(ok);
+            if (tid == 0 && ok) st_c(release, (epoch << 1) | acc);
+        }
+        if (tid == 0) {
+            unsigned v = 0;
+            s_ok = spin_ge(release, epoch, &v) ? 1 : 0;
+            s_any = v & 1u;
+        }
+        __syncthreads();
+        *any = s_any;
+        return s_ok && ld_c(abort_flag) == 0;
+    }
+};
 
 // ---- block-wide scans (kBlock threads) ----------------------------------
 // Exclusive prefix of `v` over the workgroup; *total receives the sum.

@@ -26,10 +26,13 @@ struct Work {
     int* cnt;           // [4*gmax] per-workgroup chunk counts
     int* retire;        // [n]    last iteration that updated each topleset
     int* scan_tmp;      // block sums of the scans
+    unsigned* bar;      // [(gmax + 1) * 32] barrier lines (last one: release)
 };
 
+constexpr int kLayoutParts = 18;
+
 struct Layout {
-    size_t off[17];
+    size_t off[kLayoutParts];
     size_t total;
 };
 
@@ -39,6 +42,9 @@ Work carve(void* base, int n, int f, int gmax, const Layout& L);
 // prepare pipeline; every kernel after validation is gated on the status word
 hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, const int* F,
                           const int* S, int g_bfs, hipStream_t st);
+
+// zero the barrier lines of a grid of g workgroups (before each persistent launch)
+void launch_barrier_reset(const Work& w, int g, hipStream_t st);
 
 struct RunParams {
     int n, m, rho, kmax, window;

@@ -17,7 +17,7 @@ constexpr int kScanItems = 16;                      // per thread
 constexpr int kScanTile = kBlock * kScanItems;      // per workgroup
 constexpr int kListCap = 4096;                      // BFS LDS batch
 
-__device__ inline bool gated(const int* ctrl) { return load_agent(ctrl + C_STATUS) != 0; }
+__device__ inline bool gated(const int* ctrl) { return ld_c(ctrl + C_STATUS) != 0; }
 
 __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long len, int val) {
     for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < len;
@@ -149,6 +149,7 @@ struct BfsArgs {
     unsigned* bits;
     int* cnt;
     int* ctrl;
+    unsigned* bar;
 };
 
 __device__ inline int other1(int c) { return c == 2 ? 0 : c + 1; }
@@ -164,29 +165,35 @@ __device__ inline int other2(int c) { return c == 0 ? 2 : c - 1; }
 //      CAS decides the discoverer), its bit in the next bitmap and a count in
 //      the next chunk counts.
 // One grid barrier per level.  A level with no vertex ends the loop: rho = r.
+// level, bits and cnt are shared between workgroups: coherent access only.
 __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
-    GridBarrier gb{reinterpret_cast<unsigned*>(a.ctrl + C_BAR_PREP), a.ctrl + C_ABORT, gridDim.x, 0};
     if (gated(a.ctrl)) return;
     const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x;
+    FlagBarrier gb{a.bar, a.bar + (size_t)G * kLine, a.ctrl + C_ABORT, 0};
+    unsigned any = 0;
     const long long gsz = (long long)G * kBlock;
     const long long g0 = (long long)w * kBlock + tid;
     unsigned* bits0 = a.bits;
     unsigned* bits1 = a.bits + a.nwords;
-    for (long long v = g0; v < a.n; v += gsz) a.level[v] = -1;
-    for (long long x = g0; x < 2ll * a.nwords; x += gsz) a.bits[x] = 0u;
-    for (long long x = g0; x < 4ll * G; x += gsz) a.cnt[x] = 0;
-    if (!gb.sync()) return;
+    for (long long v = g0; v < a.n; v += gsz) st_c(a.level + v, -1);
+    for (long long x = g0; x < 2ll * a.nwords; x += gsz) st_c(a.bits + x, 0u);
+    for (long long x = g0; x < 4ll * G; x += gsz) st_c(a.cnt + x, 0);
+    if (!gb.sync(0, &any)) return;
+    unsigned dup = 0;
     for (long long s = g0; s < a.m; s += gsz) {
         int v = a.S[s];
         if (atomicCAS(a.level + v, -1, 0) != -1) {
-            atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
+            dup = 1;
         } else {
             atomicOr(bits0 + (v >> 5), 1u << (v & 31));
             atomicAdd(a.cnt + (v >> 5) / a.cw, 1);
         }
     }
-    if (!gb.sync()) return;
-    if (gated(a.ctrl)) return;
+    if (!gb.sync(dup, &any)) return;
+    if (any) {
+        if (w == 0 && tid == 0) atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
+        return;
+    }
 
     __shared__ int list[kListCap];
     const int wbeg = min(w * a.cw, a.nwords);
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
         const int* cr = a.cnt + (r % 3) * G;
         int part = 0, partpre = 0;
         for (int x = tid; x < G; x += kBlock) {
-            int c = cr[x];
+            int c = ld_c(cr + x);
             part += c;
             if (x < w) partpre += c;
         }
@@ -208,19 +215,19 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
         const int chunk_pre = block_sum(partpre);
         if (total == 0) break;
         if (w == 0 && tid == 0) a.offsets[r] = base;
-        if (tid == 0) a.cnt[((r + 2) % 3) * G + w] = 0;
+        if (tid == 0) st_c(a.cnt + ((r + 2) % 3) * G + w, 0);
         unsigned* cur = (r & 1) ? bits1 : bits0;
         unsigned* nxt = (r & 1) ? bits0 : bits1;
         int* cn = a.cnt + ((r + 1) % 3) * G;
 
         int pc = 0;
-        for (int x = my0; x < my1; ++x) pc += __popc(cur[x]);
+        for (int x = my0; x < my1; ++x) pc += __popc(ld_c(cur + x));
         int tot_w;
         const int pre = block_exclusive_scan(pc, &tot_w);
         for (int done = 0; done < tot_w; done += kListCap) {
             int rank = pre;
             for (int x = my0; x < my1 && rank < done + kListCap; ++x) {
-                unsigned word = cur[x];
+                unsigned word = ld_c(cur + x);
                 while (word) {
                     int b = __ffs(word) - 1;
                     word &= word - 1;
@@ -245,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                     const int nb[2] = {a.F[3 * tri + other1(c)], a.F[3 * tri + other2(c)]};
                     for (int z = 0; z < 2; ++z) {
                         const int x = nb[z];
-                        if (a.level[x] < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
+                        if (ld_c(a.level + x) < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
                             atomicOr(nxt + (x >> 5), 1u << (x & 31));
                             atomicAdd(cn + (x >> 5) / a.cw, 1);
                         }
@@ -254,9 +261,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
             }
             __syncthreads();
         }
-        for (int x = my0; x < my1; ++x) cur[x] = 0u;
+        for (int x = my0; x < my1; ++x) st_c(cur + x, 0u);
         base += total;
-        if (!gb.sync()) return;
+        if (!gb.sync(0, &any)) return;
     }
     const int rho = r;
     const int reach = base;
@@ -268,17 +275,17 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     const int qv = (ve - vb + kBlock - 1) / kBlock;
     const int v0 = min(vb + tid * qv, ve), v1 = min(v0 + qv, ve);
     int pc = 0;
-    for (int v = v0; v < v1; ++v) pc += a.level[v] < 0;
+    for (int v = v0; v < v1; ++v) pc += ld_c(a.level + v) < 0;
     int tot_w;
     int pre = block_exclusive_scan(pc, &tot_w);
-    if (tid == 0) a.cnt[3 * G + w] = tot_w;
-    if (!gb.sync()) return;
+    if (tid == 0) st_c(a.cnt + 3 * G + w, tot_w);
+    if (!gb.sync(0, &any)) return;
     int partpre = 0;
-    for (int x = tid; x < w; x += kBlock) partpre += a.cnt[3 * G + x];
+    for (int x = tid; x < w; x += kBlock) partpre += ld_c(a.cnt + 3 * G + x);
     const int chunk_pre = block_sum(partpre);
     int pos = reach + chunk_pre + pre;
     for (int v = v0; v < v1; ++v)
-        if (a.level[v] < 0) {
+        if (ld_c(a.level + v) < 0) {
             a.perm[pos] = v;
             a.iperm[v] = pos;
             ++pos;
@@ -287,6 +294,12 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
         a.ctrl[C_RHO] = rho;
         a.ctrl[C_REACH] = reach;
     }
+}
+
+__global__ void k_zero_lines(unsigned* p, long long len) {
+    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < len;
+         x += (long long)gridDim.x * blockDim.x)
+        p[x] = 0u;
 }
 
 // degree of each position, into rowN[p + 1]
@@ -361,6 +374,8 @@ hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, co
     a.bits = w.bits;
     a.cnt = w.cnt;
     a.ctrl = w.ctrl;
+    a.bar = w.bar;
+    launch_barrier_reset(w, g_bfs, st);
     void* args[] = {&a};
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_bfs), dim3(g_bfs), dim3(kBlock),
                                    args, 0, st);
@@ -372,6 +387,12 @@ hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, co
     hipLaunchKernelGGL(k_reorder, dim3(grid_for(n)), dim3(kBlock), 0, st, V, F, w.perm, w.iperm,
                        w.rowO, w.faceO, w.rowN, n, w.xyz, w.wedge, w.ctrl);
     return hipGetLastError();
+}
+
+void launch_barrier_reset(const Work& w, int g, hipStream_t st) {
+    const long long len = (long long)(g + 1) * kLine;
+    hipLaunchKernelGGL(k_zero_lines, dim3((unsigned)((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       w.bar, len);
 }
 
 int max_coop_blocks_bfs(int cus) {

@@ -96,14 +96,25 @@ struct RelaxArgs {
     int* lab;
     int* retire;
     int* ctrl;
+    unsigned* bar;
     float* out_d;
     int* out_l;
 };
 
+constexpr int kChunk = 6;   // wedges gathered together per vertex (mean degree 6)
+
+// One persistent workgroup grid runs the whole iteration.  Per iteration k
+// every thread takes band vertices in a grid-stride loop; for each vertex it
+// first gathers up to kChunk wedges, then every neighbour distance and
+// coordinate of those wedges at once (independent loads), then evaluates the
+// planar updates.  Distances and labels are exchanged between workgroups
+// through coherent loads and stores only.
 template <bool LABELS>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
-    GridBarrier gb{reinterpret_cast<unsigned*>(a.ctrl + C_BAR_RUN), a.ctrl + C_ABORT, gridDim.x, 0};
-    const long long gsz = (long long)gridDim.x * kBlock;
+    const int G = gridDim.x;
+    FlagBarrier gb{a.bar, a.bar + (size_t)G * kLine, a.ctrl + C_ABORT, 0};
+    unsigned any = 0;
+    const long long gsz = (long long)G * kBlock;
     const long long g0 = (long long)blockIdx.x * kBlock + threadIdx.x;
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
     const int n = a.n;
@@ -115,21 +126,21 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
     for (long long v = g0; v < n; v += gsz) {
         const float d = v < m0 ? 0.f : kInf;
-        dA[v] = d;
-        dB[v] = d;
+        st_c(dA + v, d);
+        st_c(dB + v, d);
         if (LABELS && v >= m0) {
-            lA[v] = -1;
-            lB[v] = -1;
+            st_c(lA + v, -1);
+            st_c(lB + v, -1);
         }
     }
     if (LABELS)
         for (long long s = g0; s < a.m; s += gsz) {
             const int p = a.iperm[a.S[s]];
-            lA[p] = (int)s;
-            lB[p] = (int)s;
+            st_c(lA + p, (int)s);
+            st_c(lB + p, (int)s);
         }
     for (long long r = g0; r < a.rho; r += gsz) a.retire[r] = r == 0 ? 0 : -1;
-    if (!gb.sync()) return;
+    if (!gb.sync(0, &any)) return;
 
     int i = 1, lo_prev = 1, k = 0, runstat = 0;
     long long upd = 0;
@@ -150,58 +161,69 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const int bb = a.offsets[lo];        // band
         const int be = a.offsets[j + 1];
         const int tb = a.offsets[lo + 1];    // tested topleset V_lo = [bb, tb)
-        int* flag = a.ctrl + C_FLAGS + (k % 3) * 32;
-        if (leader)
-            __hip_atomic_store(a.ctrl + C_FLAGS + ((k + 1) % 3) * 32, 0, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        bool notconv = false;
-        for (long long v = cb + g0; v < be; v += gsz) {
+        unsigned notconv = 0;
+        for (long long vv = cb + g0; vv < be; vv += gsz) {
+            const int v = (int)vv;
             if (v < bb) {
-                dnew[v] = dold[v];
-                if (LABELS) lnew[v] = lold[v];
+                st_c(dnew + v, ld_c(dold + v));
+                if (LABELS) st_c(lnew + v, ld_c(lold + v));
                 continue;
             }
             const float4 x0 = a.xyz[v];
-            const float dv = dold[v];
+            const float dv = ld_c(dold + v);
             float best = kInf;
             int bl = 0x7fffffff;
             const int e0 = a.row[v], e1 = a.row[v + 1];
-            for (int e = e0; e < e1; ++e) {
-                const int2 wv = a.wedge[e];
-                const float da = dold[wv.x], db = dold[wv.y];
-                if (!(fminf(da, db) < kInf)) continue;
-                int la = 0, lb = 0, l = 0;
-                if (LABELS) {
-                    la = lold[wv.x];
-                    lb = lold[wv.y];
+            for (int base = e0; base < e1; base += kChunk) {
+                const int cnt = min(kChunk, e1 - base);
+                int2 wv[kChunk];
+                float da[kChunk], db[kChunk];
+                float4 xa[kChunk], xb[kChunk];
+                int la[kChunk], lb[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    da[q] = ld_c(dold + wv[q].x);
+                    db[q] = ld_c(dold + wv[q].y);
+                    xa[q] = a.xyz[wv[q].x];
+                    xb[q] = a.xyz[wv[q].y];
+                    if (LABELS) {
+                        la[q] = ld_c(lold + wv[q].x);
+                        lb[q] = ld_c(lold + wv[q].y);
+                    }
                 }
-                const float u = local_update<LABELS>(x0, a.xyz[wv.x], a.xyz[wv.y], da, db, la, lb, l);
-                if (u < best || (LABELS && u == best && l < bl)) {
-                    best = u;
-                    bl = l;
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    if (q < cnt && fminf(da[q], db[q]) < kInf) {
+                        int l = 0;
+                        const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q],
+                                                             LABELS ? la[q] : 0, LABELS ? lb[q] : 0, l);
+                        if (u < best || (LABELS && u == best && l < bl)) {
+                            best = u;
+                            bl = l;
+                        }
+                    }
                 }
             }
             float dn = dv;
             if (best < dv) {
                 dn = best;
-                if (LABELS) lnew[v] = bl;
+                if (LABELS) st_c(lnew + v, bl);
             } else if (LABELS) {
-                lnew[v] = lold[v];
+                st_c(lnew + v, ld_c(lold + v));
             }
-            dnew[v] = dn;
+            st_c(dnew + v, dn);
             if (v < tb) {
                 const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
-                notconv |= !conv;
+                notconv |= conv ? 0u : 1u;
             }
         }
-        if (__ballot(notconv) != 0ull && (threadIdx.x & (kWave - 1)) == 0)
-            __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         upd += be - bb;
-        if (!gb.sync()) return;
-        const int f = load_agent(flag);
+        if (!gb.sync(notconv, &any)) return;
         if (leader)
             for (int r = i; r < lo; ++r) a.retire[r] = k - 1;    // pushed out by the window
-        if (f == 0) {                                             // Eq. lower_band
+        if (!any) {                                              // Eq. lower_band
             if (leader) a.retire[lo] = k;
             i = lo + 1;
         } else {
@@ -213,8 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const int* lfin = (k & 1) ? lB : lA;
     for (long long p = g0; p < n; p += gsz) {
         const int v = a.perm[p];
-        a.out_d[v] = dfin[p];
-        if (LABELS) a.out_l[v] = lfin[p];
+        a.out_d[v] = ld_c(dfin + p);
+        if (LABELS) a.out_l[v] = ld_c(lfin + p);
     }
     if (leader) {
         a.ctrl[C_ITERS] = k;
@@ -225,22 +247,20 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 }
 
 __global__ void k_run_reset(int* ctrl) {
-    const int t = threadIdx.x;
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         ctrl[C_ITERS] = 0;
         ctrl[C_RUNSTAT] = 0;
         ctrl[C_UPD_LO] = 0;
         ctrl[C_UPD_HI] = 0;
         ctrl[C_ABORT] = 0;
-        ctrl[C_BAR_RUN] = 0;
     }
-    if (t < 3) ctrl[C_FLAGS + 32 * t] = 0;
 }
 
 }  // namespace
 
 hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st) {
     hipLaunchKernelGGL(k_run_reset, dim3(1), dim3(64), 0, st, w.ctrl);
+    launch_barrier_reset(w, g_run, st);
     RelaxArgs a;
     a.n = p.n;
     a.m = p.m;
@@ -259,6 +279,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run,
     a.lab = w.lab;
     a.retire = w.retire;
     a.ctrl = w.ctrl;
+    a.bar = w.bar;
     a.out_d = p.out_d;
     a.out_l = p.out_l;
     void* args[] = {&a};
