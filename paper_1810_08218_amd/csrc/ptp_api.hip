@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/ptp.h"
+#include "ptp.h"
 #include "ptp_device.h"
 #include "ptp_kernels.h"
 

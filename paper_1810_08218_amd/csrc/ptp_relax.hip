@@ -21,6 +21,12 @@ __device__ inline float dot3(float ax, float ay, float az, float bx, float by, f
     return ax * bx + ay * by + az * bz;
 }
 
+// Hardware square root and reciprocal (v_sqrt_f32 / v_rcp_f32, about 1 ulp):
+// the update needs relative accuracy near 1e-7, not correct rounding, and
+// the IEEE sequences are several times longer on the critical path.
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Planar update of x0 from (x1, d1), (x2, d2), at least one of d1, d2 finite.
 //
 // With e_i = x_i - x0, a = e1.e1, b = e1.e2, c = e2.e2, det = |e1 x e2|^2,
@@ -43,13 +49,13 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
     const float c = dot3(e2x, e2y, e2z, e2x, e2y, e2z);
     if (!(d2 < kInf)) {
         if (LABELS) lab = l1;
-        return d1 + sqrtf(a);
+        return d1 + fsqrt(a);
     }
     if (!(d1 < kInf)) {
         if (LABELS) lab = l2;
-        return d2 + sqrtf(c);
+        return d2 + fsqrt(c);
     }
-    const float p1 = d1 + sqrtf(a), p2 = d2 + sqrtf(c);
+    const float p1 = d1 + fsqrt(a), p2 = d2 + fsqrt(c);
     float pe;
     int le = 0;
     if (p1 < p2) {
@@ -72,7 +78,7 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
     const float delta = d2 - d1;
     const float disc = det * (A - delta * delta);
     if (det > 1e-12f * a * c && disc >= 0.f) {
-        const float q = (delta * (a - b) + sqrtf(disc)) / A;
+        const float q = (delta * (a - b) + fsqrt(disc)) * frcp(A);
         if (q * (c - b) + b * delta > 0.f && q * (a - b) > a * delta) {
             if (LABELS) lab = d1 < d2 ? l1 : (d2 < d1 ? l2 : min(l1, l2));
             return d1 + q;
@@ -162,7 +168,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const int be = a.offsets[j + 1];
         const int tb = a.offsets[lo + 1];    // tested topleset V_lo = [bb, tb)
         unsigned notconv = 0;
-        for (long long vv = cb + g0; vv < be; vv += gsz) {
+        // Anchored mapping: position v is always handled by thread v mod gsz,
+        // whatever the band, so a vertex stays on one CU across iterations and
+        // its incidence and coordinates stay in that CU's caches.
+        const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
+        for (long long vv = first; vv < be; vv += gsz) {
             const int v = (int)vv;
             if (v < bb) {
                 st_c(dnew + v, ld_c(dold + v));
