@@ -131,6 +131,78 @@ int32_t ptp_n_toplesets(const ptp_plan *plan);
 const char *ptp_last_error(const ptp_plan *plan);
 void ptp_plan_destroy(ptp_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Batches: many meshes (or one mesh with many source sets) solved in one
+ * persistent launch.  The meshes are concatenated in the caller's arrays;
+ * each descriptor gives where its rows start.  Ids inside a mesh (face
+ * entries, sources) are local to that mesh.  Several descriptors may share
+ * the same vertex and face rows with different sources and output offsets
+ * (many source sets on one mesh).  Every mesh is solved exactly as
+ * ptp_solve would solve it alone with the same options: the batch changes
+ * the schedule, never the result.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t v_off;          /* first row of this mesh in V                      */
+    int64_t f_off;          /* first row in F                                  */
+    int64_t s_off;          /* first entry in S                                */
+    int64_t out_off;        /* first entry of its distances / labels in the outputs */
+    int32_t n_vertices, n_faces, n_sources, reserved;
+} ptp_mesh;
+
+/* Work distribution of a batch over the persistent grid (tuning only; the
+ * results do not depend on it).  Meshes are split by vertex count into small
+ * (< small_limit, one workgroup each), medium and large (>= large_limit);
+ * medium and large meshes run on groups of medium_group / large_group
+ * workgroups.  Zero fields take the library's defaults. */
+typedef struct {
+    int32_t workgroups;     /* persistent grid size                            */
+    int32_t small_limit;
+    int32_t large_limit;
+    int32_t medium_group;
+    int32_t large_group;
+} ptp_schedule;
+
+typedef struct ptp_batch ptp_batch;
+
+/* Create a batch plan.  `meshes` (host, [count]) is copied.  Sizes as for
+ * ptp_plan_create, per mesh; totals must stay below 2^29 vertices and 2^31 / 3
+ * faces.  Returns PTP_EINVAL on bad descriptors or options. */
+ptp_status ptp_batch_create(ptp_batch **out, const ptp_mesh *meshes, int32_t count,
+                            const ptp_options *opt);
+ptp_status ptp_batch_workspace_bytes(const ptp_batch *batch, size_t *bytes);
+
+/* Validate every mesh and build toplesets and reorders for all of them
+ * (Sec. 4.1, 4.3) in one persistent BFS launch.  dV / dF / dS are the
+ * concatenated arrays (rows addressed by the descriptors).  Synchronises
+ * once.  PTP_EINVAL if any mesh is invalid (ptp_batch_get_stats then reports
+ * which). */
+ptp_status ptp_batch_prepare(ptp_batch *batch, const float *dV, const int32_t *dF,
+                             const int32_t *dS, void *dWork, size_t work_bytes, void *stream);
+
+/* Run PTP on every mesh in one persistent launch; dDist / dLabel are indexed
+ * by out_off + local vertex id.  Enqueues work only (capture-safe: kernel
+ * launches only). */
+ptp_status ptp_batch_run(ptp_batch *batch, float *dDist, int32_t *dLabel, void *stream);
+
+/* Synchronise and report: per-mesh stats and status (host arrays [count],
+ * either may be NULL).  Returns PTP_OK, or the first non-OK mesh status. */
+ptp_status ptp_batch_get_stats(ptp_batch *batch, ptp_stats *hStats, int32_t *hStatus);
+
+/* Replace / read the work distribution used by the next prepare and run. */
+ptp_status ptp_batch_set_schedule(ptp_batch *batch, const ptp_schedule *schedule);
+ptp_status ptp_batch_get_schedule(const ptp_batch *batch, ptp_schedule *schedule);
+
+/* Try each candidate schedule (host array [n]) on the prepared batch: one
+ * run each after a warm-up, timed with device events on `stream`; keep the
+ * fastest and write its index and time per candidate (host, [n] ms).  The
+ * outputs are overwritten by the runs.  Synchronises. */
+ptp_status ptp_batch_autotune(ptp_batch *batch, const ptp_schedule *candidates, int32_t n,
+                              float *dDist, int32_t *dLabel, float *hMs, int32_t *best,
+                              void *stream);
+
+const char *ptp_batch_last_error(const ptp_batch *batch);
+void ptp_batch_destroy(ptp_batch *batch);
+
 /* Library version string. */
 const char *ptp_version(void);
 

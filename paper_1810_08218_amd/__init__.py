@@ -6,7 +6,8 @@ The computation lives in the HIP library ``libptp.so`` behind the C ABI of
 seeded synthetic meshes.
 """
 from .ptp import (PTP_EDEVICE, PTP_EINVAL, PTP_ENOCONV, PTP_ENOMEM, PTP_EUNSUPPORTED, PTP_OK,
-                  Plan, PTPError, Solution, load, solve)
+                  Batch, MeshDesc, Plan, PTPError, Schedule, Solution, concat, load, solve)
 
-__all__ = ["Plan", "PTPError", "Solution", "load", "solve", "PTP_OK", "PTP_EINVAL",
-           "PTP_ENOMEM", "PTP_EDEVICE", "PTP_ENOCONV", "PTP_EUNSUPPORTED"]
+__all__ = ["Plan", "Batch", "MeshDesc", "Schedule", "concat", "PTPError", "Solution", "load",
+           "solve", "PTP_OK", "PTP_EINVAL", "PTP_ENOMEM", "PTP_EDEVICE", "PTP_ENOCONV",
+           "PTP_EUNSUPPORTED"]

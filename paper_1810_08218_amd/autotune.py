@@ -1,0 +1,70 @@
+"""Autotuner for the batched launch: searches the work distribution
+(persistent grid size, mesh-size classes, workgroups per group) with the
+library's ptp_batch_autotune, which times each candidate on the prepared
+batch, and caches the winner per batch shape in a JSON file.
+
+The schedule never changes results, only time.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+CACHE = os.environ.get("PTP_SCHEDULE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "ptp_mi355x",
+                                    "schedules.json"))
+
+
+def candidates() -> list:
+    out = []
+    for G in (512, 1024):
+        for sl, ll in ((8192, 131072), (32768, 262144), (65536, 524288)):
+            for mg, lg in ((4, 16), (8, 32), (16, 64)):
+                out.append(dict(workgroups=G, small_limit=sl, large_limit=ll, medium_group=mg,
+                                large_group=lg))
+    return out
+
+
+def signature(descs, labels: bool) -> str:
+    """Shape key: mesh sizes rounded to powers of two, source counts, labels."""
+    n = np.array([int(d.n_vertices) for d in descs])
+    m = np.array([int(d.n_sources) for d in descs])
+    key = np.stack([np.round(np.log2(np.maximum(n, 1))).astype(int), m], axis=1)
+    h = hashlib.sha256(key.tobytes() + bytes([int(labels)])).hexdigest()[:20]
+    return f"{len(descs)}:{h}"
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(batch, descs, dist, label=None, use_cache: bool = True) -> dict:
+    """Pick the fastest schedule for this prepared batch (from the cache when
+    the shape was tuned before) and install it.  Returns
+    {"schedule": ..., "ms": best run ms or None, "cached": bool}."""
+    sig = signature(descs, label is not None)
+    cache = _load() if use_cache else {}
+    if sig in cache:
+        batch.set_schedule(**cache[sig]["schedule"])
+        return {"schedule": cache[sig]["schedule"], "ms": cache[sig].get("ms"), "cached": True}
+    cands = candidates()
+    best, ms = batch.autotune(cands, dist, label)
+    rec = {"schedule": cands[best], "ms": ms[best]}
+    if use_cache:
+        cache[sig] = rec
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            tmp = CACHE + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1)
+            os.replace(tmp, CACHE)
+        except OSError:
+            pass
+    return {"schedule": cands[best], "ms": ms[best], "cached": False, "all_ms": ms}

@@ -1,10 +1,18 @@
-// Host side of the C ABI declared in include/ptp.h: plans, workspace carve,
-// launches and status reporting.  No allocation happens here: every device
-// buffer comes from the caller.
+// Host side of the C ABI declared in include/ptp.h: plans (one mesh) and
+// batches (many meshes) share one implementation, the batch; a plan is a
+// batch of one.  The host validates sizes, carves the caller's workspace,
+// builds the work distribution of the persistent launches (groups of
+// workgroups, longest-processing-time assignment of meshes to groups),
+// launches, and reports per-mesh status.  No device allocation happens here.
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <queue>
 #include <string>
+#include <vector>
 
 #include "ptp.h"
 #include "ptp_device.h"
@@ -12,65 +20,165 @@
 
 using namespace ptp;
 
-struct ptp_plan {
-    int n = 0, f = 0, m = 0;
-    ptp_options opt{};
-    int device = 0, cus = 0;
-    int g_bfs = 0, g_run = 0, gmax = 0, max_run = 0;
-    int g_used = 0;
-    Layout layout{};
-    Work work{};
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    const int32_t* S = nullptr;
-    int rho = 0, reach = 0;
-    bool prepared = false;
-    bool ran = false;
-    int h_ctrl[C_WORDS];
-    std::string err;
-};
-
 namespace {
 
-ptp_status fail(ptp_plan* p, ptp_status s, const std::string& msg) {
-    if (p) p->err = msg;
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Work distribution of one persistent launch.
+struct Sched {
+    int G = 0;
+    int ngroups = 0;
+    std::vector<WgInfo> wg;      // [G]
+    std::vector<int> glist;      // starts [ngroups + 1] (absolute), then mesh ids
+    std::vector<int> gsize_of;   // [B] group size that handles each mesh
+};
+
+// Seconds for one mesh on a group of s workgroups: rho dependent iterations of
+// a few microseconds each, plus the band work spread over the group (about
+// 4 n vertex updates at ~8 ns per update per workgroup).  Only the relative
+// size matters: it drives the assignment, the results never depend on it.
+double est_time(long long n, long long rho, int s) {
+    return (double)rho * 5e-6 + 4.0 * (double)n * 8e-9 / (double)s;
+}
+
+Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long long>& rho,
+                    const ptp_schedule& p, int gmax, bool single, int single_g) {
+    Sched s;
+    const int B = (int)mesh.size();
+    s.gsize_of.assign(B, 1);
+    std::vector<std::vector<int>> groups;
+    std::vector<int> gsz;
+    if (single) {
+        groups.push_back({0});
+        gsz.push_back(std::max(1, std::min(single_g, gmax)));
+        s.gsize_of[0] = gsz[0];
+    } else {
+        const int G = std::max(1, std::min(p.workgroups, gmax));
+        int size_c[3] = {1, std::max(1, p.medium_group), std::max(1, p.large_group)};
+        std::vector<int> members[3];
+        for (int b = 0; b < B; ++b) {
+            const int n = mesh[b].n;
+            members[n < p.small_limit ? 0 : (n < p.large_limit ? 1 : 2)].push_back(b);
+        }
+        for (int c = 0; c < 3; ++c) size_c[c] = std::min(size_c[c], G);
+        // every non-empty class gets one group, largest meshes first; a class
+        // that no longer fits joins the single-workgroup class
+        int ng[3] = {0, 0, 0};
+        int used = 0;
+        for (int c = 2; c >= 1; --c) {
+            if (members[c].empty()) continue;
+            if (used + size_c[c] + (members[0].empty() ? 0 : 1) > G) {
+                members[0].insert(members[0].end(), members[c].begin(), members[c].end());
+                members[c].clear();
+                continue;
+            }
+            ng[c] = 1;
+            used += size_c[c];
+        }
+        if (!members[0].empty()) {
+            ng[0] = 1;
+            used += 1;
+        }
+        double C[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c)
+            for (int b : members[c]) C[c] += est_time(mesh[b].n, rho[b], size_c[c]);
+        // hand out the remaining workgroups to the class with the largest load per group
+        for (;;) {
+            int best = -1;
+            double bl = 0;
+            for (int c = 0; c < 3; ++c) {
+                if (members[c].empty() || ng[c] >= (int)members[c].size()) continue;
+                if (used + size_c[c] > G) continue;
+                const double load = C[c] / ng[c];
+                if (load > bl) {
+                    bl = load;
+                    best = c;
+                }
+            }
+            if (best < 0) break;
+            ng[best] += 1;
+            used += size_c[best];
+        }
+        // longest processing time first inside each class
+        for (int c = 2; c >= 0; --c) {
+            if (members[c].empty()) continue;
+            std::vector<int> ord = members[c];
+            const int sc = size_c[c];
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+                return est_time(mesh[x].n, rho[x], sc) > est_time(mesh[y].n, rho[y], sc);
+            });
+            const int first = (int)groups.size();
+            for (int g = 0; g < ng[c]; ++g) {
+                groups.emplace_back();
+                gsz.push_back(sc);
+            }
+            using Item = std::pair<double, int>;
+            std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+            for (int g = 0; g < ng[c]; ++g) heap.push({0.0, first + g});
+            for (int b : ord) {
+                Item it = heap.top();
+                heap.pop();
+                groups[it.second].push_back(b);
+                it.first += est_time(mesh[b].n, rho[b], sc);
+                heap.push(it);
+                s.gsize_of[b] = sc;
+            }
+        }
+    }
+    s.ngroups = (int)groups.size();
+    s.glist.assign(s.ngroups + 1, 0);
+    int pos = s.ngroups + 1;
+    for (int g = 0; g < s.ngroups; ++g) {
+        s.glist[g] = pos;
+        pos += (int)groups[g].size();
+    }
+    s.glist[s.ngroups] = pos;
+    for (int g = 0; g < s.ngroups; ++g)
+        for (int b : groups[g]) s.glist.push_back(b);
+    int first = 0;
+    for (int g = 0; g < s.ngroups; ++g) {
+        for (int r = 0; r < gsz[g]; ++r) s.wg.push_back(WgInfo{g, r, gsz[g], first});
+        first += gsz[g];
+    }
+    s.G = first;
     return s;
 }
-
-ptp_status hip_fail(ptp_plan* p, hipError_t e, const char* what) {
-    return fail(p, PTP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
 namespace ptp {
 
-size_t work_layout(int n, int f, int gmax, Layout* L) {
-    const size_t N = (size_t)n, Fc = 3 * (size_t)f;
-    const size_t nwords = (N + 31) / 32;
+size_t work_layout(const Sizes& z, Layout* L) {
+    const size_t N = (size_t)z.N, F3 = 3 * (size_t)z.F, B = (size_t)z.B, G = (size_t)z.gmax;
     const size_t scan_blocks = (N + 1 + 4095) / 4096 + 1;
     const size_t sizes[kLayoutParts] = {
-        sizeof(int) * C_WORDS,      // ctrl
-        sizeof(int) * N,            // level
-        sizeof(int) * N,            // perm
-        sizeof(int) * N,            // iperm
-        sizeof(int) * (N + 2),      // offsets
-        sizeof(int) * (N + 1),      // rowO
-        sizeof(int) * (Fc + 1),     // faceO
-        sizeof(int) * N,            // cursor
-        sizeof(int) * (N + 1),      // rowN
-        sizeof(int2) * (Fc + 1),    // wedge
-        sizeof(float4) * N,         // xyz
-        sizeof(float) * 2 * N,      // dist
-        sizeof(int) * 2 * N,        // lab
-        sizeof(unsigned) * 2 * nwords,
-        sizeof(int) * 4 * (size_t)gmax,
-        sizeof(int) * N,            // retire
-        sizeof(int) * scan_blocks,  // scan_tmp
-        sizeof(unsigned) * kLine * ((size_t)gmax + 1),   // barrier lines
+        sizeof(int) * C_WORDS,                 // ctrl
+        sizeof(MeshDesc) * B,                  // mesh
+        sizeof(MeshState) * B,                 // state
+        sizeof(WgInfo) * G,                    // wg_prep
+        sizeof(int) * (G + 1 + B),             // glist_prep
+        sizeof(WgInfo) * G,                    // wg_run
+        sizeof(int) * (G + 1 + B),             // glist_run
+        sizeof(int) * (B + 1),                 // vo
+        sizeof(int) * (B + 1),                 // fo3
+        sizeof(int) * (B + 1),                 // so
+        sizeof(int) * N,                       // level
+        sizeof(int) * N,                       // perm
+        sizeof(int) * N,                       // iperm
+        sizeof(int) * (N + B + 1),             // offsets
+        sizeof(int) * (N + 1),                 // rowO
+        sizeof(int2) * (F3 + 1),               // wedgeO
+        sizeof(int) * N,                       // cursor
+        sizeof(int) * (N + 1),                 // rowN
+        sizeof(int2) * (F3 + 1),               // wedge
+        sizeof(float4) * N,                    // xyz
+        sizeof(float) * 2 * N,                 // dist
+        sizeof(int) * 2 * N,                   // lab
+        sizeof(unsigned) * 2 * (size_t)z.W,    // bits
+        sizeof(int) * 4 * G,                   // cnt
+        sizeof(int) * N,                       // retire
+        sizeof(int) * scan_blocks,             // scan_tmp
+        sizeof(unsigned) * kLine * 2 * G,      // barrier lines
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -81,180 +189,412 @@ size_t work_layout(int n, int f, int gmax, Layout* L) {
     return off;
 }
 
-Work carve(void* base, int, int, int, const Layout& L) {
+Work carve(void* base, const Layout& L) {
     char* b = static_cast<char*>(base);
     Work w;
     w.ctrl = reinterpret_cast<int*>(b + L.off[0]);
-    w.level = reinterpret_cast<int*>(b + L.off[1]);
-    w.perm = reinterpret_cast<int*>(b + L.off[2]);
-    w.iperm = reinterpret_cast<int*>(b + L.off[3]);
-    w.offsets = reinterpret_cast<int*>(b + L.off[4]);
-    w.rowO = reinterpret_cast<int*>(b + L.off[5]);
-    w.faceO = reinterpret_cast<int*>(b + L.off[6]);
-    w.cursor = reinterpret_cast<int*>(b + L.off[7]);
-    w.rowN = reinterpret_cast<int*>(b + L.off[8]);
-    w.wedge = reinterpret_cast<int2*>(b + L.off[9]);
-    w.xyz = reinterpret_cast<float4*>(b + L.off[10]);
-    w.dist = reinterpret_cast<float*>(b + L.off[11]);
-    w.lab = reinterpret_cast<int*>(b + L.off[12]);
-    w.bits = reinterpret_cast<unsigned*>(b + L.off[13]);
-    w.cnt = reinterpret_cast<int*>(b + L.off[14]);
-    w.retire = reinterpret_cast<int*>(b + L.off[15]);
-    w.scan_tmp = reinterpret_cast<int*>(b + L.off[16]);
-    w.bar = reinterpret_cast<unsigned*>(b + L.off[17]);
+    w.mesh = reinterpret_cast<MeshDesc*>(b + L.off[1]);
+    w.state = reinterpret_cast<MeshState*>(b + L.off[2]);
+    w.wg_prep = reinterpret_cast<WgInfo*>(b + L.off[3]);
+    w.glist_prep = reinterpret_cast<int*>(b + L.off[4]);
+    w.wg_run = reinterpret_cast<WgInfo*>(b + L.off[5]);
+    w.glist_run = reinterpret_cast<int*>(b + L.off[6]);
+    w.vo = reinterpret_cast<int*>(b + L.off[7]);
+    w.fo3 = reinterpret_cast<int*>(b + L.off[8]);
+    w.so = reinterpret_cast<int*>(b + L.off[9]);
+    w.level = reinterpret_cast<int*>(b + L.off[10]);
+    w.perm = reinterpret_cast<int*>(b + L.off[11]);
+    w.iperm = reinterpret_cast<int*>(b + L.off[12]);
+    w.offsets = reinterpret_cast<int*>(b + L.off[13]);
+    w.rowO = reinterpret_cast<int*>(b + L.off[14]);
+    w.wedgeO = reinterpret_cast<int2*>(b + L.off[15]);
+    w.cursor = reinterpret_cast<int*>(b + L.off[16]);
+    w.rowN = reinterpret_cast<int*>(b + L.off[17]);
+    w.wedge = reinterpret_cast<int2*>(b + L.off[18]);
+    w.xyz = reinterpret_cast<float4*>(b + L.off[19]);
+    w.dist = reinterpret_cast<float*>(b + L.off[20]);
+    w.lab = reinterpret_cast<int*>(b + L.off[21]);
+    w.bits = reinterpret_cast<unsigned*>(b + L.off[22]);
+    w.cnt = reinterpret_cast<int*>(b + L.off[23]);
+    w.retire = reinterpret_cast<int*>(b + L.off[24]);
+    w.scan_tmp = reinterpret_cast<int*>(b + L.off[25]);
+    w.bar = reinterpret_cast<unsigned*>(b + L.off[26]);
     return w;
 }
 
 }  // namespace ptp
 
+// ---- the shared implementation ------------------------------------------
+struct Solver {
+    std::vector<MeshDesc> mesh;
+    std::vector<int> h_vo, h_fo3, h_so;
+    Sizes z{};
+    ptp_options opt{};
+    bool single = false;
+    int device = 0, cus = 0, max_prep = 0, max_run = 0;
+    ptp_schedule sched{};
+    Sched s_prep, s_run;
+    Layout layout{};
+    Work work{};
+    hipStream_t stream = nullptr;
+    const int32_t* S = nullptr;
+    std::vector<MeshState> hstate;
+    bool prepared = false, ran = false;
+    std::string err;
+    int h_ctrl[8];
+
+    ptp_status fail(ptp_status s, const std::string& msg) {
+        err = msg;
+        return s;
+    }
+    ptp_status hip_fail(hipError_t e, const char* what) {
+        return fail(PTP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+
+    ptp_status init(const ptp_mesh* m, int count, const ptp_options* o, bool one) {
+        single = one;
+        if (count < 1 || !m) return PTP_EINVAL;
+        if (o) {
+            opt = *o;
+        } else {
+            opt.tol = 1e-3f;
+            opt.max_iters = 0;
+            opt.window = 0;
+            opt.want_labels = 0;
+            opt.workgroups = 0;
+        }
+        if (!(opt.tol > 0.f) || opt.max_iters < 0 || opt.window < 0 || opt.workgroups < 0)
+            return PTP_EINVAL;
+        long long N = 0, F = 0, Sn = 0, W = 0;
+        h_vo.assign(1, 0);
+        h_fo3.assign(1, 0);
+        h_so.assign(1, 0);
+        for (int b = 0; b < count; ++b) {
+            const ptp_mesh& d = m[b];
+            if (d.n_vertices < 1 || d.n_faces < 0 || d.n_sources < 1 || d.n_sources > d.n_vertices)
+                return PTP_EINVAL;
+            if (d.v_off < 0 || d.f_off < 0 || d.s_off < 0 || d.out_off < 0) return PTP_EINVAL;
+            MeshDesc md;
+            md.v_off = (int)N;
+            md.f_off = (int)F;
+            md.s_off = (int)Sn;
+            md.w_off = (int)W;
+            md.n = d.n_vertices;
+            md.f = d.n_faces;
+            md.m = d.n_sources;
+            md.pad = 0;
+            md.v_in = d.v_off;
+            md.f_in = d.f_off;
+            md.s_in = d.s_off;
+            md.out_off = d.out_off;
+            N += d.n_vertices;
+            F += d.n_faces;
+            Sn += d.n_sources;
+            W += (d.n_vertices + 31) / 32;
+            if (N > (1ll << 29) || 3 * F >= (1ll << 31) || Sn >= (1ll << 31)) return PTP_EUNSUPPORTED;
+            mesh.push_back(md);
+            h_vo.push_back((int)N);
+            h_fo3.push_back((int)(3 * F));
+            h_so.push_back((int)Sn);
+        }
+        hipError_t e = hipGetDevice(&device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+        int coop = 0;
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
+        if (e != hipSuccess || !coop || cus < 1) return PTP_EDEVICE;
+        max_prep = max_coop_blocks_bfs(cus);
+        max_run = max_coop_blocks_run(cus, opt.want_labels != 0);
+        z.N = N;
+        z.F = F;
+        z.S = Sn;
+        z.B = count;
+        z.W = W;
+        z.gmax = std::max(max_prep, max_run);
+        sched = default_schedule();
+        work_layout(z, &layout);
+        return PTP_OK;
+    }
+
+    ptp_schedule default_schedule() const {
+        ptp_schedule p;
+        p.workgroups = std::min(max_run, 4 * cus);
+        p.small_limit = 32768;
+        p.large_limit = 262144;
+        p.medium_group = 4;
+        p.large_group = 16;
+        return p;
+    }
+
+    void set_schedule(const ptp_schedule* s) {
+        ptp_schedule d = default_schedule();
+        if (s) {
+            if (s->workgroups > 0) d.workgroups = s->workgroups;
+            if (s->small_limit > 0) d.small_limit = s->small_limit;
+            if (s->large_limit > 0) d.large_limit = s->large_limit;
+            if (s->medium_group > 0) d.medium_group = s->medium_group;
+            if (s->large_group > 0) d.large_group = s->large_group;
+        }
+        sched = d;
+    }
+
+    // Single mesh: one group; about one workgroup per 1024 reachable vertices
+    // within [16, 512] (the per-iteration cost is flat from ~n/2048 to ~n/512
+    // workgroups on the icosphere workloads and rises outside).
+    int single_group(int gmax, long long reach) const {
+        if (opt.workgroups > 0) return std::min(opt.workgroups, gmax);
+        long long g = reach / 1024;
+        g = std::max(16ll, std::min(512ll, g));
+        return (int)std::min<long long>(g, gmax);
+    }
+
+    hipError_t upload(const Sched& s, WgInfo* dwg, int* dgl) {
+        hipError_t e = hipMemcpyAsync(dwg, s.wg.data(), sizeof(WgInfo) * s.wg.size(),
+                                      hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dgl, s.glist.data(), sizeof(int) * s.glist.size(), hipMemcpyHostToDevice,
+                               stream);
+        return e;
+    }
+
+    ptp_status prepare(const float* dV, const int32_t* dF, const int32_t* dS, void* dWork,
+                       size_t bytes, void* st) {
+        prepared = false;
+        ran = false;
+        if (!dV || !dS || (!dF && z.F > 0) || !dWork) return fail(PTP_EINVAL, "null pointer argument");
+        if (reinterpret_cast<uintptr_t>(dWork) & 255)
+            return fail(PTP_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < layout.total) return fail(PTP_ENOMEM, "workspace smaller than the plan needs");
+        stream = static_cast<hipStream_t>(st);
+        work = carve(dWork, layout);
+        S = dS;
+        std::vector<long long> rho_est(z.B);
+        for (int b = 0; b < z.B; ++b) rho_est[b] = (long long)(2.0 * std::sqrt((double)mesh[b].n)) + 1;
+        s_prep = make_schedule(mesh, rho_est, sched, max_prep, single,
+                               single ? std::min(cus, max_prep) : 0);
+        hstate.assign(z.B, MeshState{});
+        hipError_t e = hipMemcpyAsync(work.mesh, mesh.data(), sizeof(MeshDesc) * z.B,
+                                      hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work.vo, h_vo.data(), sizeof(int) * (z.B + 1), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work.fo3, h_fo3.data(), sizeof(int) * (z.B + 1), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work.so, h_so.data(), sizeof(int) * (z.B + 1), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work.state, hstate.data(), sizeof(MeshState) * z.B, hipMemcpyHostToDevice,
+                               stream);
+        if (e == hipSuccess) e = upload(s_prep, work.wg_prep, work.glist_prep);
+        if (e != hipSuccess) return hip_fail(e, "prepare upload");
+        e = launch_prepare(work, z, dV, dF, dS, s_prep.G, stream);
+        if (e != hipSuccess) return hip_fail(e, "prepare launch");
+        e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hstate.data(), work.state, sizeof(MeshState) * z.B, hipMemcpyDeviceToHost,
+                               stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "prepare");
+        if (h_ctrl[C_ABORT]) return fail(PTP_EDEVICE, "BFS barrier timed out");
+        const int stw = h_ctrl[C_STATUS];
+        if (stw) {
+            std::string msg = "invalid input:";
+            if (stw & ST_BAD_FACE) msg += " face index out of range;";
+            if (stw & ST_BAD_COORD) msg += " non-finite coordinate;";
+            if (stw & ST_BAD_SOURCE) msg += " source index out of range;";
+            if (stw & ST_DUP_SOURCE) msg += " duplicate source;";
+            return fail(PTP_EINVAL, msg);
+        }
+        std::vector<long long> rho(z.B);
+        long long reach = 0;
+        for (int b = 0; b < z.B; ++b) {
+            const MeshState& x = hstate[b];
+            if (x.rho < 1 || x.reach < mesh[b].m || x.reach > mesh[b].n)
+                return fail(PTP_EDEVICE, "BFS produced an inconsistent result");
+            rho[b] = x.rho;
+            reach += x.reach;
+        }
+        s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
+        e = upload(s_run, work.wg_run, work.glist_run);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "schedule upload");
+        prepared = true;
+        return PTP_OK;
+    }
+
+    ptp_status run(float* dDist, int32_t* dLabel, void* st) {
+        if (!prepared) return fail(PTP_EINVAL, "run before a successful prepare");
+        if (!dDist) return fail(PTP_EINVAL, "null distance output");
+        const bool labels = opt.want_labels != 0;
+        if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
+        stream = static_cast<hipStream_t>(st);
+        RunParams rp;
+        rp.B = z.B;
+        rp.kmax_fixed = opt.max_iters;
+        rp.window = opt.window;
+        rp.N = z.N;
+        rp.tol = opt.tol;
+        rp.S = S;
+        rp.out_d = dDist;
+        rp.out_l = labels ? dLabel : nullptr;
+        hipError_t e = launch_run(work, rp, labels, s_run.G, stream);
+        if (e != hipSuccess) return hip_fail(e, "run launch");
+        ran = true;
+        return PTP_OK;
+    }
+
+    ptp_status stats(ptp_stats* out, int32_t* status) {
+        if (!ran) return fail(PTP_EINVAL, "no run to report");
+        hipError_t e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hstate.data(), work.state, sizeof(MeshState) * z.B, hipMemcpyDeviceToHost,
+                               stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "stats");
+        ptp_status agg = PTP_OK;
+        for (int b = 0; b < z.B; ++b) {
+            const MeshState& x = hstate[b];
+            ptp_status sb = PTP_OK;
+            if (x.status) sb = PTP_EINVAL;
+            else if (h_ctrl[C_ABORT]) sb = PTP_EDEVICE;
+            else if (x.runstat) sb = PTP_ENOCONV;
+            if (status) status[b] = sb;
+            if (out) {
+                out[b].iterations = x.iters;
+                out[b].n_toplesets = x.rho;
+                out[b].reachable = x.reach;
+                out[b].workgroups = s_run.gsize_of[b];
+                out[b].vertex_updates = x.updates;
+            }
+            if (agg == PTP_OK && sb != PTP_OK) agg = sb;
+        }
+        if (h_ctrl[C_ABORT]) return fail(PTP_EDEVICE, "relaxation barrier timed out");
+        if (agg == PTP_ENOCONV) return fail(PTP_ENOCONV, "iteration cap reached");
+        return agg;
+    }
+
+    ptp_status autotune(const ptp_schedule* cand, int n, float* dDist, int32_t* dLabel, float* hMs,
+                        int32_t* best, void* st) {
+        if (!prepared) return fail(PTP_EINVAL, "autotune before a successful prepare");
+        if (!cand || n < 1) return fail(PTP_EINVAL, "no candidate schedules");
+        stream = static_cast<hipStream_t>(st);
+        std::vector<long long> rho(z.B);
+        long long reach = 0;
+        for (int b = 0; b < z.B; ++b) {
+            rho[b] = hstate[b].rho;
+            reach += hstate[b].reach;
+        }
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return fail(PTP_EDEVICE, "event");
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(PTP_EDEVICE, "event");
+        }
+        const ptp_schedule keep = sched;
+        int bi = -1;
+        float bms = 0.f;
+        ptp_status rc = PTP_OK;
+        for (int c = 0; c < n && rc == PTP_OK; ++c) {
+            set_schedule(&cand[c]);
+            s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
+            hipError_t e = upload(s_run, work.wg_run, work.glist_run);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "schedule upload");
+                break;
+            }
+            rc = run(dDist, dLabel, st);                  // warm-up
+            if (rc != PTP_OK) break;
+            e = hipEventRecord(e0, stream);
+            if (e == hipSuccess) rc = run(dDist, dLabel, st);
+            if (e == hipSuccess && rc == PTP_OK) e = hipEventRecord(e1, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "autotune timing");
+                break;
+            }
+            ptp_status sr = stats(nullptr, nullptr);
+            if (sr == PTP_EDEVICE) {
+                rc = sr;
+                break;
+            }
+            if (hMs) hMs[c] = ms;
+            if (bi < 0 || ms < bms) {
+                bi = c;
+                bms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != PTP_OK) {
+            sched = keep;
+            return rc;
+        }
+        set_schedule(&cand[bi]);
+        s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
+        hipError_t e = upload(s_run, work.wg_run, work.glist_run);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "schedule upload");
+        if (best) *best = bi;
+        return PTP_OK;
+    }
+};
+
+struct ptp_plan {
+    Solver s;
+};
+struct ptp_batch {
+    Solver s;
+};
+
 extern "C" {
 
-const char* ptp_version(void) { return "ptp-mi355x 0.1 (gfx950)"; }
+const char* ptp_version(void) { return "ptp-mi355x 0.2 (gfx950)"; }
 
+// ---- one mesh ------------------------------------------------------------
 ptp_status ptp_plan_create(ptp_plan** out, int32_t n, int32_t f, int32_t m, const ptp_options* opt) {
     if (!out) return PTP_EINVAL;
     *out = nullptr;
     if (n < 1 || f < 0 || m < 1 || m > n) return PTP_EINVAL;
     if (n > (1 << 29) || (long long)f * 3 >= (1ll << 31)) return PTP_EUNSUPPORTED;
-    ptp_options o;
-    if (opt) {
-        o = *opt;
-    } else {
-        o.tol = 1e-3f;
-        o.max_iters = 0;
-        o.window = 0;
-        o.want_labels = 0;
-        o.workgroups = 0;
-    }
-    if (!(o.tol > 0.f) || o.max_iters < 0 || o.window < 0 || o.workgroups < 0) return PTP_EINVAL;
+    if (opt && (!(opt->tol > 0.f) || opt->max_iters < 0 || opt->window < 0 || opt->workgroups < 0))
+        return PTP_EINVAL;
     ptp_plan* p = new (std::nothrow) ptp_plan();
     if (!p) return PTP_ENOMEM;
-    p->n = n;
-    p->f = f;
-    p->m = m;
-    p->opt = o;
-    hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    int coop = 0;
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device);
-    if (e != hipSuccess || !coop || p->cus < 1) {
+    ptp_mesh d;
+    d.v_off = d.f_off = d.s_off = d.out_off = 0;
+    d.n_vertices = n;
+    d.n_faces = f;
+    d.n_sources = m;
+    d.reserved = 0;
+    ptp_status s = p->s.init(&d, 1, opt, true);
+    if (s != PTP_OK) {
         delete p;
-        return PTP_EDEVICE;
+        return s;
     }
-    const bool labels = o.want_labels != 0;
-    const int max_bfs = max_coop_blocks_bfs(p->cus);
-    const int max_run = max_coop_blocks_run(p->cus, labels);
-    p->g_bfs = p->cus < max_bfs ? p->cus : max_bfs;
-    p->max_run = max_run;
-    // an explicit grid is fixed here; the automatic one is chosen per prepared
-    // mesh in ptp_run, so the barrier lines cover the largest possible grid
-    p->g_run = o.workgroups > 0 ? (o.workgroups < max_run ? o.workgroups : max_run) : 0;
-    p->gmax = p->g_bfs > max_run ? p->g_bfs : max_run;
-    work_layout(n, f, p->gmax, &p->layout);
     *out = p;
     return PTP_OK;
 }
 
 ptp_status ptp_workspace_bytes(const ptp_plan* p, size_t* bytes) {
     if (!p || !bytes) return PTP_EINVAL;
-    *bytes = p->layout.total;
+    *bytes = p->s.layout.total;
     return PTP_OK;
 }
 
 ptp_status ptp_prepare(ptp_plan* p, const float* dV, const int32_t* dF, const int32_t* dS,
                        void* dWork, size_t work_bytes, void* stream) {
     if (!p) return PTP_EINVAL;
-    p->prepared = false;
-    p->ran = false;
-    if (!dV || !dS || (!dF && p->f > 0) || !dWork)
-        return fail(p, PTP_EINVAL, "null pointer argument");
-    if (reinterpret_cast<uintptr_t>(dWork) & 255)
-        return fail(p, PTP_EINVAL, "workspace must be 256-byte aligned");
-    if (work_bytes < p->layout.total)
-        return fail(p, PTP_ENOMEM, "workspace smaller than ptp_workspace_bytes()");
-    p->ws = dWork;
-    p->ws_bytes = work_bytes;
-    p->stream = static_cast<hipStream_t>(stream);
-    p->work = carve(dWork, p->n, p->f, p->gmax, p->layout);
-    p->S = dS;
-    hipError_t e = launch_prepare(p->work, p->n, p->f, p->m, dV, dF, dS, p->g_bfs, p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "prepare launch");
-    e = hipMemcpyAsync(p->h_ctrl, p->work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "prepare");
-    const int st = p->h_ctrl[C_STATUS];
-    if (p->h_ctrl[C_ABORT]) return fail(p, PTP_EDEVICE, "BFS barrier timed out");
-    if (st) {
-        std::string msg = "invalid input:";
-        if (st & ST_BAD_FACE) msg += " face index out of range;";
-        if (st & ST_BAD_COORD) msg += " non-finite coordinate;";
-        if (st & ST_BAD_SOURCE) msg += " source index out of range;";
-        if (st & ST_DUP_SOURCE) msg += " duplicate source;";
-        return fail(p, PTP_EINVAL, msg);
-    }
-    p->rho = p->h_ctrl[C_RHO];
-    p->reach = p->h_ctrl[C_REACH];
-    if (p->rho < 1 || p->reach < p->m || p->reach > p->n)
-        return fail(p, PTP_EDEVICE, "BFS produced an inconsistent result");
-    p->prepared = true;
-    return PTP_OK;
+    return p->s.prepare(dV, dF, dS, dWork, work_bytes, stream);
 }
 
 ptp_status ptp_run(ptp_plan* p, float* dDist, int32_t* dLabel, void* stream) {
     if (!p) return PTP_EINVAL;
-    if (!p->prepared) return fail(p, PTP_EINVAL, "ptp_run before a successful ptp_prepare");
-    if (!dDist) return fail(p, PTP_EINVAL, "null distance output");
-    const bool labels = p->opt.want_labels != 0;
-    if (labels && !dLabel) return fail(p, PTP_EINVAL, "plan wants labels: null label output");
-    p->stream = static_cast<hipStream_t>(stream);
-    RunParams rp;
-    rp.n = p->n;
-    rp.m = p->m;
-    rp.rho = p->rho;
-    rp.kmax = p->opt.max_iters > 0 ? p->opt.max_iters : 4 * p->rho + 16;
-    rp.window = p->opt.window;
-    rp.tol = p->opt.tol;
-    rp.S = p->S;
-    rp.out_d = dDist;
-    rp.out_l = labels ? dLabel : nullptr;
-    // Automatic grid: about one workgroup (256 threads) per 1024 reachable
-    // vertices, within [16, 512] and the co-residency limit.  Measured on the
-    // icosphere workloads: the per-iteration cost is flat from ~n/2048 to
-    // ~n/512 workgroups and rises outside.
-    int g = p->g_run;
-    if (g <= 0) {
-        g = p->reach / 1024;
-        if (g < 16) g = 16;
-        if (g > 512) g = 512;
-        if (g > p->max_run) g = p->max_run;
-    }
-    p->g_used = g;
-    hipError_t e = launch_run(p->work, rp, labels, g, p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "run launch");
-    p->ran = true;
-    return PTP_OK;
+    return p->s.run(dDist, dLabel, stream);
 }
 
 ptp_status ptp_get_stats(ptp_plan* p, ptp_stats* st) {
     if (!p) return PTP_EINVAL;
-    if (!p->ran) return fail(p, PTP_EINVAL, "no run to report");
-    hipError_t e = hipMemcpyAsync(p->h_ctrl, p->work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost,
-                                  p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "stats");
-    if (st) {
-        st->iterations = p->h_ctrl[C_ITERS];
-        st->n_toplesets = p->rho;
-        st->reachable = p->reach;
-        st->workgroups = p->g_used;
-        st->vertex_updates = ((int64_t)(uint32_t)p->h_ctrl[C_UPD_HI] << 32) |
-                             (int64_t)(uint32_t)p->h_ctrl[C_UPD_LO];
-    }
-    if (p->h_ctrl[C_ABORT]) return fail(p, PTP_EDEVICE, "relaxation barrier timed out");
-    if (p->h_ctrl[C_RUNSTAT]) return fail(p, PTP_ENOCONV, "iteration cap reached");
-    return PTP_OK;
+    return p->s.stats(st, nullptr);
 }
 
 ptp_status ptp_solve(ptp_plan* p, const float* dV, const int32_t* dF, const int32_t* dS,
@@ -269,33 +609,107 @@ ptp_status ptp_solve(ptp_plan* p, const float* dV, const int32_t* dF, const int3
 
 ptp_status ptp_get_order(ptp_plan* p, int32_t* dPerm, int32_t* dOffsets, void* stream) {
     if (!p) return PTP_EINVAL;
-    if (!p->prepared) return fail(p, PTP_EINVAL, "no prepared mesh");
+    Solver& s = p->s;
+    if (!s.prepared) return s.fail(PTP_EINVAL, "no prepared mesh");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (dPerm)
-        e = hipMemcpyAsync(dPerm, p->work.perm, sizeof(int) * (size_t)p->n,
-                           hipMemcpyDeviceToDevice, st);
+        e = hipMemcpyAsync(dPerm, s.work.perm, sizeof(int) * (size_t)s.z.N, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && dOffsets)
-        e = hipMemcpyAsync(dOffsets, p->work.offsets, sizeof(int) * ((size_t)p->rho + 1),
+        e = hipMemcpyAsync(dOffsets, s.work.offsets, sizeof(int) * ((size_t)s.hstate[0].rho + 1),
                            hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(p, e, "get_order");
+    if (e != hipSuccess) return s.hip_fail(e, "get_order");
     return PTP_OK;
 }
 
 ptp_status ptp_get_schedule(ptp_plan* p, int32_t* hRetire) {
     if (!p || !hRetire) return PTP_EINVAL;
-    if (!p->ran) return fail(p, PTP_EINVAL, "no run to report");
-    hipError_t e = hipMemcpyAsync(hRetire, p->work.retire, sizeof(int) * (size_t)p->rho,
-                                  hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "get_schedule");
+    Solver& s = p->s;
+    if (!s.ran) return s.fail(PTP_EINVAL, "no run to report");
+    hipError_t e = hipMemcpyAsync(hRetire, s.work.retire, sizeof(int) * (size_t)s.hstate[0].rho,
+                                  hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return s.hip_fail(e, "get_schedule");
     return PTP_OK;
 }
 
-int32_t ptp_n_toplesets(const ptp_plan* p) { return p && p->prepared ? p->rho : -1; }
+int32_t ptp_n_toplesets(const ptp_plan* p) {
+    return p && p->s.prepared ? p->s.hstate[0].rho : -1;
+}
 
-const char* ptp_last_error(const ptp_plan* p) { return p ? p->err.c_str() : "null plan"; }
+const char* ptp_last_error(const ptp_plan* p) { return p ? p->s.err.c_str() : "null plan"; }
 
 void ptp_plan_destroy(ptp_plan* p) { delete p; }
+
+// ---- batches -------------------------------------------------------------
+ptp_status ptp_batch_create(ptp_batch** out, const ptp_mesh* meshes, int32_t count,
+                            const ptp_options* opt) {
+    if (!out) return PTP_EINVAL;
+    *out = nullptr;
+    if (!meshes || count < 1) return PTP_EINVAL;
+    ptp_batch* p = new (std::nothrow) ptp_batch();
+    if (!p) return PTP_ENOMEM;
+    ptp_status s = p->s.init(meshes, count, opt, false);
+    if (s != PTP_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return PTP_OK;
+}
+
+ptp_status ptp_batch_workspace_bytes(const ptp_batch* p, size_t* bytes) {
+    if (!p || !bytes) return PTP_EINVAL;
+    *bytes = p->s.layout.total;
+    return PTP_OK;
+}
+
+ptp_status ptp_batch_prepare(ptp_batch* p, const float* dV, const int32_t* dF, const int32_t* dS,
+                             void* dWork, size_t work_bytes, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.prepare(dV, dF, dS, dWork, work_bytes, stream);
+}
+
+ptp_status ptp_batch_run(ptp_batch* p, float* dDist, int32_t* dLabel, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.run(dDist, dLabel, stream);
+}
+
+ptp_status ptp_batch_get_stats(ptp_batch* p, ptp_stats* hStats, int32_t* hStatus) {
+    if (!p) return PTP_EINVAL;
+    Solver& s = p->s;
+    if (!s.ran) {   // after a failed prepare: report which meshes were invalid
+        if (hStatus)
+            for (int b = 0; b < s.z.B; ++b)
+                hStatus[b] = (b < (int)s.hstate.size() && s.hstate[b].status) ? PTP_EINVAL : PTP_OK;
+        return s.fail(PTP_EINVAL, "no run to report");
+    }
+    return s.stats(hStats, hStatus);
+}
+
+ptp_status ptp_batch_set_schedule(ptp_batch* p, const ptp_schedule* sch) {
+    if (!p) return PTP_EINVAL;
+    if (sch && (sch->workgroups < 0 || sch->small_limit < 0 || sch->large_limit < 0 ||
+                sch->medium_group < 0 || sch->large_group < 0))
+        return p->s.fail(PTP_EINVAL, "negative schedule field");
+    p->s.set_schedule(sch);
+    return PTP_OK;
+}
+
+ptp_status ptp_batch_get_schedule(const ptp_batch* p, ptp_schedule* sch) {
+    if (!p || !sch) return PTP_EINVAL;
+    *sch = p->s.sched;
+    return PTP_OK;
+}
+
+ptp_status ptp_batch_autotune(ptp_batch* p, const ptp_schedule* candidates, int32_t n, float* dDist,
+                              int32_t* dLabel, float* hMs, int32_t* best, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.autotune(candidates, n, dDist, dLabel, hMs, best, stream);
+}
+
+const char* ptp_batch_last_error(const ptp_batch* p) { return p ? p->s.err.c_str() : "null batch"; }
+
+void ptp_batch_destroy(ptp_batch* p) { delete p; }
 
 }  // extern "C"

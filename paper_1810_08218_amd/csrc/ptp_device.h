@@ -51,22 +51,25 @@ __device__ inline void st_c(T* p, T v) {
 // a compiler barrier: no access moves across it.
 __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// ---- grid barrier ------------------------------------------------------
-// Flag-array barrier for cooperative launches.  Every workgroup publishes
-// (epoch << 1 | bit) in its own 128-byte line; workgroup 0 polls all lines
-// with its 256 threads, ORs the bits and publishes (epoch << 1 | any) in a
-// release line that everybody polls.  No counter is contended, so the cost
-// barely grows with the grid.  The bit carries the "not converged" vote of
-// the PTP iteration.  A wall-clock limit turns a barrier that can never
-// complete into an abort flag instead of a hang.
+// ---- group barrier -----------------------------------------------------
+// Flag-array barrier among the gsize consecutive workgroups of a group of a
+// cooperative launch.  Every workgroup publishes (epoch << 1 | bit) in its
+// own 128-byte line; the group's first workgroup polls all lines with its 256
+// threads, ORs the bits and publishes (epoch << 1 | any) in the group's
+// release line, which the others poll.  No counter is contended, so the cost
+// barely grows with the group.  The bit carries a vote (the "not converged"
+// vote of the PTP iteration, a duplicate source in the BFS).  A wall-clock
+// limit turns a barrier that can never complete into an abort flag instead
+// of a hang.
 //
 // Ordering: each wave waits for its own coherent stores to complete before
 // the workgroup arrives; loads after the barrier are coherent loads issued
 // after the release line was observed.
 struct FlagBarrier {
-    unsigned* flags;     // [G * kLine], zero at launch
+    unsigned* flags;     // [gsize * kLine], zero at launch
     unsigned* release;   // one line, zero at launch
     int* abort_flag;
+    unsigned gsize, rank;
     unsigned epoch;
 
     static constexpr long long kTimeoutTicks = 400000000ll;   // seconds at 100 MHz
@@ -87,19 +90,19 @@ struct FlagBarrier {
     }
 
     // Returns false when the barrier timed out (the kernel must exit);
-    // *any receives the OR of `bit` over all workgroups.
+    // *any receives the OR of `bit` over the group.
     __device__ bool sync(unsigned bit, unsigned* any) {
         __shared__ unsigned s_any;
         __shared__ int s_ok;
-        const unsigned G = gridDim.x, w = blockIdx.x, tid = threadIdx.x;
+        const unsigned tid = threadIdx.x;
         wait_memory();
         bit = __syncthreads_or(bit) ? 1u : 0u;
         epoch += 1;
-        if (tid == 0) st_c(flags + (size_t)w * kLine, (epoch << 1) | bit);
-        if (w == 0) {
+        if (tid == 0) st_c(flags + (size_t)rank * kLine, (epoch << 1) | bit);
+        if (rank == 0) {
             unsigned acc = 0;
             int ok = 1;
-            for (unsigned x = tid; x < G; x += kBlock) {
+            for (unsigned x = tid; x < gsize; x += kBlock) {
                 unsigned v;
                 if (!spin_ge(flags + (size_t)x * kLine, epoch, &v)) {
                     ok = 0;
@@ -121,6 +124,18 @@ struct FlagBarrier {
         return s_ok && ld_c(abort_flag) == 0;
     }
 };
+
+// Mesh of a flat element index: the largest b with prefix[b] <= x
+// (prefix[0] = 0, prefix[B] = total; empty meshes are skipped).
+__device__ inline int mesh_of(const int* prefix, int B, long long x) {
+    int lo = 0, hi = B;          // invariant: prefix[lo] <= x < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)prefix[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // ---- block-wide scans (kBlock threads) ----------------------------------
 // Exclusive prefix of `v` over the workgroup; *total receives the sum.

@@ -1,4 +1,11 @@
 // Internal interface between the host API and the kernel sources.
+//
+// Every solve is a batch: B meshes concatenated in the caller's arrays
+// (one mesh is a batch of one).  Vertex, face and source ids inside each
+// mesh are local; the library works on the concatenation, in which mesh b
+// owns the positions [v_off_b, v_off_b + n_b).  The persistent kernels run
+// "groups" of consecutive workgroups; each group takes its meshes one after
+// the other, with a barrier of its own.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,47 +14,83 @@
 
 namespace ptp {
 
-// Device workspace of one plan, carved from the caller's buffer.
-struct Work {
-    int* ctrl;          // C_WORDS control words
-    int* level;         // [n]    hop distance, caller ids (-1 unreachable)
-    int* perm;          // [n]    position -> caller id (the BFS queue)
-    int* iperm;         // [n]    caller id -> position
-    int* offsets;       // [n+2]  topleset starts in positions
-    int* rowO;          // [n+1]  incidence CSR over caller ids
-    int* faceO;         // [3f]   incident corners (3 * face + corner)
-    int* cursor;        // [n]    fill cursors
-    int* rowN;          // [n+1]  incidence CSR over positions
-    int2* wedge;        // [3f]   opposite edge of each incident triangle, positions
-    float4* xyz;        // [n]    coordinates by position (w unused)
-    float* dist;        // [2n]   Jacobi double buffer
-    int* lab;           // [2n]   label double buffer
-    unsigned* bits;     // [2*nwords] frontier bitmaps
-    int* cnt;           // [4*gmax] per-workgroup chunk counts
-    int* retire;        // [n]    last iteration that updated each topleset
-    int* scan_tmp;      // block sums of the scans
-    unsigned* bar;      // [(gmax + 1) * 32] barrier lines (last one: release)
+struct MeshDesc {          // per mesh, host and device
+    int v_off, f_off, s_off, w_off;     // internal prefixes: vertices, faces, sources, bitmap words
+    int n, f, m, pad;                   // sizes
+    long long v_in, f_in, s_in;         // first row / entry in the caller's V, F, S
+    long long out_off;                  // first entry in the caller's outputs
 };
 
-constexpr int kLayoutParts = 18;
+struct MeshState {         // per mesh, written by the kernels
+    int status;            // StatusBits of the mesh
+    int rho, reach;        // toplesets, reachable vertices
+    int iters, runstat;    // K, 1 = cap reached
+    int pad;
+    long long updates;     // U
+};
+
+struct WgInfo {            // per workgroup of a persistent launch
+    int group, rank, gsize, first;
+};
+
+// Device workspace, carved from the caller's buffer.
+struct Work {
+    int* ctrl;          // C_WORDS control words (batch-wide)
+    MeshDesc* mesh;     // [B]
+    MeshState* state;   // [B]
+    WgInfo* wg_prep;    // [gmax]  group layout of the BFS launch
+    int* glist_prep;    // [gmax + 1 + B] per-group mesh lists (CSR: starts then ids)
+    WgInfo* wg_run;     // [gmax]  group layout of the relaxation launch
+    int* glist_run;     // [gmax + 1 + B]
+    int* vo;            // [B + 1] internal vertex prefix (mesh of a position / vertex)
+    int* fo3;           // [B + 1] 3 * internal face prefix (mesh of a face corner)
+    int* so;            // [B + 1] internal source prefix (mesh of a source)
+    int* level;         // [N]     hop distance by global vertex id (-1 unreachable)
+    int* perm;          // [N]     position -> global vertex id
+    int* iperm;         // [N]     global vertex id -> position
+    int* offsets;       // [N + B] topleset starts, mesh b at v_off_b + b
+    int* rowO;          // [N + 1] incidence CSR over global vertex ids
+    int2* wedgeO;       // [3F]    opposite edge of each incident triangle, global ids
+    int* cursor;        // [N]     fill cursors
+    int* rowN;          // [N + 1] incidence CSR over positions
+    int2* wedge;        // [3F]    opposite edge, positions
+    float4* xyz;        // [N]     coordinates by position (w unused)
+    float* dist;        // [2N]    Jacobi double buffer
+    int* lab;           // [2N]    label double buffer
+    unsigned* bits;     // [2 * W] frontier bitmaps, mesh b at 2 * w_off_b
+    int* cnt;           // [4 * gmax] per-workgroup chunk counts
+    int* retire;        // [N]     last iteration that updated each topleset, mesh b at v_off_b
+    int* scan_tmp;      // block sums of the scans
+    unsigned* bar;      // [32 * 2 * gmax] barrier lines: one per workgroup, then one per group
+};
+
+constexpr int kLayoutParts = 27;
+
+struct Sizes {
+    long long N, F, S;      // internal totals over the batch
+    int B;                  // meshes
+    long long W;            // bitmap words (sum over meshes)
+    int gmax;               // largest persistent grid
+};
 
 struct Layout {
     size_t off[kLayoutParts];
     size_t total;
 };
 
-size_t work_layout(int n, int f, int gmax, Layout* L);
-Work carve(void* base, int n, int f, int gmax, const Layout& L);
+size_t work_layout(const Sizes& z, Layout* L);
+Work carve(void* base, const Layout& L);
 
-// prepare pipeline; every kernel after validation is gated on the status word
-hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, const int* F,
-                          const int* S, int g_bfs, hipStream_t st);
+// prepare: every kernel after validation is gated on the batch status word
+hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
+                          const int* S, int g_prep, hipStream_t st);
 
-// zero the barrier lines of a grid of g workgroups (before each persistent launch)
-void launch_barrier_reset(const Work& w, int g, hipStream_t st);
+// zero the barrier lines (one per workgroup, one per group) of a launch
+void launch_barrier_reset(const Work& w, int lines, hipStream_t st);
 
 struct RunParams {
-    int n, m, rho, kmax, window;
+    int B, kmax_fixed, window;   // kmax_fixed 0: 4 rho + 16 per mesh
+    long long N;
     float tol;
     const int* S;
     float* out_d;
@@ -56,7 +99,6 @@ struct RunParams {
 
 hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st);
 
-// occupancy-bounded cooperative grid sizes
 int max_coop_blocks_bfs(int cus);
 int max_coop_blocks_run(int cus, bool labels);
 

@@ -1,11 +1,10 @@
-// Preparation of a mesh for PTP on the device:
+// Preparation of a batch of meshes for PTP on the device:
 //   validation (problem statement, Sec. 3.1),
-//   vertex -> triangle incidence,
-//   toplesets V_r by a level-synchronous BFS from S (Sec. 4.1), emitted in the
-//   canonical order (topleset, then ascending caller id),
-//   reorder of coordinates and incidence into that order (Sec. 4.3), with
-//   every triangle stored at each of its corners as the opposite edge
-//   ("wedge") in new positions.
+//   vertex -> triangle incidence over the concatenation, every triangle stored
+//   at each of its corners as the opposite edge ("wedge"),
+//   toplesets V_r of each mesh by a level-synchronous BFS from its sources
+//   (Sec. 4.1), emitted in the canonical order (topleset, then ascending id),
+//   reorder of coordinates and incidence into that order (Sec. 4.3).
 #include "ptp_device.h"
 #include "ptp_kernels.h"
 
@@ -18,6 +17,8 @@ constexpr int kScanTile = kBlock * kScanItems;      // per workgroup
 constexpr int kListCap = 4096;                      // BFS LDS batch
 
 __device__ inline bool gated(const int* ctrl) { return ld_c(ctrl + C_STATUS) != 0; }
+__device__ inline int other1(int c) { return c == 2 ? 0 : c + 1; }
+__device__ inline int other2(int c) { return c == 0 ? 2 : c - 1; }
 
 __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long len, int val) {
     for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < len;
@@ -25,42 +26,78 @@ __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long len, int val)
         p[x] = val;
 }
 
-__global__ __launch_bounds__(kBlock) void k_validate(const float* V, int n, const int* F, int f,
-                                                     const int* S, int m, int* ctrl) {
-    int bad = 0;
+__global__ __launch_bounds__(kBlock) void k_zero_lines(unsigned* p, long long len) {
+    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < len;
+         x += (long long)gridDim.x * kBlock)
+        p[x] = 0u;
+}
+
+// Face ids must lie in their mesh, coordinates be finite, sources lie in
+// their mesh.  Bad meshes are flagged in their state and in the batch word.
+// Loops run over the internal (concatenated) index spaces; each element finds
+// its mesh by binary search and reads the caller's row.
+__global__ __launch_bounds__(kBlock) void k_validate(const float* V, const int* F, const int* S,
+                                                     const MeshDesc* mesh, int B, const int* vo,
+                                                     const int* fo3, const int* so, long long N,
+                                                     long long F3, long long Stot, MeshState* state,
+                                                     int* ctrl) {
     const long long gsz = (long long)gridDim.x * kBlock;
     const long long g0 = blockIdx.x * (long long)kBlock + threadIdx.x;
-    for (long long x = g0; x < 3ll * f; x += gsz) {
-        int v = F[x];
-        if (v < 0 || v >= n) bad |= ST_BAD_FACE;
+    int bad = 0;
+    for (long long x = g0; x < F3; x += gsz) {
+        const int b = mesh_of(fo3, B, x);
+        const int v = F[3 * mesh[b].f_in + (x - fo3[b])];
+        if (v < 0 || v >= mesh[b].n) {
+            atomicOr(&state[b].status, ST_BAD_FACE);
+            bad |= ST_BAD_FACE;
+        }
     }
-    for (long long x = g0; x < 3ll * n; x += gsz) {
-        float c = V[x];
-        if (!(fabsf(c) <= 3.0e38f)) bad |= ST_BAD_COORD;
+    for (long long p = g0; p < N; p += gsz) {
+        const int b = mesh_of(vo, B, p);
+        const float* c = V + 3 * (mesh[b].v_in + (p - vo[b]));
+        if (!(fabsf(c[0]) <= 3.0e38f) || !(fabsf(c[1]) <= 3.0e38f) || !(fabsf(c[2]) <= 3.0e38f)) {
+            atomicOr(&state[b].status, ST_BAD_COORD);
+            bad |= ST_BAD_COORD;
+        }
     }
-    for (long long x = g0; x < m; x += gsz) {
-        int s = S[x];
-        if (s < 0 || s >= n) bad |= ST_BAD_SOURCE;
+    for (long long x = g0; x < Stot; x += gsz) {
+        const int b = mesh_of(so, B, x);
+        const int s = S[mesh[b].s_in + (x - so[b])];
+        if (s < 0 || s >= mesh[b].n) {
+            atomicOr(&state[b].status, ST_BAD_SOURCE);
+            bad |= ST_BAD_SOURCE;
+        }
     }
     if (bad) atomicOr(ctrl + C_STATUS, bad);
 }
 
-// degree of each caller vertex, counted into row[v + 1]
-__global__ __launch_bounds__(kBlock) void k_count(const int* F, int f, int* row, const int* ctrl) {
+// degree of each internal vertex, counted into row[v + 1]
+__global__ __launch_bounds__(kBlock) void k_count(const int* F, const MeshDesc* mesh, int B,
+                                                  const int* fo3, long long F3, int* row,
+                                                  const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < 3ll * f; x += gsz)
-        atomicAdd(row + F[x] + 1, 1);
+    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < F3; x += gsz) {
+        const int b = mesh_of(fo3, B, x);
+        atomicAdd(row + mesh[b].v_off + F[3 * mesh[b].f_in + (x - fo3[b])] + 1, 1);
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, int f, const int* row,
-                                                           int* cursor, int* corner, const int* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const MeshDesc* mesh, int B,
+                                                           const int* fo3, long long F3,
+                                                           const int* row, int* cursor,
+                                                           int2* wedgeO, const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < 3ll * f; x += gsz) {
-        int v = F[x];
-        int slot = atomicAdd(cursor + v, 1);
-        corner[row[v] + slot] = (int)x;
+    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < F3; x += gsz) {
+        const int b = mesh_of(fo3, B, x);
+        const int vo = mesh[b].v_off;
+        const long long lc = x - fo3[b];                 // corner inside the mesh
+        const long long t3 = 3 * mesh[b].f_in + (lc - lc % 3);
+        const int c = (int)(lc % 3);
+        const int v = vo + F[t3 + c];
+        const int slot = atomicAdd(cursor + v, 1);
+        wedgeO[row[v] + slot] = make_int2(vo + F[t3 + other1(c)], vo + F[t3 + other2(c)]);
     }
 }
 
@@ -135,13 +172,16 @@ hipError_t scan_inplace(int* a, long long len, int* tmp, const int* ctrl, hipStr
     return hipGetLastError();
 }
 
-// ---- BFS toplesets (persistent, cooperative launch) ---------------------
+// ---- BFS toplesets (persistent, cooperative launch, groups of workgroups) --
 struct BfsArgs {
-    int n, m, nwords, cw;
-    const int* F;
+    int G;                 // workgroups of the launch
+    const MeshDesc* mesh;
+    MeshState* state;
+    const WgInfo* wg;
+    const int* glist;      // per group: starts [ngroups + 1], then mesh ids
     const int* S;
     const int* row;
-    const int* corner;
+    const int2* wedgeO;
     int* level;
     int* perm;
     int* iperm;
@@ -152,11 +192,9 @@ struct BfsArgs {
     unsigned* bar;
 };
 
-__device__ inline int other1(int c) { return c == 2 ? 0 : c + 1; }
-__device__ inline int other2(int c) { return c == 0 ? 2 : c - 1; }
-
-// The bitmap of V_r is split into G equal chunks of words, one per
-// workgroup.  Per level r, each workgroup
+// One group handles one mesh at a time.  The mesh's bitmap of V_r is split
+// into gsize equal chunks of words, one per workgroup of the group.  Per
+// level r, each workgroup
 //   1. reads the chunk counts of V_r (made by the discoveries of level r-1),
 //      giving |V_r| and the start of its chunk inside V_r;
 //   2. writes its chunk's vertices, in ascending id order, to perm (this is
@@ -164,171 +202,185 @@ __device__ inline int other2(int c) { return c == 0 ? 2 : c - 1; }
 //   3. expands those vertices: each unvisited neighbour gets level r+1 (one
 //      CAS decides the discoverer), its bit in the next bitmap and a count in
 //      the next chunk counts.
-// One grid barrier per level.  A level with no vertex ends the loop: rho = r.
+// One group barrier per level.  A level with no vertex ends the loop: rho = r.
 // level, bits and cnt are shared between workgroups: coherent access only.
 __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     if (gated(a.ctrl)) return;
-    const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x;
-    FlagBarrier gb{a.bar, a.bar + (size_t)G * kLine, a.ctrl + C_ABORT, 0};
+    const WgInfo me = a.wg[blockIdx.x];
+    const int gs = me.gsize, w = me.rank, tid = threadIdx.x;
+    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
+                   a.ctrl + C_ABORT, (unsigned)gs, (unsigned)w, 0};
     unsigned any = 0;
-    const long long gsz = (long long)G * kBlock;
+    const long long gsz = (long long)gs * kBlock;
     const long long g0 = (long long)w * kBlock + tid;
-    unsigned* bits0 = a.bits;
-    unsigned* bits1 = a.bits + a.nwords;
-    for (long long v = g0; v < a.n; v += gsz) st_c(a.level + v, -1);
-    for (long long x = g0; x < 2ll * a.nwords; x += gsz) st_c(a.bits + x, 0u);
-    for (long long x = g0; x < 4ll * G; x += gsz) st_c(a.cnt + x, 0);
-    if (!gb.sync(0, &any)) return;
-    unsigned dup = 0;
-    for (long long s = g0; s < a.m; s += gsz) {
-        int v = a.S[s];
-        if (atomicCAS(a.level + v, -1, 0) != -1) {
-            dup = 1;
-        } else {
-            atomicOr(bits0 + (v >> 5), 1u << (v & 31));
-            atomicAdd(a.cnt + (v >> 5) / a.cw, 1);
-        }
-    }
-    if (!gb.sync(dup, &any)) return;
-    if (any) {
-        if (w == 0 && tid == 0) atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
-        return;
-    }
-
+    int* cntg = a.cnt + 4 * me.first;
     __shared__ int list[kListCap];
-    const int wbeg = min(w * a.cw, a.nwords);
-    const int wend = min(wbeg + a.cw, a.nwords);
-    const int q = (wend - wbeg + kBlock - 1) / kBlock;
-    const int my0 = min(wbeg + tid * q, wend);
-    const int my1 = min(my0 + q, wend);
-    int base = 0;
-    int r = 0;
-    for (;; ++r) {
-        const int* cr = a.cnt + (r % 3) * G;
-        int part = 0, partpre = 0;
-        for (int x = tid; x < G; x += kBlock) {
-            int c = ld_c(cr + x);
-            part += c;
-            if (x < w) partpre += c;
-        }
-        const int total = block_sum(part);
-        const int chunk_pre = block_sum(partpre);
-        if (total == 0) break;
-        if (w == 0 && tid == 0) a.offsets[r] = base;
-        if (tid == 0) st_c(a.cnt + ((r + 2) % 3) * G + w, 0);
-        unsigned* cur = (r & 1) ? bits1 : bits0;
-        unsigned* nxt = (r & 1) ? bits0 : bits1;
-        int* cn = a.cnt + ((r + 1) % 3) * G;
 
-        int pc = 0;
-        for (int x = my0; x < my1; ++x) pc += __popc(ld_c(cur + x));
-        int tot_w;
-        const int pre = block_exclusive_scan(pc, &tot_w);
-        for (int done = 0; done < tot_w; done += kListCap) {
-            int rank = pre;
-            for (int x = my0; x < my1 && rank < done + kListCap; ++x) {
-                unsigned word = ld_c(cur + x);
-                while (word) {
-                    int b = __ffs(word) - 1;
-                    word &= word - 1;
-                    int u = x * 32 + b;
-                    if (rank >= done && rank < done + kListCap) {
-                        list[rank - done] = u;
-                        int pos = base + chunk_pre + rank;
-                        a.perm[pos] = u;
-                        a.iperm[u] = pos;
-                    }
-                    ++rank;
-                }
+    const int* lst = a.glist + a.glist[me.group];
+    const int nlst = a.glist[me.group + 1] - a.glist[me.group];
+    for (int li = 0; li < nlst; ++li) {
+        const int b = lst[li];
+        const MeshDesc d = a.mesh[b];
+        const int n = d.n, vo = d.v_off;
+        const int nwords = (n + 31) / 32;
+        const int cw = max(1, (nwords + gs - 1) / gs);
+        unsigned* bits0 = a.bits + 2ll * d.w_off;
+        unsigned* bits1 = bits0 + nwords;
+        int* offs = a.offsets + vo + b;
+        for (long long v = g0; v < n; v += gsz) st_c(a.level + vo + v, -1);
+        for (long long x = g0; x < 2ll * nwords; x += gsz) st_c(bits0 + x, 0u);
+        for (long long x = g0; x < 4ll * gs; x += gsz) st_c(cntg + x, 0);
+        if (!gb.sync(0, &any)) return;
+        unsigned dup = 0;
+        for (long long s = g0; s < d.m; s += gsz) {
+            const int v = a.S[d.s_in + s];
+            if (atomicCAS(a.level + vo + v, -1, 0) != -1) {
+                dup = 1;
+            } else {
+                atomicOr(bits0 + (v >> 5), 1u << (v & 31));
+                atomicAdd(cntg + (v >> 5) / cw, 1);
             }
-            __syncthreads();
-            const int cntl = min(kListCap, tot_w - done);
-            const int lvl = r + 1;
-            for (int t = tid; t < cntl; t += kBlock) {
-                const int u = list[t];
-                for (int e = a.row[u]; e < a.row[u + 1]; ++e) {
-                    const int cx = a.corner[e];
-                    const int tri = cx / 3, c = cx - 3 * tri;
-                    const int nb[2] = {a.F[3 * tri + other1(c)], a.F[3 * tri + other2(c)]};
-                    for (int z = 0; z < 2; ++z) {
-                        const int x = nb[z];
-                        if (ld_c(a.level + x) < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
-                            atomicOr(nxt + (x >> 5), 1u << (x & 31));
-                            atomicAdd(cn + (x >> 5) / a.cw, 1);
+        }
+        if (!gb.sync(dup, &any)) return;
+        if (any) {
+            if (w == 0 && tid == 0) {
+                atomicOr(&a.state[b].status, ST_DUP_SOURCE);
+                atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
+            }
+            continue;   // every workgroup of the group skips this mesh
+        }
+
+        const int wbeg = min(w * cw, nwords);
+        const int wend = min(wbeg + cw, nwords);
+        const int q = (wend - wbeg + kBlock - 1) / kBlock;
+        const int my0 = min(wbeg + tid * q, wend);
+        const int my1 = min(my0 + q, wend);
+        int base = 0;
+        int r = 0;
+        for (;; ++r) {
+            const int* cr = cntg + (r % 3) * gs;
+            int part = 0, partpre = 0;
+            for (int x = tid; x < gs; x += kBlock) {
+                const int c = ld_c(cr + x);
+                part += c;
+                if (x < w) partpre += c;
+            }
+            const int total = block_sum(part);
+            const int chunk_pre = block_sum(partpre);
+            if (total == 0) break;
+            if (w == 0 && tid == 0) offs[r] = base;
+            if (tid == 0) st_c(cntg + ((r + 2) % 3) * gs + w, 0);
+            unsigned* cur = (r & 1) ? bits1 : bits0;
+            unsigned* nxt = (r & 1) ? bits0 : bits1;
+            int* cn = cntg + ((r + 1) % 3) * gs;
+
+            int pc = 0;
+            for (int x = my0; x < my1; ++x) pc += __popc(ld_c(cur + x));
+            int tot_w;
+            const int pre = block_exclusive_scan(pc, &tot_w);
+            for (int done = 0; done < tot_w; done += kListCap) {
+                int rank = pre;
+                for (int x = my0; x < my1 && rank < done + kListCap; ++x) {
+                    unsigned word = ld_c(cur + x);
+                    while (word) {
+                        const int bt = __ffs(word) - 1;
+                        word &= word - 1;
+                        const int u = x * 32 + bt;
+                        if (rank >= done && rank < done + kListCap) {
+                            list[rank - done] = u;
+                            const int pos = base + chunk_pre + rank;
+                            a.perm[vo + pos] = vo + u;
+                            a.iperm[vo + u] = vo + pos;
+                        }
+                        ++rank;
+                    }
+                }
+                __syncthreads();
+                const int cntl = min(kListCap, tot_w - done);
+                const int lvl = r + 1;
+                for (int t = tid; t < cntl; t += kBlock) {
+                    const int u = vo + list[t];
+                    for (int e = a.row[u]; e < a.row[u + 1]; ++e) {
+                        const int2 nb = a.wedgeO[e];
+                        const int xs[2] = {nb.x, nb.y};
+                        for (int z = 0; z < 2; ++z) {
+                            const int x = xs[z];
+                            if (ld_c(a.level + x) < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
+                                const int xl = x - vo;
+                                atomicOr(nxt + (xl >> 5), 1u << (xl & 31));
+                                atomicAdd(cn + (xl >> 5) / cw, 1);
+                            }
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
+            for (int x = my0; x < my1; ++x) st_c(cur + x, 0u);
+            base += total;
+            if (!gb.sync(0, &any)) return;
         }
-        for (int x = my0; x < my1; ++x) st_c(cur + x, 0u);
-        base += total;
+        const int rho = r;
+        const int reach = base;
+        if (w == 0 && tid == 0) offs[rho] = reach;
+
+        // unreachable vertices of the mesh follow, in ascending id order
+        const int cv = (n + gs - 1) / gs;
+        const int vb = min(w * cv, n), ve = min(vb + cv, n);
+        const int qv = (ve - vb + kBlock - 1) / kBlock;
+        const int v0 = min(vb + tid * qv, ve), v1 = min(v0 + qv, ve);
+        int pc = 0;
+        for (int v = v0; v < v1; ++v) pc += ld_c(a.level + vo + v) < 0;
+        int tot_w;
+        const int pre = block_exclusive_scan(pc, &tot_w);
+        if (tid == 0) st_c(cntg + 3 * gs + w, tot_w);
         if (!gb.sync(0, &any)) return;
-    }
-    const int rho = r;
-    const int reach = base;
-    if (w == 0 && tid == 0) a.offsets[rho] = reach;
-
-    // unreachable vertices follow, in ascending id order
-    const int cv = (a.n + G - 1) / G;
-    const int vb = min(w * cv, a.n), ve = min(vb + cv, a.n);
-    const int qv = (ve - vb + kBlock - 1) / kBlock;
-    const int v0 = min(vb + tid * qv, ve), v1 = min(v0 + qv, ve);
-    int pc = 0;
-    for (int v = v0; v < v1; ++v) pc += ld_c(a.level + v) < 0;
-    int tot_w;
-    int pre = block_exclusive_scan(pc, &tot_w);
-    if (tid == 0) st_c(a.cnt + 3 * G + w, tot_w);
-    if (!gb.sync(0, &any)) return;
-    int partpre = 0;
-    for (int x = tid; x < w; x += kBlock) partpre += ld_c(a.cnt + 3 * G + x);
-    const int chunk_pre = block_sum(partpre);
-    int pos = reach + chunk_pre + pre;
-    for (int v = v0; v < v1; ++v)
-        if (ld_c(a.level + v) < 0) {
-            a.perm[pos] = v;
-            a.iperm[v] = pos;
-            ++pos;
+        int partpre = 0;
+        for (int x = tid; x < w; x += kBlock) partpre += ld_c(cntg + 3 * gs + x);
+        const int chunk_pre = block_sum(partpre);
+        int pos = reach + chunk_pre + pre;
+        for (int v = v0; v < v1; ++v)
+            if (ld_c(a.level + vo + v) < 0) {
+                a.perm[vo + pos] = vo + v;
+                a.iperm[vo + v] = vo + pos;
+                ++pos;
+            }
+        if (w == 0 && tid == 0) {
+            a.state[b].rho = rho;
+            a.state[b].reach = reach;
         }
-    if (w == 0 && tid == 0) {
-        a.ctrl[C_RHO] = rho;
-        a.ctrl[C_REACH] = reach;
+        if (!gb.sync(0, &any)) return;   // the group's counters are reused by its next mesh
     }
-}
-
-__global__ void k_zero_lines(unsigned* p, long long len) {
-    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < len;
-         x += (long long)gridDim.x * blockDim.x)
-        p[x] = 0u;
 }
 
 // degree of each position, into rowN[p + 1]
-__global__ __launch_bounds__(kBlock) void k_degree_new(const int* perm, const int* rowO, int n,
-                                                       int* rowN, const int* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_degree_new(const int* perm, const int* rowO,
+                                                       long long N, int* rowN, const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < n; p += gsz) {
-        int v = perm[p];
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
+        const int v = perm[p];
         rowN[p + 1] = rowO[v + 1] - rowO[v];
         if (p == 0) rowN[0] = 0;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const int* F, const int* perm,
-                                                    const int* iperm, const int* rowO,
-                                                    const int* corner, const int* rowN, int n,
-                                                    float4* xyz, int2* wedge, const int* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const MeshDesc* mesh, int B,
+                                                    const int* vo, const int* perm, const int* iperm,
+                                                    const int* rowO, const int2* wedgeO,
+                                                    const int* rowN, long long N, float4* xyz,
+                                                    int2* wedge, const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < n; p += gsz) {
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
         const int v = perm[p];
-        xyz[p] = make_float4(V[3ll * v], V[3ll * v + 1], V[3ll * v + 2], 0.f);
-        const int b = rowO[v], e = rowO[v + 1];
+        const int mb = mesh_of(vo, B, v);
+        const float* c = V + 3 * (mesh[mb].v_in + (v - vo[mb]));
+        xyz[p] = make_float4(c[0], c[1], c[2], 0.f);
+        const int r0 = rowO[v], r1 = rowO[v + 1];
         int o = rowN[p];
-        for (int x = b; x < e; ++x, ++o) {
-            const int cx = corner[x];
-            const int tri = cx / 3, c = cx - 3 * tri;
-            wedge[o] = make_int2(iperm[F[3 * tri + other1(c)]], iperm[F[3 * tri + other2(c)]]);
+        for (int x = r0; x < r1; ++x, ++o) {
+            const int2 t = wedgeO[x];
+            wedge[o] = make_int2(iperm[t.x], iperm[t.y]);
         }
     }
 }
@@ -342,31 +394,37 @@ int grid_for(long long work) {
 
 }  // namespace
 
-hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, const int* F,
-                          const int* S, int g_bfs, hipStream_t st) {
+void launch_barrier_reset(const Work& w, int lines, hipStream_t st) {
+    const long long len = (long long)lines * kLine;
+    hipLaunchKernelGGL(k_zero_lines, dim3(grid_for(len)), dim3(kBlock), 0, st, w.bar, len);
+}
+
+hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
+                          const int* S, int g_prep, hipStream_t st) {
+    const long long N = z.N, F3 = 3 * z.F;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, st, w.ctrl, (long long)C_WORDS, 0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, w.rowO, (long long)n + 1, 0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, st, w.cursor, (long long)n, 0);
-    long long vwork = 3ll * (f > n ? f : n);
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(vwork)), dim3(kBlock), 0, st, V, n, F, f, S, m, w.ctrl);
-    hipLaunchKernelGGL(k_count, dim3(grid_for(3ll * f)), dim3(kBlock), 0, st, F, f, w.rowO, w.ctrl);
-    hipError_t e = scan_inplace(w.rowO + 1, n, w.scan_tmp, w.ctrl, st);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(N + 1)), dim3(kBlock), 0, st, w.rowO, N + 1, 0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, w.cursor, N, 0);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(F3 > N ? F3 : N)), dim3(kBlock), 0, st, V, F, S,
+                       w.mesh, z.B, w.vo, w.fo3, w.so, N, F3, z.S, w.state, w.ctrl);
+    hipLaunchKernelGGL(k_count, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B, w.fo3, F3,
+                       w.rowO, w.ctrl);
+    hipError_t e = scan_inplace(w.rowO + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(3ll * f)), dim3(kBlock), 0, st, F, f, w.rowO,
-                       w.cursor, w.faceO, w.ctrl);
+    hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
+                       w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
     BfsArgs a;
-    a.n = n;
-    a.m = m;
-    a.nwords = (n + 31) / 32;
-    a.cw = (a.nwords + g_bfs - 1) / g_bfs;
-    if (a.cw < 1) a.cw = 1;
-    a.F = F;
+    a.G = g_prep;
+    a.mesh = w.mesh;
+    a.state = w.state;
+    a.wg = w.wg_prep;
+    a.glist = w.glist_prep;
     a.S = S;
     a.row = w.rowO;
-    a.corner = w.faceO;
+    a.wedgeO = w.wedgeO;
     a.level = w.level;
     a.perm = w.perm;
     a.iperm = w.iperm;
@@ -375,24 +433,18 @@ hipError_t launch_prepare(const Work& w, int n, int f, int m, const float* V, co
     a.cnt = w.cnt;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
-    launch_barrier_reset(w, g_bfs, st);
+    launch_barrier_reset(w, 2 * g_prep, st);
     void* args[] = {&a};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_bfs), dim3(g_bfs), dim3(kBlock),
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_bfs), dim3(g_prep), dim3(kBlock),
                                    args, 0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_degree_new, dim3(grid_for(n)), dim3(kBlock), 0, st, w.perm, w.rowO, n,
+    hipLaunchKernelGGL(k_degree_new, dim3(grid_for(N)), dim3(kBlock), 0, st, w.perm, w.rowO, N,
                        w.rowN, w.ctrl);
-    e = scan_inplace(w.rowN + 1, n, w.scan_tmp, w.ctrl, st);
+    e = scan_inplace(w.rowN + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reorder, dim3(grid_for(n)), dim3(kBlock), 0, st, V, F, w.perm, w.iperm,
-                       w.rowO, w.faceO, w.rowN, n, w.xyz, w.wedge, w.ctrl);
+    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo,
+                       w.perm, w.iperm, w.rowO, w.wedgeO, w.rowN, N, w.xyz, w.wedge, w.ctrl);
     return hipGetLastError();
-}
-
-void launch_barrier_reset(const Work& w, int g, hipStream_t st) {
-    const long long len = (long long)(g + 1) * kLine;
-    hipLaunchKernelGGL(k_zero_lines, dim3((unsigned)((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                       w.bar, len);
 }
 
 int max_coop_blocks_bfs(int cus) {

@@ -1,13 +1,15 @@
-// The PTP iteration (Sec. 4.2) as one persistent, cooperative kernel:
+// The PTP iteration (Sec. 4.2) as one persistent, cooperative kernel over a
+// batch of meshes; per mesh:
 //   init (d = +inf, d(S) = 0, labels),
 //   for k = 1, 2, ...: Jacobi update of the band B_{i_k}^{j_k} from the
 //     previous map with the planar update (Sec. 3.2) in increment form,
 //     relative-change test of the band's first topleset (Eq. lower_band),
 //     band ends advanced on the device (Eq. upper_band / lower_band),
 //   unpermute of distances and labels to the caller's order.
-// One grid barrier per iteration; the controller state (i, j, k) is kept in
-// registers, identical in every workgroup, and the only cross-workgroup datum
-// per iteration is the "not converged" word of the tested topleset.
+// One group barrier per iteration; the controller state (i, j, k) is kept in
+// registers, identical in every workgroup of the group, and the only datum
+// exchanged per iteration besides the distances is the "not converged" vote,
+// carried by the barrier.
 #include "ptp_device.h"
 #include "ptp_kernels.h"
 
@@ -89,8 +91,13 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
 }
 
 struct RelaxArgs {
-    int n, m, rho, kmax, window;
+    int G;                 // workgroups of the launch
+    int kmax_fixed, window;
     float tol;
+    const MeshDesc* mesh;
+    MeshState* state;
+    const WgInfo* wg;
+    const int* glist;      // per group: starts [ngroups + 1], then mesh ids
     const int* S;
     const int* perm;
     const int* iperm;
@@ -98,186 +105,200 @@ struct RelaxArgs {
     const int* row;
     const int2* wedge;
     const float4* xyz;
-    float* dist;
-    int* lab;
+    float* dist;           // [2N]
+    int* lab;              // [2N]
     int* retire;
     int* ctrl;
     unsigned* bar;
+    long long N;
     float* out_d;
     int* out_l;
 };
 
 constexpr int kChunk = 6;   // wedges gathered together per vertex (mean degree 6)
 
-// One persistent workgroup grid runs the whole iteration.  Per iteration k
-// every thread takes band vertices in a grid-stride loop; for each vertex it
-// first gathers up to kChunk wedges, then every neighbour distance and
-// coordinate of those wedges at once (independent loads), then evaluates the
-// planar updates.  Distances and labels are exchanged between workgroups
-// through coherent loads and stores only.
+// Groups of consecutive workgroups run the whole iteration of one mesh at a
+// time, with a barrier of their own.  Per iteration k every thread of the
+// group takes band vertices in a strided loop; position p of the mesh is
+// always handled by group thread p mod (gsize * 256), whatever the band, so a
+// vertex stays on one CU across iterations and its incidence and coordinates
+// stay in that CU's caches.  For each vertex it first gathers up to kChunk
+// wedges, then every neighbour distance and coordinate of those wedges at
+// once (independent loads), then evaluates the planar updates.  Distances and
+// labels are exchanged between workgroups through coherent loads and stores.
 template <bool LABELS>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
-    const int G = gridDim.x;
-    FlagBarrier gb{a.bar, a.bar + (size_t)G * kLine, a.ctrl + C_ABORT, 0};
+    const WgInfo me = a.wg[blockIdx.x];
+    const int gs = me.gsize;
+    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
+                   a.ctrl + C_ABORT, (unsigned)gs, (unsigned)me.rank, 0};
     unsigned any = 0;
-    const long long gsz = (long long)G * kBlock;
-    const long long g0 = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
-    const int n = a.n;
+    const long long gsz = (long long)gs * kBlock;
+    const long long g0 = (long long)me.rank * kBlock + threadIdx.x;
+    const bool leader = me.rank == 0 && threadIdx.x == 0;
     float* dA = a.dist;
-    float* dB = a.dist + n;
+    float* dB = a.dist + a.N;
     int* lA = a.lab;
-    int* lB = a.lab + n;
-    const int m0 = a.offsets[1];  // |V_0|: the sources occupy positions [0, m0)
+    int* lB = a.lab + a.N;
 
-    for (long long v = g0; v < n; v += gsz) {
-        const float d = v < m0 ? 0.f : kInf;
-        st_c(dA + v, d);
-        st_c(dB + v, d);
-        if (LABELS && v >= m0) {
-            st_c(lA + v, -1);
-            st_c(lB + v, -1);
-        }
-    }
-    if (LABELS)
-        for (long long s = g0; s < a.m; s += gsz) {
-            const int p = a.iperm[a.S[s]];
-            st_c(lA + p, (int)s);
-            st_c(lB + p, (int)s);
-        }
-    for (long long r = g0; r < a.rho; r += gsz) a.retire[r] = r == 0 ? 0 : -1;
-    if (!gb.sync(0, &any)) return;
+    const int* lst = a.glist + a.glist[me.group];
+    const int nlst = a.glist[me.group + 1] - a.glist[me.group];
+    for (int li = 0; li < nlst; ++li) {
+        const int b = lst[li];
+        const MeshDesc md = a.mesh[b];
+        const int n = md.n, vo = md.v_off;
+        const int rho = a.state[b].rho;
+        const int* offs = a.offsets + vo + b;    // topleset starts, local positions
+        int* retire = a.retire + vo;
+        const int kmax = a.kmax_fixed > 0 ? a.kmax_fixed : 4 * rho + 16;
+        const int m0 = offs[1];                  // |V_0|: the sources occupy [0, m0)
 
-    int i = 1, lo_prev = 1, k = 0, runstat = 0;
-    long long upd = 0;
-    while (i < a.rho) {
-        if (k >= a.kmax) {
-            runstat = 1;
-            break;
-        }
-        ++k;
-        const int j = min(k, a.rho - 1);                       // Eq. upper_band
-        int lo = i;
-        if (a.window > 0) lo = max(lo, j - a.window + 1);
-        const float* dold = (k & 1) ? dA : dB;
-        float* dnew = (k & 1) ? dB : dA;
-        const int* lold = (k & 1) ? lA : lB;
-        int* lnew = (k & 1) ? lB : lA;
-        const int cb = a.offsets[lo_prev];   // retired since last iteration: copy
-        const int bb = a.offsets[lo];        // band
-        const int be = a.offsets[j + 1];
-        const int tb = a.offsets[lo + 1];    // tested topleset V_lo = [bb, tb)
-        unsigned notconv = 0;
-        // Anchored mapping: position v is always handled by thread v mod gsz,
-        // whatever the band, so a vertex stays on one CU across iterations and
-        // its incidence and coordinates stay in that CU's caches.
-        const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
-        for (long long vv = first; vv < be; vv += gsz) {
-            const int v = (int)vv;
-            if (v < bb) {
-                st_c(dnew + v, ld_c(dold + v));
-                if (LABELS) st_c(lnew + v, ld_c(lold + v));
-                continue;
+        for (long long p = g0; p < n; p += gsz) {
+            const float d = p < m0 ? 0.f : kInf;
+            st_c(dA + vo + p, d);
+            st_c(dB + vo + p, d);
+            if (LABELS && p >= m0) {
+                st_c(lA + vo + p, -1);
+                st_c(lB + vo + p, -1);
             }
-            const float4 x0 = a.xyz[v];
-            const float dv = ld_c(dold + v);
-            float best = kInf;
-            int bl = 0x7fffffff;
-            const int e0 = a.row[v], e1 = a.row[v + 1];
-            for (int base = e0; base < e1; base += kChunk) {
-                const int cnt = min(kChunk, e1 - base);
-                int2 wv[kChunk];
-                float da[kChunk], db[kChunk];
-                float4 xa[kChunk], xb[kChunk];
-                int la[kChunk], lb[kChunk];
-#pragma unroll
-                for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
-#pragma unroll
-                for (int q = 0; q < kChunk; ++q) {
-                    da[q] = ld_c(dold + wv[q].x);
-                    db[q] = ld_c(dold + wv[q].y);
-                    xa[q] = a.xyz[wv[q].x];
-                    xb[q] = a.xyz[wv[q].y];
-                    if (LABELS) {
-                        la[q] = ld_c(lold + wv[q].x);
-                        lb[q] = ld_c(lold + wv[q].y);
-                    }
+        }
+        if (LABELS)
+            for (long long s = g0; s < md.m; s += gsz) {
+                const int p = a.iperm[vo + a.S[md.s_in + s]];
+                st_c(lA + p, (int)s);
+                st_c(lB + p, (int)s);
+            }
+        for (long long r = g0; r < rho; r += gsz) retire[r] = r == 0 ? 0 : -1;
+        if (!gb.sync(0, &any)) return;
+
+        int i = 1, lo_prev = 1, k = 0, runstat = 0;
+        long long upd = 0;
+        while (i < rho) {
+            if (k >= kmax) {
+                runstat = 1;
+                break;
+            }
+            ++k;
+            const int j = min(k, rho - 1);                       // Eq. upper_band
+            int lo = i;
+            if (a.window > 0) lo = max(lo, j - a.window + 1);
+            const float* dold = (k & 1) ? dA : dB;
+            float* dnew = (k & 1) ? dB : dA;
+            const int* lold = (k & 1) ? lA : lB;
+            int* lnew = (k & 1) ? lB : lA;
+            const int cb = offs[lo_prev];   // retired since last iteration: copy
+            const int bb = offs[lo];        // band
+            const int be = offs[j + 1];
+            const int tb = offs[lo + 1];    // tested topleset V_lo = [bb, tb)
+            unsigned notconv = 0;
+            const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
+            for (long long pp = first; pp < be; pp += gsz) {
+                const int v = vo + (int)pp;
+                if (pp < bb) {
+                    st_c(dnew + v, ld_c(dold + v));
+                    if (LABELS) st_c(lnew + v, ld_c(lold + v));
+                    continue;
                 }
+                const float4 x0 = a.xyz[v];
+                const float dv = ld_c(dold + v);
+                float best = kInf;
+                int bl = 0x7fffffff;
+                const int e0 = a.row[v], e1 = a.row[v + 1];
+                for (int base = e0; base < e1; base += kChunk) {
+                    const int cnt = min(kChunk, e1 - base);
+                    int2 wv[kChunk];
+                    float da[kChunk], db[kChunk];
+                    float4 xa[kChunk], xb[kChunk];
+                    int la[kChunk], lb[kChunk];
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) {
-                    if (q < cnt && fminf(da[q], db[q]) < kInf) {
-                        int l = 0;
-                        const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q],
-                                                             LABELS ? la[q] : 0, LABELS ? lb[q] : 0, l);
-                        if (u < best || (LABELS && u == best && l < bl)) {
-                            best = u;
-                            bl = l;
+                    for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
+#pragma unroll
+                    for (int q = 0; q < kChunk; ++q) {
+                        da[q] = ld_c(dold + wv[q].x);
+                        db[q] = ld_c(dold + wv[q].y);
+                        xa[q] = a.xyz[wv[q].x];
+                        xb[q] = a.xyz[wv[q].y];
+                        if (LABELS) {
+                            la[q] = ld_c(lold + wv[q].x);
+                            lb[q] = ld_c(lold + wv[q].y);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < kChunk; ++q) {
+                        if (q < cnt && fminf(da[q], db[q]) < kInf) {
+                            int l = 0;
+                            const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q],
+                                                                 LABELS ? la[q] : 0, LABELS ? lb[q] : 0, l);
+                            if (u < best || (LABELS && u == best && l < bl)) {
+                                best = u;
+                                bl = l;
+                            }
                         }
                     }
                 }
+                float dn = dv;
+                if (best < dv) {
+                    dn = best;
+                    if (LABELS) st_c(lnew + v, bl);
+                } else if (LABELS) {
+                    st_c(lnew + v, ld_c(lold + v));
+                }
+                st_c(dnew + v, dn);
+                if (pp < tb) {
+                    const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
+                    notconv |= conv ? 0u : 1u;
+                }
             }
-            float dn = dv;
-            if (best < dv) {
-                dn = best;
-                if (LABELS) st_c(lnew + v, bl);
-            } else if (LABELS) {
-                st_c(lnew + v, ld_c(lold + v));
+            upd += be - bb;
+            if (!gb.sync(notconv, &any)) return;
+            if (leader)
+                for (int r = i; r < lo; ++r) retire[r] = k - 1;      // pushed out by the window
+            if (!any) {                                              // Eq. lower_band
+                if (leader) retire[lo] = k;
+                i = lo + 1;
+            } else {
+                i = lo;
             }
-            st_c(dnew + v, dn);
-            if (v < tb) {
-                const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
-                notconv |= conv ? 0u : 1u;
-            }
+            lo_prev = lo;
         }
-        upd += be - bb;
-        if (!gb.sync(notconv, &any)) return;
-        if (leader)
-            for (int r = i; r < lo; ++r) a.retire[r] = k - 1;    // pushed out by the window
-        if (!any) {                                              // Eq. lower_band
-            if (leader) a.retire[lo] = k;
-            i = lo + 1;
-        } else {
-            i = lo;
+        const float* dfin = (k & 1) ? dB : dA;
+        const int* lfin = (k & 1) ? lB : lA;
+        for (long long p = g0; p < n; p += gsz) {
+            const int v = a.perm[vo + p];
+            a.out_d[md.out_off + (v - vo)] = ld_c(dfin + vo + p);
+            if (LABELS) a.out_l[md.out_off + (v - vo)] = ld_c(lfin + vo + p);
         }
-        lo_prev = lo;
-    }
-    const float* dfin = (k & 1) ? dB : dA;
-    const int* lfin = (k & 1) ? lB : lA;
-    for (long long p = g0; p < n; p += gsz) {
-        const int v = a.perm[p];
-        a.out_d[v] = ld_c(dfin + p);
-        if (LABELS) a.out_l[v] = ld_c(lfin + p);
-    }
-    if (leader) {
-        a.ctrl[C_ITERS] = k;
-        a.ctrl[C_RUNSTAT] = runstat;
-        a.ctrl[C_UPD_LO] = (int)(upd & 0xffffffffll);
-        a.ctrl[C_UPD_HI] = (int)(upd >> 32);
+        if (leader) {
+            a.state[b].iters = k;
+            a.state[b].runstat = runstat;
+            a.state[b].updates = upd;
+        }
     }
 }
 
-__global__ void k_run_reset(int* ctrl) {
-    if (threadIdx.x == 0) {
-        ctrl[C_ITERS] = 0;
-        ctrl[C_RUNSTAT] = 0;
-        ctrl[C_UPD_LO] = 0;
-        ctrl[C_UPD_HI] = 0;
-        ctrl[C_ABORT] = 0;
+__global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[C_ABORT] = 0;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        state[b].iters = 0;
+        state[b].runstat = 0;
+        state[b].updates = 0;
     }
 }
 
 }  // namespace
 
 hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st) {
-    hipLaunchKernelGGL(k_run_reset, dim3(1), dim3(64), 0, st, w.ctrl);
-    launch_barrier_reset(w, g_run, st);
+    hipLaunchKernelGGL(k_run_reset, dim3((p.B + 255) / 256), dim3(256), 0, st, w.ctrl, w.state, p.B);
+    launch_barrier_reset(w, 2 * g_run, st);
     RelaxArgs a;
-    a.n = p.n;
-    a.m = p.m;
-    a.rho = p.rho;
-    a.kmax = p.kmax;
+    a.G = g_run;
+    a.kmax_fixed = p.kmax_fixed;
     a.window = p.window;
     a.tol = p.tol;
+    a.mesh = w.mesh;
+    a.state = w.state;
+    a.wg = w.wg_run;
+    a.glist = w.glist_run;
     a.S = p.S;
     a.perm = w.perm;
     a.iperm = w.iperm;
@@ -290,6 +311,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run,
     a.retire = w.retire;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
+    a.N = p.N;
     a.out_d = p.out_d;
     a.out_l = p.out_l;
     void* args[] = {&a};

@@ -27,7 +27,10 @@ _NAMES = {0: "PTP_OK", -1: "PTP_EINVAL", -2: "PTP_ENOMEM", -3: "PTP_EDEVICE",
 # every symbol include/ptp.h declares
 EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "ptp_solve",
            "ptp_get_stats", "ptp_get_order", "ptp_get_schedule", "ptp_n_toplesets",
-           "ptp_last_error", "ptp_plan_destroy", "ptp_version")
+           "ptp_last_error", "ptp_plan_destroy", "ptp_version",
+           "ptp_batch_create", "ptp_batch_workspace_bytes", "ptp_batch_prepare", "ptp_batch_run",
+           "ptp_batch_get_stats", "ptp_batch_set_schedule", "ptp_batch_get_schedule",
+           "ptp_batch_autotune", "ptp_batch_last_error", "ptp_batch_destroy")
 
 
 class PTPError(RuntimeError):
@@ -45,6 +48,24 @@ class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_toplesets", C.c_int32),
                 ("reachable", C.c_int32), ("workgroups", C.c_int32),
                 ("vertex_updates", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class MeshDesc(C.Structure):
+    """One mesh of a batch: where its rows start in the concatenated V, F, S
+    and in the outputs (ptp_mesh)."""
+    _fields_ = [("v_off", C.c_int64), ("f_off", C.c_int64), ("s_off", C.c_int64),
+                ("out_off", C.c_int64), ("n_vertices", C.c_int32), ("n_faces", C.c_int32),
+                ("n_sources", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Schedule(C.Structure):
+    """Work distribution of a batch (ptp_schedule); 0 fields = defaults."""
+    _fields_ = [("workgroups", C.c_int32), ("small_limit", C.c_int32),
+                ("large_limit", C.c_int32), ("medium_group", C.c_int32),
+                ("large_group", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -87,6 +108,28 @@ def load() -> C.CDLL:
     lib.ptp_plan_destroy.restype = None
     lib.ptp_version.argtypes = []
     lib.ptp_version.restype = C.c_char_p
+    lib.ptp_batch_create.argtypes = [C.POINTER(vp), C.POINTER(MeshDesc), C.c_int32,
+                                     C.POINTER(Options)]
+    lib.ptp_batch_create.restype = C.c_int
+    lib.ptp_batch_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.ptp_batch_workspace_bytes.restype = C.c_int
+    lib.ptp_batch_prepare.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.ptp_batch_prepare.restype = C.c_int
+    lib.ptp_batch_run.argtypes = [vp, vp, vp, vp]
+    lib.ptp_batch_run.restype = C.c_int
+    lib.ptp_batch_get_stats.argtypes = [vp, vp, vp]
+    lib.ptp_batch_get_stats.restype = C.c_int
+    lib.ptp_batch_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
+    lib.ptp_batch_set_schedule.restype = C.c_int
+    lib.ptp_batch_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
+    lib.ptp_batch_get_schedule.restype = C.c_int
+    lib.ptp_batch_autotune.argtypes = [vp, C.POINTER(Schedule), C.c_int32, vp, vp, vp,
+                                       C.POINTER(C.c_int32), vp]
+    lib.ptp_batch_autotune.restype = C.c_int
+    lib.ptp_batch_last_error.argtypes = [vp]
+    lib.ptp_batch_last_error.restype = C.c_char_p
+    lib.ptp_batch_destroy.argtypes = [vp]
+    lib.ptp_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -239,3 +282,138 @@ def solve(V, F, S, tol: float, labels: bool = False, max_iters: int = 0, window:
     plan.run(dist, lab, stream=stream)
     st = plan.stats()
     return Solution(dist, lab, st, plan)
+
+
+# ---------------------------------------------------------------- batches ---
+
+def concat(meshes, share=None):
+    """Concatenate meshes (objects with V, F, S numpy arrays) into one V, F, S
+    and a list of MeshDesc.  `share` (optional list) gives, per mesh, the index
+    of an earlier mesh whose V and F rows it reuses (many source sets on one
+    mesh); outputs never overlap."""
+    Vs, Fs, Ss, descs = [], [], [], []
+    v_off = f_off = s_off = out_off = 0
+    rows = {}
+    for i, m in enumerate(meshes):
+        src = share[i] if share is not None and share[i] is not None else None
+        if src is not None:
+            vo, fo = rows[src]
+        else:
+            vo, fo = v_off, f_off
+            Vs.append(np.asarray(m.V, np.float32))
+            Fs.append(np.asarray(m.F, np.int32).reshape(-1, 3))
+            v_off += m.V.shape[0]
+            f_off += Fs[-1].shape[0]
+        rows[i] = (vo, fo)
+        Ss.append(np.asarray(m.S, np.int32))
+        descs.append(MeshDesc(vo, fo, s_off, out_off, m.V.shape[0], np.asarray(m.F).shape[0],
+                              len(m.S), 0))
+        s_off += len(m.S)
+        out_off += m.V.shape[0]
+    V = np.ascontiguousarray(np.concatenate(Vs, axis=0))
+    F = np.ascontiguousarray(np.concatenate(Fs, axis=0)) if Fs else np.zeros((0, 3), np.int32)
+    S = np.ascontiguousarray(np.concatenate(Ss))
+    return V, F, S, descs, out_off
+
+
+class Batch:
+    """Many meshes solved in one persistent launch (ptp_batch_*).  Every mesh
+    gets exactly the result a Plan would give it alone."""
+
+    def __init__(self, descs, tol: float, max_iters: int = 0, window: int = 0,
+                 want_labels: bool = False):
+        lib = load()
+        self._lib = lib
+        self.count = len(descs)
+        self._descs = (MeshDesc * self.count)(*descs)
+        self.out_len = max(int(d.out_off) + int(d.n_vertices) for d in descs)
+        self.want_labels = bool(want_labels)
+        opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)), 0)
+        h = C.c_void_p()
+        rc = lib.ptp_batch_create(C.byref(h), self._descs, self.count, C.byref(opt))
+        if rc != PTP_OK:
+            raise PTPError(rc, "ptp_batch_create")
+        self._h = h
+        self._work = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ptp_batch_destroy(h)
+            self._h = None
+
+    def _err(self, rc, what):
+        msg = self._lib.ptp_batch_last_error(self._h)
+        return PTPError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t(0)
+        rc = self._lib.ptp_batch_workspace_bytes(self._h, C.byref(b))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, device=None):
+        import torch
+        need = self.workspace_bytes()
+        if self._work is None or self._work.numel() < need + 256:
+            self._work = torch.empty(need + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-self._work.data_ptr()) % 256
+        return self._work[off:off + need]
+
+    def prepare(self, V, F, S, work=None, stream=None):
+        import torch
+        _check_dev(V, torch.float32, (3,), "V")
+        _check_dev(F, torch.int32, (3,), "F")
+        _check_dev(S, torch.int32, None, "S")
+        if work is None:
+            work = self.workspace(V.device)
+        rc = self._lib.ptp_batch_prepare(self._h, _ptr(V), _ptr(F), _ptr(S), _ptr(work),
+                                         work.numel(), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_prepare")
+        self._keep = (V, F, S, work)
+
+    def run(self, dist, label=None, stream=None):
+        import torch
+        _check_dev(dist, torch.float32, None, "dist")
+        if dist.numel() < self.out_len:
+            raise ValueError("dist too short for the batch outputs")
+        if label is not None:
+            _check_dev(label, torch.int32, None, "label")
+        rc = self._lib.ptp_batch_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_run")
+
+    def stats(self):
+        """(aggregate status, [per-mesh stats dict], [per-mesh status])"""
+        st = (Stats * self.count)()
+        status = (C.c_int32 * self.count)()
+        rc = self._lib.ptp_batch_get_stats(self._h, st, status)
+        return rc, [s.as_dict() for s in st], [int(x) for x in status]
+
+    def set_schedule(self, **kw):
+        sch = Schedule(**{k: int(v) for k, v in kw.items()})
+        rc = self._lib.ptp_batch_set_schedule(self._h, C.byref(sch))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_set_schedule")
+
+    def get_schedule(self) -> dict:
+        sch = Schedule()
+        rc = self._lib.ptp_batch_get_schedule(self._h, C.byref(sch))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_get_schedule")
+        return sch.as_dict()
+
+    def autotune(self, candidates, dist, label=None, stream=None):
+        """Time each candidate schedule (dicts of Schedule fields) on the
+        prepared batch, keep the fastest.  Returns (best index, ms list)."""
+        n = len(candidates)
+        arr = (Schedule * n)(*[Schedule(**{k: int(v) for k, v in c.items()}) for c in candidates])
+        ms = (C.c_float * n)()
+        best = C.c_int32(-1)
+        rc = self._lib.ptp_batch_autotune(self._h, arr, n, _ptr(dist), _ptr(label), ms,
+                                          C.byref(best), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_autotune")
+        return int(best.value), [float(x) for x in ms]
