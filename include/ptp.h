@@ -70,6 +70,8 @@ typedef struct {
     int32_t workgroups;     /* persistent grid size used                        */
     int64_t vertex_updates; /* U = sum over k of |B_{i_k}^{j_k}|  (Eq.
                                n_operations without the constant)             */
+    int32_t certify_rounds; /* warm start: certification sweeps (0 otherwise)  */
+    int32_t certify_rejected; /* warm start: bounds the certification withdrew */
 } ptp_stats;
 
 typedef struct ptp_plan ptp_plan;
@@ -99,8 +101,8 @@ ptp_status ptp_prepare(ptp_plan *plan, const float *dV, const int32_t *dF,
 /* Run the PTP iteration on a prepared plan and write dist (and label when
  * dLabel is non-NULL and the plan wants labels) in the caller's vertex
  * order.  Enqueues work only: no host synchronisation, no allocation.  The
- * outcome (PTP_OK / PTP_ENOCONV / device fault) is read by ptp_get_stats or
- * ptp_run_status after the stream has drained. */
+ * outcome (PTP_OK / PTP_ENOCONV / device fault) is read by ptp_get_stats
+ * after the stream has drained. */
 ptp_status ptp_run(ptp_plan *plan, float *dDist, int32_t *dLabel, void *stream);
 
 /* ptp_prepare + ptp_run + synchronise; fills *stats when non-NULL.  Returns
@@ -202,6 +204,94 @@ ptp_status ptp_batch_autotune(ptp_batch *batch, const ptp_schedule *candidates, 
 
 const char *ptp_batch_last_error(const ptp_batch *batch);
 void ptp_batch_destroy(ptp_batch *batch);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension; the paper starts every vertex but the
+ * sources at +inf).  A small network predicts each vertex's distance from
+ * local geometry and its BFS hop count; the prediction, inflated, is
+ * certified into an upper bound and the PTP iteration starts from it.  The
+ * min-relaxation of Sec. 4.2 descends from any upper bound of the fixed point
+ * to that fixed point, and the band and retirement rules (Eq. upper_band,
+ * Eq. lower_band) stay as in the plain run with one addition: V_r retires no
+ * earlier than iteration r + 1.  Labels are not computed on this path.
+ *
+ * Certification: every vertex whose bound w(v) is below the planar update
+ * U(w)(v) from its neighbours' bounds (Sec. 3.2 update_step) loses its bound
+ * (+inf), repeated until nothing changes; the result satisfies w >= U(w) with
+ * w = 0 on S, a supersolution, hence w >= the fixed point.  Any input is
+ * therefore safe: a bad prediction costs time, never accuracy.
+ *
+ * Network (one float32 parameter vector of PTP_MLP_PARAMS values):
+ *   x  = (f1 / l, hop, f3 * l) / (64, 64, 1)
+ *        l   = mean edge length of the mesh (each triangle's three edges)
+ *        f1  = Euclidean distance to the nearest source
+ *        hop = topleset index r of the vertex (Sec. 4.1)
+ *        f3  = signed discrete mean curvature: H = |K| / 2 with the sign of
+ *              K . n, K the cotangent Laplacian of the position over the
+ *              barycentric area (a third of the incident triangle areas),
+ *              n the sum of the incident (unnormalised) face normals
+ *   h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), o = h2 . W3 + b3
+ *   d^ = 64 l softplus(o)                      gelu with the exact erf
+ *   layout [W1 3x64 | b1 64 | W2 64x64 | b2 64 | W3 64 | b3 1], matrices
+ *   input-major (W[i][j] at i * cols + j).  The weight matrices are rounded
+ *   to bfloat16 (nearest even) where used; layer 2 runs on the matrix cores
+ *   with bfloat16 inputs (h1 rounded) and float32 accumulation; the rest is
+ *   float32.
+ * ---------------------------------------------------------------------- */
+#define PTP_MLP_PARAMS 4481
+
+/* Network inputs of a prepared plan in the caller's vertex order: X[n][3]
+ * and scale[n] = l (-1 for unreachable vertices).  Asynchronous. */
+ptp_status ptp_warm_features(ptp_plan *plan, float *dX, float *dScale, void *stream);
+
+/* Predicted upper bound in the caller's order: upper[v] = inflate * d^(v),
+ * 0 at the sources, +inf where unreachable.  inflate >= 1 (1.05 by design).
+ * dParams is a device vector [PTP_MLP_PARAMS].  Asynchronous. */
+ptp_status ptp_warm_predict(ptp_plan *plan, const float *dParams, float inflate, float *dUpper,
+                            void *stream);
+
+/* Certify dUpper[n] (caller order; negative or NaN entries mean no bound) and
+ * run PTP from it; writes dist like ptp_run.  dUpper is read before dist is
+ * written, so it may be the same buffer.  PTP_EUNSUPPORTED when the plan
+ * wants labels.  Enqueues work only; ptp_get_stats reports the outcome and
+ * the certification counts. */
+ptp_status ptp_run_warm(ptp_plan *plan, const float *dUpper, float *dDist, void *stream);
+
+/* The same three on a batch; arrays are indexed by out_off + local id. */
+ptp_status ptp_batch_warm_features(ptp_batch *batch, float *dX, float *dScale, void *stream);
+ptp_status ptp_batch_warm_predict(ptp_batch *batch, const float *dParams, float inflate,
+                                  float *dUpper, void *stream);
+ptp_status ptp_batch_run_warm(ptp_batch *batch, const float *dUpper, float *dDist, void *stream);
+
+/* Number of network parameters (PTP_MLP_PARAMS). */
+int32_t ptp_mlp_params(void);
+
+/* out[i] = 64 * scale[i] * softplus(o(X[i])) for n rows X[n][3].  n = 0 is a
+ * no-op.  Asynchronous. */
+ptp_status ptp_mlp_apply(const float *dParams, const float *dX, const float *dScale, int64_t n,
+                         float *dOut, void *stream);
+
+/* Device scratch ptp_mlp_grad needs, in bytes. */
+size_t ptp_mlp_scratch_bytes(void);
+
+/* Training loss and its gradient over n >= 1 rows:
+ *   L = (1/n) sum_i ((d^_i - target_i) / max(target_i, scale_i))^2
+ * grad[PTP_MLP_PARAMS] = dL/dparams (with the bfloat16 rounding of the
+ * weights taken as the identity), loss[1] = L (dLoss may be NULL).  The
+ * result does not depend on scheduling (fixed reduction order).  dScratch:
+ * caller device buffer of ptp_mlp_scratch_bytes(), 16-byte aligned;
+ * PTP_ENOMEM if smaller.  Asynchronous. */
+ptp_status ptp_mlp_grad(const float *dParams, const float *dX, const float *dScale,
+                        const float *dTarget, int64_t n, void *dScratch, size_t scratch_bytes,
+                        float *dGrad, float *dLoss, void *stream);
+
+/* One Adam step (bias-corrected, step t >= 1) on the float32 parameters:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * dM, dV [PTP_MLP_PARAMS] are the caller's moment buffers (zero at t = 1).
+ * Asynchronous. */
+ptp_status ptp_adam_step(float *dParams, const float *dGrad, float *dM, float *dV, int32_t t,
+                         float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Library version string. */
 const char *ptp_version(void);

@@ -91,6 +91,8 @@ def _declare(lib):
     lib.ptpo_local_update.restype = C.c_double
     lib.ptpo_run.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
                              dptr, iptr, C.POINTER(_Stats), iptr, iptr, dptr, C.c_int]
+    lib.ptpo_run_warm.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
+                                  dptr, dptr, C.POINTER(_Stats), iptr, C.POINTER(C.c_int), dptr]
     lib.ptpo_fixed_point.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.c_int,
                                      dptr, iptr, C.POINTER(C.c_int)]
     lib.ptpo_fast_marching.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, dptr]
@@ -166,6 +168,41 @@ def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, advance_all=False,
     K = st.iterations
     return Result(dist, label, rc, K, st.rho, st.reachable, int(st.updates),
                   retire[: st.rho].copy(), tlo[: K + 1].copy(), tmr[: K + 1].copy())
+
+
+@dataclass
+class WarmResult:
+    dist: np.ndarray
+    status: int
+    iterations: int
+    rho: int
+    reachable: int
+    updates: int
+    retire_k: np.ndarray
+    rejected: int
+    certified: np.ndarray
+
+
+def run_warm(V, F, S, tol, upper, max_iters=0, window=0, lib=None) -> WarmResult:
+    """PTP started from the upper bound `upper[n]` (caller order) after
+    certifying it; `rejected` counts the bounds the certification withdrew."""
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    w = np.ascontiguousarray(upper, dtype=np.float64)
+    if w.shape != (n,):
+        raise ValueError("upper must have n entries")
+    dist = np.empty(n, np.float64)
+    cert = np.empty(n, np.float64)
+    retire = np.empty(n, np.int32)
+    st = _Stats()
+    rej = C.c_int(0)
+    opts = _Opts(float(tol), int(max_iters), 0, int(window), 0)
+    rc = _L(lib).ptpo_run_warm(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), w, dist,
+                               C.byref(st), retire, C.byref(rej), cert)
+    if rc not in (OK, ENOCONV):
+        raise ValueError(f"ptpo_run_warm failed: {rc}")
+    return WarmResult(dist, rc, st.iterations, st.rho, st.reachable, int(st.updates),
+                      retire[: st.rho].copy(), rej.value, cert)
 
 
 def fixed_point(V, F, S, max_sweeps=100000, lib=None):

@@ -19,6 +19,9 @@
  *                       B_{i_k}^{j_k} (Sec. 4.2), band ends from Eq. upper_band
  *                       and Eq. lower_band; optionally the fixed half band of
  *                       the complexity analysis (Sec. 6).
+ *   ptpo_run_warm       the same iteration started from a caller's upper
+ *                       bound instead of +inf, after certifying it (an
+ *                       extension of the method, not in the paper).
  *   ptpo_fixed_point    plain Jacobi over all vertices until nothing changes:
  *                       the fixed point d* that PTP approximates.
  *   ptpo_fast_marching  sequential Fast Marching (Sec. 3.2) with the same
@@ -315,9 +318,10 @@ typedef struct {
  * Returns PTPO_OK, PTPO_ENOCONV (cap reached; results so far written) or an
  * error.
  */
-int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
-             const ptpo_options *opt, double *dist, int *label, ptpo_stats *st,
-             int *retire_k, int *trace_lo, double *trace_maxrel, int trace_len)
+static int run_core(int n, int nf, const double *X, const int *F, int m, const int *S,
+                    const ptpo_options *opt, const double *upper, double *dist, int *label,
+                    ptpo_stats *st, int *retire_k, int *trace_lo, double *trace_maxrel,
+                    int trace_len, int *rejected_out, double *certified_out)
 {
     int rc = check_mesh(n, nf, F, m, S);
     if (rc) return rc;
@@ -347,6 +351,35 @@ int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
     for (int a = 0; a < m; ++a) {
         dold[S[a]] = 0.0;
         lold[S[a]] = a;
+    }
+    if (upper) {
+        /* Warm start.  Every reachable non-source vertex starts from the
+         * caller's bound (negative or NaN: no bound).  Certification: a vertex
+         * whose bound is below the best planar update from its neighbours'
+         * bounds, w(v) < U(w)(v), loses it (+inf); repeated until nothing
+         * changes.  Withdrawing a bound can only raise U elsewhere, so the set
+         * withdrawn does not depend on the sweep order.  What remains obeys
+         * w >= U(w) with w = 0 on S. */
+        for (int v = 0; v < n; ++v)
+            if (level[v] > 0) dold[v] = upper[v] >= 0.0 ? upper[v] : INFINITY;
+        int rejected = 0, changed = 1;
+        while (changed) {
+            changed = 0;
+            for (int q = 0; q < n; ++q) {
+                int v = order[q];
+                if (level[v] <= 0 || !isfinite(dold[v])) continue;
+                double bu;
+                int bl;
+                best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+                if (dold[v] < bu) {
+                    dold[v] = INFINITY;
+                    rejected++;
+                    changed = 1;
+                }
+            }
+        }
+        if (rejected_out) *rejected_out = rejected;
+        if (certified_out) memcpy(certified_out, dold, sizeof(double) * (size_t)n);
     }
     if (retire_k) {
         for (int r = 0; r < n; ++r) retire_k[r] = -1;
@@ -402,10 +435,13 @@ int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
                 for (int r = i; r < inew && r < rho; ++r) retire_k[r] = k;
         } else {
             /* Eq. lower_band: V_lo retires when every value in it was finite
-             * and changed by a relative amount below tol */
+             * and changed by a relative amount below tol, and not before its
+             * second update (k > lo).  From +inf a value is first finite after
+             * the iteration that reached its topleset, so the second condition
+             * only binds for a warm start. */
             inew = lo;
             for (;;) {
-                if (inew >= rho || inew > j) break;
+                if (inew >= rho || inew > j || k <= inew) break;
                 double worst = 0.0;
                 int ok = 1;
                 for (int q = offsets[inew]; q < offsets[inew + 1]; ++q) {
@@ -454,6 +490,26 @@ out:
     free(dold); free(dnew); free(lold); free(lnew);
     free_incidence(&inc);
     return rc;
+}
+
+int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
+             const ptpo_options *opt, double *dist, int *label, ptpo_stats *st,
+             int *retire_k, int *trace_lo, double *trace_maxrel, int trace_len)
+{
+    return run_core(n, nf, X, F, m, S, opt, NULL, dist, label, st, retire_k, trace_lo,
+                    trace_maxrel, trace_len, NULL, NULL);
+}
+
+/* upper[n]: the warm start in the caller's vertex order.  rejected_out (may
+ * be NULL): number of bounds the certification withdrew; certified[n] (may be
+ * NULL): the certified start, caller order. */
+int ptpo_run_warm(int n, int nf, const double *X, const int *F, int m, const int *S,
+                  const ptpo_options *opt, const double *upper, double *dist, ptpo_stats *st,
+                  int *retire_k, int *rejected_out, double *certified)
+{
+    if (!upper) return PTPO_EINVAL;
+    return run_core(n, nf, X, F, m, S, opt, upper, dist, NULL, st, retire_k, NULL, NULL, 0,
+                    rejected_out, certified);
 }
 
 /* ------------------------------------------------------------------ */

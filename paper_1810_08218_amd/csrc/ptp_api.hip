@@ -17,6 +17,7 @@
 #include "ptp.h"
 #include "ptp_device.h"
 #include "ptp_kernels.h"
+#include "ptp_mlp.h"
 
 using namespace ptp;
 
@@ -179,6 +180,8 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * N,                       // retire
         sizeof(int) * scan_blocks,             // scan_tmp
         sizeof(unsigned) * kLine * 2 * G,      // barrier lines
+        sizeof(float4) * N,                    // feat
+        sizeof(unsigned long long) * 2 * B,    // edge_acc (sums, maxima)
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -219,6 +222,8 @@ Work carve(void* base, const Layout& L) {
     w.retire = reinterpret_cast<int*>(b + L.off[24]);
     w.scan_tmp = reinterpret_cast<int*>(b + L.off[25]);
     w.bar = reinterpret_cast<unsigned*>(b + L.off[26]);
+    w.feat = reinterpret_cast<float4*>(b + L.off[27]);
+    w.edge_acc = reinterpret_cast<unsigned long long*>(b + L.off[28]);
     return w;
 }
 
@@ -420,11 +425,13 @@ struct Solver {
         return PTP_OK;
     }
 
-    ptp_status run(float* dDist, int32_t* dLabel, void* st) {
+    // dUpper non-null: warm start from that caller-order upper bound.
+    ptp_status run(float* dDist, int32_t* dLabel, void* st, const float* dUpper = nullptr) {
         if (!prepared) return fail(PTP_EINVAL, "run before a successful prepare");
         if (!dDist) return fail(PTP_EINVAL, "null distance output");
         const bool labels = opt.want_labels != 0;
         if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
+        if (labels && dUpper) return fail(PTP_EUNSUPPORTED, "a warm start does not compute labels");
         stream = static_cast<hipStream_t>(st);
         RunParams rp;
         rp.B = z.B;
@@ -433,11 +440,33 @@ struct Solver {
         rp.N = z.N;
         rp.tol = opt.tol;
         rp.S = S;
+        rp.upper = dUpper;
         rp.out_d = dDist;
         rp.out_l = labels ? dLabel : nullptr;
         hipError_t e = launch_run(work, rp, labels, s_run.G, stream);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         ran = true;
+        return PTP_OK;
+    }
+
+    ptp_status warm_features(float* dX, float* dScale, void* st) {
+        if (!prepared) return fail(PTP_EINVAL, "features before a successful prepare");
+        if (!dX || !dScale) return fail(PTP_EINVAL, "null feature output");
+        stream = static_cast<hipStream_t>(st);
+        hipError_t e = launch_features(work, z, stream);
+        if (e == hipSuccess) e = launch_export_features(work, z, dX, dScale, stream);
+        if (e != hipSuccess) return hip_fail(e, "features launch");
+        return PTP_OK;
+    }
+
+    ptp_status warm_predict(const float* dParams, float inflate, float* dUpper, void* st) {
+        if (!prepared) return fail(PTP_EINVAL, "predict before a successful prepare");
+        if (!dParams || !dUpper) return fail(PTP_EINVAL, "null parameters or output");
+        if (!(inflate >= 1.f) || !std::isfinite(inflate)) return fail(PTP_EINVAL, "inflate must be >= 1");
+        stream = static_cast<hipStream_t>(st);
+        hipError_t e = launch_features(work, z, stream);
+        if (e == hipSuccess) e = launch_predict(work, z, dParams, inflate, dUpper, stream);
+        if (e != hipSuccess) return hip_fail(e, "predict launch");
         return PTP_OK;
     }
 
@@ -463,6 +492,8 @@ struct Solver {
                 out[b].reachable = x.reach;
                 out[b].workgroups = s_run.gsize_of[b];
                 out[b].vertex_updates = x.updates;
+                out[b].certify_rounds = x.cert_rounds;
+                out[b].certify_rejected = x.cert_rejected;
             }
             if (agg == PTP_OK && sb != PTP_OK) agg = sb;
         }
@@ -548,7 +579,7 @@ struct ptp_batch {
 
 extern "C" {
 
-const char* ptp_version(void) { return "ptp-mi355x 0.2 (gfx950)"; }
+const char* ptp_version(void) { return "ptp-mi355x 0.3 (gfx950)"; }
 
 // ---- one mesh ------------------------------------------------------------
 ptp_status ptp_plan_create(ptp_plan** out, int32_t n, int32_t f, int32_t m, const ptp_options* opt) {
@@ -637,6 +668,22 @@ int32_t ptp_n_toplesets(const ptp_plan* p) {
     return p && p->s.prepared ? p->s.hstate[0].rho : -1;
 }
 
+ptp_status ptp_warm_features(ptp_plan* p, float* dX, float* dScale, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.warm_features(dX, dScale, stream);
+}
+
+ptp_status ptp_warm_predict(ptp_plan* p, const float* dParams, float inflate, float* dUpper, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.warm_predict(dParams, inflate, dUpper, stream);
+}
+
+ptp_status ptp_run_warm(ptp_plan* p, const float* dUpper, float* dDist, void* stream) {
+    if (!p) return PTP_EINVAL;
+    if (!dUpper) return p->s.fail(PTP_EINVAL, "null upper bound");
+    return p->s.run(dDist, nullptr, stream, dUpper);
+}
+
 const char* ptp_last_error(const ptp_plan* p) { return p ? p->s.err.c_str() : "null plan"; }
 
 void ptp_plan_destroy(ptp_plan* p) { delete p; }
@@ -708,8 +755,62 @@ ptp_status ptp_batch_autotune(ptp_batch* p, const ptp_schedule* candidates, int3
     return p->s.autotune(candidates, n, dDist, dLabel, hMs, best, stream);
 }
 
+ptp_status ptp_batch_warm_features(ptp_batch* p, float* dX, float* dScale, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.warm_features(dX, dScale, stream);
+}
+
+ptp_status ptp_batch_warm_predict(ptp_batch* p, const float* dParams, float inflate, float* dUpper,
+                                  void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.warm_predict(dParams, inflate, dUpper, stream);
+}
+
+ptp_status ptp_batch_run_warm(ptp_batch* p, const float* dUpper, float* dDist, void* stream) {
+    if (!p) return PTP_EINVAL;
+    if (!dUpper) return p->s.fail(PTP_EINVAL, "null upper bound");
+    return p->s.run(dDist, nullptr, stream, dUpper);
+}
+
 const char* ptp_batch_last_error(const ptp_batch* p) { return p ? p->s.err.c_str() : "null batch"; }
 
 void ptp_batch_destroy(ptp_batch* p) { delete p; }
+
+// ---- the warm-start network ----------------------------------------------
+int32_t ptp_mlp_params(void) { return kParams; }
+
+size_t ptp_mlp_scratch_bytes(void) { return mlp_scratch_bytes(); }
+
+ptp_status ptp_mlp_apply(const float* dParams, const float* dX, const float* dScale, int64_t n, float* dOut,
+                         void* stream) {
+    if (!dParams || n < 0 || (n > 0 && (!dX || !dScale || !dOut))) return PTP_EINVAL;
+    if (n == 0) return PTP_OK;
+    return launch_mlp_apply(dParams, dX, dScale, n, dOut, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? PTP_OK
+               : PTP_EDEVICE;
+}
+
+ptp_status ptp_mlp_grad(const float* dParams, const float* dX, const float* dScale, const float* dTarget,
+                        int64_t n, void* dScratch, size_t scratch_bytes, float* dGrad, float* dLoss,
+                        void* stream) {
+    if (!dParams || !dX || !dScale || !dTarget || !dScratch || !dGrad || n < 1) return PTP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dScratch) & 15) return PTP_EINVAL;
+    if (scratch_bytes < mlp_scratch_bytes()) return PTP_ENOMEM;
+    return launch_mlp_grad(dParams, dX, dScale, dTarget, n, static_cast<float*>(dScratch), dGrad, dLoss,
+                           static_cast<hipStream_t>(stream)) == hipSuccess
+               ? PTP_OK
+               : PTP_EDEVICE;
+}
+
+ptp_status ptp_adam_step(float* dParams, const float* dGrad, float* dM, float* dV, int32_t t, float lr,
+                         float beta1, float beta2, float eps, void* stream) {
+    if (!dParams || !dGrad || !dM || !dV || t < 1) return PTP_EINVAL;
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return PTP_EINVAL;
+    return launch_adam(dParams, dGrad, dM, dV, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? PTP_OK
+               : PTP_EDEVICE;
+}
 
 }  // extern "C"

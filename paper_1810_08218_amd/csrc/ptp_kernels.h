@@ -25,8 +25,10 @@ struct MeshState {         // per mesh, written by the kernels
     int status;            // StatusBits of the mesh
     int rho, reach;        // toplesets, reachable vertices
     int iters, runstat;    // K, 1 = cap reached
-    int pad;
+    float mean_edge;       // mean edge length (warm-start features)
     long long updates;     // U
+    int cert_rounds;       // warm start: certification sweeps
+    int cert_rejected;     // warm start: bounds withdrawn by the certification
 };
 
 struct WgInfo {            // per workgroup of a persistent launch
@@ -62,9 +64,11 @@ struct Work {
     int* retire;        // [N]     last iteration that updated each topleset, mesh b at v_off_b
     int* scan_tmp;      // block sums of the scans
     unsigned* bar;      // [32 * 2 * gmax] barrier lines: one per workgroup, then one per group
+    float4* feat;       // [N]     warm-start network inputs and scale per position
+    unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
 };
 
-constexpr int kLayoutParts = 27;
+constexpr int kLayoutParts = 29;
 
 struct Sizes {
     long long N, F, S;      // internal totals over the batch
@@ -93,11 +97,25 @@ struct RunParams {
     long long N;
     float tol;
     const int* S;
+    const float* upper;          // warm start: caller-order upper bound, or null
     float* out_d;
     int* out_l;
 };
 
 hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st);
+
+// learned warm start
+hipError_t launch_features(const Work& w, const Sizes& z, hipStream_t st);
+hipError_t launch_export_features(const Work& w, const Sizes& z, float* X, float* scale, hipStream_t st);
+hipError_t launch_predict(const Work& w, const Sizes& z, const float* params, float inflate, float* upper,
+                          hipStream_t st);
+hipError_t launch_mlp_apply(const float* params, const float* X, const float* S, long long n, float* out,
+                            hipStream_t st);
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* S, const float* D, long long n,
+                           float* scratch, float* grad, float* loss, hipStream_t st);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int t, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
+size_t mlp_scratch_bytes();
 
 int max_coop_blocks_bfs(int cus);
 int max_coop_blocks_run(int cus, bool labels);

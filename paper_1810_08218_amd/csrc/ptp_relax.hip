@@ -11,6 +11,8 @@
 // exchanged per iteration besides the distances is the "not converged" vote,
 // carried by the barrier.
 #include "ptp_device.h"
+#include <algorithm>
+
 #include "ptp_kernels.h"
 
 namespace ptp {
@@ -99,6 +101,7 @@ struct RelaxArgs {
     const WgInfo* wg;
     const int* glist;      // per group: starts [ngroups + 1], then mesh ids
     const int* S;
+    const float* upper;    // warm start: caller-order upper bound, or null
     const int* perm;
     const int* iperm;
     const int* offsets;
@@ -115,7 +118,55 @@ struct RelaxArgs {
     int* out_l;
 };
 
-constexpr int kChunk = 6;   // wedges gathered together per vertex (mean degree 6)
+// Wedges gathered together per vertex (mean degree 6); the warm-start
+// variant gathers 4 at a time to stay within 128 registers (the minimum over
+// wedges does not depend on the grouping).
+constexpr int kChunk = 6;
+constexpr int kCertifyRounds = 4096;   // cap on the certification closure
+
+// Smallest planar update of position v over its incident triangles, reading
+// distances (and labels) from dold / lold: first up to kChunk wedges, then
+// every neighbour distance and coordinate of those wedges at once
+// (independent loads), then the updates.  (value, label) lexicographic min.
+template <bool LABELS, int kChunk>
+__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const float* dold,
+                                   const int* lold, float& best, int& bl) {
+    best = kInf;
+    bl = 0x7fffffff;
+    const int e0 = a.row[v], e1 = a.row[v + 1];
+    for (int base = e0; base < e1; base += kChunk) {
+        const int cnt = min(kChunk, e1 - base);
+        int2 wv[kChunk];
+        float da[kChunk], db[kChunk];
+        float4 xa[kChunk], xb[kChunk];
+        int la[kChunk], lb[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            da[q] = ld_c(dold + wv[q].x);
+            db[q] = ld_c(dold + wv[q].y);
+            xa[q] = a.xyz[wv[q].x];
+            xb[q] = a.xyz[wv[q].y];
+            if (LABELS) {
+                la[q] = ld_c(lold + wv[q].x);
+                lb[q] = ld_c(lold + wv[q].y);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            if (q < cnt && fminf(da[q], db[q]) < kInf) {
+                int l = 0;
+                const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
+                                                     LABELS ? lb[q] : 0, l);
+                if (u < best || (LABELS && u == best && l < bl)) {
+                    best = u;
+                    bl = l;
+                }
+            }
+        }
+    }
+}
 
 // Groups of consecutive workgroups run the whole iteration of one mesh at a
 // time, with a barrier of their own.  Per iteration k every thread of the
@@ -126,7 +177,7 @@ constexpr int kChunk = 6;   // wedges gathered together per vertex (mean degree 
 // wedges, then every neighbour distance and coordinate of those wedges at
 // once (independent loads), then evaluates the planar updates.  Distances and
 // labels are exchanged between workgroups through coherent loads and stores.
-template <bool LABELS>
+template <bool LABELS, bool WARM>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
     const int gs = me.gsize;
@@ -153,8 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const int kmax = a.kmax_fixed > 0 ? a.kmax_fixed : 4 * rho + 16;
         const int m0 = offs[1];                  // |V_0|: the sources occupy [0, m0)
 
+        const int reach = a.state[b].reach;
         for (long long p = g0; p < n; p += gsz) {
-            const float d = p < m0 ? 0.f : kInf;
+            float d = p < m0 ? 0.f : kInf;
+            if (WARM && p >= m0 && p < reach) {      // warm start: the caller's bound
+                const int v = a.perm[vo + p];
+                const float w = a.upper[md.out_off + (v - vo)];
+                d = w >= 0.f ? w : kInf;                 // NaN or negative: no bound
+            }
             st_c(dA + vo + p, d);
             st_c(dB + vo + p, d);
             if (LABELS && p >= m0) {
@@ -170,6 +227,47 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             }
         for (long long r = g0; r < rho; r += gsz) retire[r] = r == 0 ? 0 : -1;
         if (!gb.sync(0, &any)) return;
+
+        if (WARM) {
+            // Certification of the warm start: a vertex whose bound lies below
+            // the planar update from its neighbours' bounds (w < U(w)) loses its
+            // bound (+inf); repeated until no vertex changes.  The result is a
+            // supersolution (w >= U(w), w(S) = 0), hence above the fixed point,
+            // so the min-relaxation from it descends to the same fixed point.
+            // Marking only raises U elsewhere, so the closure is unique and the
+            // order of the in-place updates does not matter.
+            const long long firstc = m0 + ((g0 - m0 % gsz) + gsz) % gsz;
+            int rejected = 0, round = 0;
+            for (;; ++round) {
+                unsigned changed = 0;
+                for (long long pp = firstc; pp < reach; pp += gsz) {
+                    const int v = vo + (int)pp;
+                    const float w = ld_c(dA + v);
+                    if (!(w < kInf)) continue;
+                    float u;
+                    int ul;
+                    best_update<false, 4>(a, v, a.xyz[v], dA, nullptr, u, ul);
+                    if (w < u) {
+                        st_c(dA + v, kInf);
+                        changed = 1;
+                        ++rejected;
+                    }
+                }
+                if (!gb.sync(changed, &any)) return;
+                if (!any) break;
+                if (round == kCertifyRounds) {           // no closure in time: no bound
+                    for (long long pp = firstc; pp < reach; pp += gsz) st_c(dA + vo + pp, kInf);
+                    if (!gb.sync(0, &any)) return;
+                    rejected = 0;
+                    if (leader) rejected = reach - m0;
+                    break;
+                }
+            }
+            if (rejected) atomicAdd(&a.state[b].cert_rejected, rejected);
+            if (leader) a.state[b].cert_rounds = round + 1;
+            for (long long pp = firstc; pp < reach; pp += gsz) st_c(dB + vo + pp, ld_c(dA + vo + pp));
+            if (!gb.sync(0, &any)) return;
+        }
 
         int i = 1, lo_prev = 1, k = 0, runstat = 0;
         long long upd = 0;
@@ -201,41 +299,9 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 }
                 const float4 x0 = a.xyz[v];
                 const float dv = ld_c(dold + v);
-                float best = kInf;
-                int bl = 0x7fffffff;
-                const int e0 = a.row[v], e1 = a.row[v + 1];
-                for (int base = e0; base < e1; base += kChunk) {
-                    const int cnt = min(kChunk, e1 - base);
-                    int2 wv[kChunk];
-                    float da[kChunk], db[kChunk];
-                    float4 xa[kChunk], xb[kChunk];
-                    int la[kChunk], lb[kChunk];
-#pragma unroll
-                    for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
-#pragma unroll
-                    for (int q = 0; q < kChunk; ++q) {
-                        da[q] = ld_c(dold + wv[q].x);
-                        db[q] = ld_c(dold + wv[q].y);
-                        xa[q] = a.xyz[wv[q].x];
-                        xb[q] = a.xyz[wv[q].y];
-                        if (LABELS) {
-                            la[q] = ld_c(lold + wv[q].x);
-                            lb[q] = ld_c(lold + wv[q].y);
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < kChunk; ++q) {
-                        if (q < cnt && fminf(da[q], db[q]) < kInf) {
-                            int l = 0;
-                            const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q],
-                                                                 LABELS ? la[q] : 0, LABELS ? lb[q] : 0, l);
-                            if (u < best || (LABELS && u == best && l < bl)) {
-                                best = u;
-                                bl = l;
-                            }
-                        }
-                    }
-                }
+                float best;
+                int bl;
+                best_update<LABELS, WARM ? 4 : kChunk>(a, v, x0, dold, lold, best, bl);
                 float dn = dv;
                 if (best < dv) {
                     dn = best;
@@ -253,7 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             if (!gb.sync(notconv, &any)) return;
             if (leader)
                 for (int r = i; r < lo; ++r) retire[r] = k - 1;      // pushed out by the window
-            if (!any) {                                              // Eq. lower_band
+            // Eq. lower_band.  V_lo may retire only after its second update
+            // (k > lo): from +inf that is automatic, and a warm start keeps the
+            // same causality, so the band never runs ahead of the front.
+            if (!any && k > lo) {
                 if (leader) retire[lo] = k;
                 i = lo + 1;
             } else {
@@ -282,6 +351,8 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
         state[b].iters = 0;
         state[b].runstat = 0;
         state[b].updates = 0;
+        state[b].cert_rounds = 0;
+        state[b].cert_rejected = 0;
     }
 }
 
@@ -300,6 +371,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run,
     a.wg = w.wg_run;
     a.glist = w.glist_run;
     a.S = p.S;
+    a.upper = p.upper;
     a.perm = w.perm;
     a.iperm = w.iperm;
     a.offsets = w.offsets;
@@ -315,15 +387,25 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run,
     a.out_d = p.out_d;
     a.out_l = p.out_l;
     void* args[] = {&a};
-    const void* fn = labels ? reinterpret_cast<const void*>(&k_relax<true>)
-                            : reinterpret_cast<const void*>(&k_relax<false>);
+    const void* fn = labels    ? reinterpret_cast<const void*>(&k_relax<true, false>)
+                     : p.upper ? reinterpret_cast<const void*>(&k_relax<false, true>)
+                               : reinterpret_cast<const void*>(&k_relax<false, false>);
     return hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
 }
 
+// Co-resident workgroups of the relaxation kernels a plan may launch: the
+// labelled one, or (without labels) the plain and the warm-start one.
 int max_coop_blocks_run(int cus, bool labels) {
-    int nb = 0;
-    hipError_t e = labels ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true>, kBlock, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false>, kBlock, 0);
+    int nb = 0, nw = 0;
+    hipError_t e;
+    if (labels) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false>, kBlock, 0);
+        nw = nb;
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false>, kBlock, 0);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true>, kBlock, 0);
+    }
+    nb = std::min(nb, nw);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb * cus;
 }

@@ -22,6 +22,8 @@ them, see the experimental section of the paper):
   random sources (multi-source / Voronoi runs, Fig. ptp_speedup_sources).
 * ``batch_mesh(t)`` / ``batch_meshes()``: 512 uneven meshes, jittered grids and
   tori, 1-4 sources each (batched form).
+* ``training_mesh(t)``: the warm-start network's training and evaluation
+  meshes (jittered grids, noisy and bumpy icospheres, 1-32 sources).
 """
 from __future__ import annotations
 
@@ -181,11 +183,19 @@ def subdivide(V: np.ndarray, F: np.ndarray) -> tuple:
     return np.concatenate([V, mid], axis=0), F2
 
 
+_ICO_CACHE: dict = {}
+
+
 def icosphere64(level: int) -> tuple:
-    V, F = icosahedron()
-    for _ in range(level):
-        V, F = subdivide(V, F)
-    return V, F
+    """Unit icosphere after ``level`` subdivisions (float64 vertices, int64
+    faces).  Returns fresh copies of a cached mesh."""
+    if level not in _ICO_CACHE:
+        V, F = icosahedron()
+        for _ in range(level):
+            V, F = subdivide(V, F)
+        _ICO_CACHE[level] = (V, F)
+    V, F = _ICO_CACHE[level]
+    return V.copy(), F.copy()
 
 
 def mean_edge_length(V: np.ndarray, F: np.ndarray) -> float:
@@ -266,3 +276,39 @@ def batch_mesh(t: int, seed: int = 4) -> Mesh:
 
 def batch_meshes(count: int = 512, seed: int = 4, first: int = 0) -> list:
     return [batch_mesh(t, seed) for t in range(first, first + count)]
+
+
+# ------------------------------------------------------- warm-start data ---
+
+def training_mesh(t: int, seed: int = 5) -> Mesh:
+    """Mesh t of the warm-start training set (another ``seed`` gives held-out
+    meshes).  t % 3 == 0: jittered grid, side round(exp(U(ln 32, ln 256)));
+    1: icosphere of level U{3..6} with tangential noise of 0.1 mean edge;
+    2: bumpy icosphere (radial sum of 8 sines as in ``bumpy_icosphere``) of
+    level U{4..6}.  1-32 distinct random sources."""
+    rng = np.random.default_rng([seed, t])
+    kind = t % 3
+    if kind == 0:
+        s = int(round(math.exp(rng.uniform(math.log(32.0), math.log(256.0)))))
+        V, F = jittered_grid(s, rng)
+        name = f"jgrid{s}"
+        V64 = V.astype(np.float64)
+    elif kind == 1:
+        level = int(rng.integers(3, 7))
+        V64, F = icosphere64(level)
+        V64 = _tangential_noise(V64, F, rng, 0.1)
+        name = f"noisy_icosphere{level}"
+    else:
+        level = int(rng.integers(4, 7))
+        N, F = icosphere64(level)
+        a = rng.uniform(0.0, 1.0, 8) / np.arange(1, 9)
+        fr = rng.uniform(2.0, 12.0, 8)
+        u = rng.normal(size=(8, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        r = 1.0 + 0.15 * (a[None, :] * np.sin(fr[None, :] * (N @ u.T))).sum(axis=1)
+        V64 = N * r[:, None]
+        name = f"bumpy_icosphere{level}"
+    n = V64.shape[0]
+    m = int(rng.integers(1, 33))
+    S = np.sort(rng.choice(n, m, replace=False))
+    return Mesh(_f32(V64), _i32(F), _i32(S), name=name, meta={"t": t, "seed": seed})

@@ -30,7 +30,12 @@ EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "
            "ptp_last_error", "ptp_plan_destroy", "ptp_version",
            "ptp_batch_create", "ptp_batch_workspace_bytes", "ptp_batch_prepare", "ptp_batch_run",
            "ptp_batch_get_stats", "ptp_batch_set_schedule", "ptp_batch_get_schedule",
-           "ptp_batch_autotune", "ptp_batch_last_error", "ptp_batch_destroy")
+           "ptp_batch_autotune", "ptp_batch_last_error", "ptp_batch_destroy",
+           "ptp_warm_features", "ptp_warm_predict", "ptp_run_warm", "ptp_batch_warm_features",
+           "ptp_batch_warm_predict", "ptp_batch_run_warm", "ptp_mlp_params", "ptp_mlp_apply",
+           "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step")
+
+MLP_PARAMS = 4481       # PTP_MLP_PARAMS
 
 
 class PTPError(RuntimeError):
@@ -47,7 +52,8 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_toplesets", C.c_int32),
                 ("reachable", C.c_int32), ("workgroups", C.c_int32),
-                ("vertex_updates", C.c_int64)]
+                ("vertex_updates", C.c_int64), ("certify_rounds", C.c_int32),
+                ("certify_rejected", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -130,6 +136,28 @@ def load() -> C.CDLL:
     lib.ptp_batch_last_error.restype = C.c_char_p
     lib.ptp_batch_destroy.argtypes = [vp]
     lib.ptp_batch_destroy.restype = None
+    for name in ("ptp_warm_features", "ptp_batch_warm_features"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+        getattr(lib, name).restype = C.c_int
+    for name in ("ptp_warm_predict", "ptp_batch_warm_predict"):
+        getattr(lib, name).argtypes = [vp, vp, C.c_float, vp, vp]
+        getattr(lib, name).restype = C.c_int
+    for name in ("ptp_run_warm", "ptp_batch_run_warm"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+        getattr(lib, name).restype = C.c_int
+    lib.ptp_mlp_params.argtypes = []
+    lib.ptp_mlp_params.restype = C.c_int32
+    lib.ptp_mlp_apply.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+    lib.ptp_mlp_apply.restype = C.c_int
+    lib.ptp_mlp_scratch_bytes.argtypes = []
+    lib.ptp_mlp_scratch_bytes.restype = C.c_size_t
+    lib.ptp_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_int64, vp, C.c_size_t, vp, vp, vp]
+    lib.ptp_mlp_grad.restype = C.c_int
+    lib.ptp_adam_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                  C.c_float, vp]
+    lib.ptp_adam_step.restype = C.c_int
+    if lib.ptp_mlp_params() != MLP_PARAMS:
+        raise RuntimeError("libptp.so was built with another network size")
     _lib = lib
     return lib
 
@@ -227,6 +255,40 @@ class Plan:
         rc = self._lib.ptp_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
         if rc != PTP_OK:
             raise self._err(rc, "ptp_run")
+
+    # -- learned warm start --------------------------------------------------
+    def warm_features(self, stream=None):
+        """Network inputs X [n, 3] and scale [n] (caller order) as device tensors."""
+        import torch
+        X = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        scale = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        rc = self._lib.ptp_warm_features(self._h, _ptr(X), _ptr(scale), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_warm_features")
+        return X, scale
+
+    def warm_predict(self, params, upper, inflate: float = 1.05, stream=None):
+        """upper[n] = inflate * predicted distance (0 at sources, +inf unreachable)."""
+        import torch
+        _check_dev(params, torch.float32, None, "params")
+        _check_dev(upper, torch.float32, None, "upper")
+        if params.numel() != MLP_PARAMS or upper.numel() != self.n:
+            raise ValueError("params must have MLP_PARAMS values and upper n")
+        rc = self._lib.ptp_warm_predict(self._h, _ptr(params), float(inflate), _ptr(upper),
+                                        _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_warm_predict")
+
+    def run_warm(self, upper, dist, stream=None):
+        """Certify `upper` and run PTP from it (may be the same tensor as dist)."""
+        import torch
+        _check_dev(upper, torch.float32, None, "upper")
+        _check_dev(dist, torch.float32, None, "dist")
+        if upper.numel() != self.n or dist.numel() != self.n:
+            raise ValueError("upper and dist must have n elements")
+        rc = self._lib.ptp_run_warm(self._h, _ptr(upper), _ptr(dist), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_run_warm")
 
     def stats(self, allow_noconv: bool = True) -> dict:
         st = Stats()
@@ -385,6 +447,37 @@ class Batch:
         if rc != PTP_OK:
             raise self._err(rc, "ptp_batch_run")
 
+    def warm_features(self, stream=None):
+        """Network inputs X [out_len, 3] and scale [out_len] as device tensors."""
+        import torch
+        X = torch.empty((self.out_len, 3), dtype=torch.float32, device="cuda")
+        scale = torch.empty(self.out_len, dtype=torch.float32, device="cuda")
+        rc = self._lib.ptp_batch_warm_features(self._h, _ptr(X), _ptr(scale), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_warm_features")
+        return X, scale
+
+    def warm_predict(self, params, upper, inflate: float = 1.05, stream=None):
+        import torch
+        _check_dev(params, torch.float32, None, "params")
+        _check_dev(upper, torch.float32, None, "upper")
+        if params.numel() != MLP_PARAMS or upper.numel() < self.out_len:
+            raise ValueError("params must have MLP_PARAMS values and upper out_len")
+        rc = self._lib.ptp_batch_warm_predict(self._h, _ptr(params), float(inflate), _ptr(upper),
+                                              _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_warm_predict")
+
+    def run_warm(self, upper, dist, stream=None):
+        import torch
+        _check_dev(upper, torch.float32, None, "upper")
+        _check_dev(dist, torch.float32, None, "dist")
+        if upper.numel() < self.out_len or dist.numel() < self.out_len:
+            raise ValueError("upper and dist too short for the batch outputs")
+        rc = self._lib.ptp_batch_run_warm(self._h, _ptr(upper), _ptr(dist), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_run_warm")
+
     def stats(self):
         """(aggregate status, [per-mesh stats dict], [per-mesh status])"""
         st = (Stats * self.count)()
@@ -417,3 +510,74 @@ class Batch:
         if rc != PTP_OK:
             raise self._err(rc, "ptp_batch_autotune")
         return int(best.value), [float(x) for x in ms]
+
+
+# ------------------------------------------------------- warm-start network ---
+
+def mlp_apply(params, X, scale, out=None, stream=None):
+    """out[i] = 64 scale[i] softplus(o(X[i])) on the GPU (ptp_mlp_apply)."""
+    import torch
+    lib = load()
+    _check_dev(params, torch.float32, None, "params")
+    _check_dev(X, torch.float32, (3,), "X")
+    _check_dev(scale, torch.float32, None, "scale")
+    n = X.shape[0]
+    if params.numel() != MLP_PARAMS or scale.numel() != n:
+        raise ValueError("params / scale sizes")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=X.device)
+    rc = lib.ptp_mlp_apply(_ptr(params), _ptr(X), _ptr(scale), n, _ptr(out), _stream(stream))
+    if rc != PTP_OK:
+        raise PTPError(rc, "ptp_mlp_apply")
+    return out
+
+
+class MlpTrainer:
+    """Device buffers for training the warm-start network with the library's
+    forward/backward and Adam kernels (gradient scratch, moments)."""
+
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        import torch
+        lib = load()
+        self._lib = lib
+        _check_dev(params, torch.float32, None, "params")
+        if params.numel() != MLP_PARAMS:
+            raise ValueError("params must have MLP_PARAMS values")
+        self.params = params
+        self.lr, self.betas, self.eps = float(lr), betas, float(eps)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        nb = int(lib.ptp_mlp_scratch_bytes())
+        self.scratch = torch.empty((nb + 3) // 4, dtype=torch.float32, device=params.device)
+        self.t = 0
+
+    def grad_loss(self, X, scale, target, stream=None):
+        """Gradient (into self.grad) and loss (self.loss) over the rows."""
+        import torch
+        _check_dev(X, torch.float32, (3,), "X")
+        _check_dev(scale, torch.float32, None, "scale")
+        _check_dev(target, torch.float32, None, "target")
+        n = X.shape[0]
+        if scale.numel() != n or target.numel() != n or n < 1:
+            raise ValueError("row counts")
+        rc = self._lib.ptp_mlp_grad(_ptr(self.params), _ptr(X), _ptr(scale), _ptr(target), n,
+                                    _ptr(self.scratch), self.scratch.numel() * 4, _ptr(self.grad),
+                                    _ptr(self.loss), _stream(stream))
+        if rc != PTP_OK:
+            raise PTPError(rc, "ptp_mlp_grad")
+        return self.grad, self.loss
+
+    def adam(self, stream=None):
+        self.t += 1
+        rc = self._lib.ptp_adam_step(_ptr(self.params), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
+                                     self.t, self.lr, float(self.betas[0]), float(self.betas[1]),
+                                     self.eps, _stream(stream))
+        if rc != PTP_OK:
+            raise PTPError(rc, "ptp_adam_step")
+
+    def step(self, X, scale, target, stream=None):
+        self.grad_loss(X, scale, target, stream)
+        self.adam(stream)
+        return self.loss
