@@ -13,7 +13,9 @@ ms to converge (ptp_run alone), the roofline of the relaxation kernel, the
 oracle's single-thread CPU rate on the same mesh, and the max relative error
 of the GPU distances against the oracle.  Alongside ("batched"): the 512-mesh
 uneven batch (jittered grids and tori, 71M vertices) in one persistent launch
-with an autotuned schedule, against the same meshes run one plan at a time.
+with an autotuned schedule, against the same meshes run one plan at a time;
+and ("warm_start", for the single mesh and the batch) the learned warm start
+against the plain run at the same tolerance.
 """
 from __future__ import annotations
 
@@ -71,10 +73,75 @@ def cpu_baseline(mesh, tol, budget_s=12.0):
                            f"oracle (median {t * 1e3:.0f} ms each, U={res.updates})"}
 
 
-def bench_batched(steps, P, I):
+def note(msg):
+    """Progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(fn, stream, reps):
+    """Median device time (ms) of fn() over reps runs after 3 warm-ups."""
+    import torch
+    for _ in range(3):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        z.record(stream)
+        z.synchronize()
+        ts.append(a.elapsed_time(z))
+    return statistics.median(ts)
+
+
+def bench_warm(obj, n_out, stream, reps):
+    """Learned warm start against the plain run on a prepared plan or batch:
+    ms to converge of (features + network + certified run) vs (run), both
+    3 warm-ups then the median of `reps`; iterations, updates and the
+    largest relative difference of the results."""
+    import torch
+    from paper_1810_08218_amd import train_warmstart
+    params = train_warmstart.load_params()
+    plain = torch.empty(n_out, dtype=torch.float32, device="cuda")
+    warm = torch.empty(n_out, dtype=torch.float32, device="cuda")
+
+    def run_plain():
+        obj.run(plain, stream=stream)
+
+    def run_warm():
+        obj.warm_predict(params, warm, inflate=1.05, stream=stream)
+        obj.run_warm(warm, warm, stream=stream)
+
+    ms_plain = _timed(run_plain, stream, reps)
+    sp = obj.stats()
+    ms_warm = _timed(run_warm, stream, reps)
+    sw = obj.stats()
+    if isinstance(sp, tuple):                   # batch: (rc, per-mesh stats, status)
+        agg = lambda st, k: sum(x[k] for x in st[1])
+        kp, kw = max(x["iterations"] for x in sp[1]), max(x["iterations"] for x in sw[1])
+        up, uw = agg(sp, "vertex_updates"), agg(sw, "vertex_updates")
+        rej, reach = agg(sw, "certify_rejected"), agg(sw, "reachable")
+        rounds = max(x["certify_rounds"] for x in sw[1])
+    else:
+        kp, kw, up, uw = sp["iterations"], sw["iterations"], sp["vertex_updates"], sw["vertex_updates"]
+        rej, reach, rounds = sw["certify_rejected"], sw["reachable"], sw["certify_rounds"]
+    p, w = plain.double(), warm.double()
+    fin = torch.isfinite(p) & (p > 0)
+    rel = float(((w[fin] - p[fin]).abs() / p[fin]).max())
+    return {"ms_to_converge_plain": round(ms_plain, 3), "ms_to_converge_warm": round(ms_warm, 3),
+            "speedup": round(ms_plain / ms_warm, 3), "iterations_plain": kp,
+            "iterations_warm": kw, "vertex_updates_plain": int(up), "vertex_updates_warm": int(uw),
+            "certify_rejected_frac": round(rej / max(1, reach), 4), "certify_rounds_max": rounds,
+            "max_rel_diff_warm_vs_plain": rel, "inflate": 1.05,
+            "timed": f"3 warm-ups, median of {reps}; warm includes features, network and "
+                     f"certification"}
+
+
+def bench_batched(steps, P, I, warm=True):
     """512 uneven meshes in one persistent launch vs one plan per mesh."""
     import torch
     from paper_1810_08218_amd import autotune
+    note("batched: generating 512 meshes")
     meshes = I.batch_meshes(512)
     V, F, S, descs, out_len = P.concat(meshes)
     dV, dF, dS = (torch.from_numpy(x).cuda() for x in (V, F, S))
@@ -84,6 +151,7 @@ def bench_batched(steps, P, I):
     work = b.workspace()
     dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
     b.prepare(dV, dF, dS, work=work)
+    note("batched: autotuning the schedule")
     tuned = autotune.tune(b, descs, dist, use_cache=False)
     stream = torch.cuda.current_stream()
     b.run(dist, stream=stream)              # warm-up with the tuned schedule
@@ -103,6 +171,7 @@ def bench_batched(steps, P, I):
     ms_run = statistics.mean(a.elapsed_time(z) for a, z in ev)
     U = sum(x["vertex_updates"] for x in stats)
     # the same meshes, one plan each (run only)
+    note("batched: one plan per mesh")
     plain_ms = 0.0
     for m in meshes:
         Vm, Fm, Sm = (torch.from_numpy(x).cuda() for x in (m.V, m.F, m.S))
@@ -127,7 +196,8 @@ def bench_batched(steps, P, I):
             "speedup_vs_plain": round(plain_ms / ms_run, 3),
             "schedule": tuned["schedule"],
             "max_iterations": max(x["iterations"] for x in stats),
-            "max_toplesets": max(x["n_toplesets"] for x in stats)}
+            "max_toplesets": max(x["n_toplesets"] for x in stats),
+            "warm_start": bench_warm(b, out_len, stream, 3) if warm else None}
 
 
 def main():
@@ -139,6 +209,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 256 MiB (a kernel of known traffic for "
                          "scaling the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -181,6 +252,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    note(f"single mesh: {args.warmup} warm-up + {args.steps} timed steps")
     for _ in range(args.warmup):
         st = step()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -209,12 +281,16 @@ def main():
     cpu = None
     max_rel = None
     if not args.no_cpu_baseline:
+        note("CPU baseline (oracle)")
         res, cpu = cpu_baseline(mesh, tol)
         o = res.dist
         mask = np.isfinite(o) & (o > 0)
         max_rel = float(np.max(np.abs(gpu_d[mask] - o[mask]) / o[mask]))
         same_sched = bool(np.array_equal(plan.schedule(), res.retire_k))
-    batched = None if args.no_batched else bench_batched(args.batched_steps, P, I)
+    note("warm start on the single mesh")
+    warm = None if args.no_warm else bench_warm(plan, mesh.n, stream, 20)
+    batched = None if args.no_batched else bench_batched(args.batched_steps, P, I,
+                                                         warm=not args.no_warm)
     line = {
         "metric": "vertex-updates/s at <=1e-4 rel err (ms to converge alongside)",
         "value": round(value, 1),
@@ -242,6 +318,7 @@ def main():
     }
     if cpu is not None:
         line["schedule_matches_oracle"] = same_sched
+    line["warm_start"] = warm
     line["batched"] = batched
     print(json.dumps(line), flush=True)
 

@@ -430,8 +430,8 @@ struct Solver {
         if (!prepared) return fail(PTP_EINVAL, "run before a successful prepare");
         if (!dDist) return fail(PTP_EINVAL, "null distance output");
         const bool labels = opt.want_labels != 0;
-        if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
         if (labels && dUpper) return fail(PTP_EUNSUPPORTED, "a warm start does not compute labels");
+        if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
         stream = static_cast<hipStream_t>(st);
         RunParams rp;
         rp.B = z.B;

@@ -80,6 +80,31 @@ __global__ void k_edge_mean(const unsigned long long* acc, const unsigned long l
     }
 }
 
+// One incident triangle (v, a, b) of a vertex at x: the unnormalised face
+// normal q = (a - x) x (b - x), twice its area, and its term of the
+// cotangent Laplacian, cot(angle at b)(a - x) + cot(angle at a)(b - x)
+// (zero for a degenerate triangle).
+struct WedgeGeo {
+    float3 q, k;
+    float dbl;
+};
+
+__device__ inline WedgeGeo wedge_geo(const float4 x, const float4 a, const float4 c) {
+    WedgeGeo g;
+    const float ax = a.x - x.x, ay = a.y - x.y, az = a.z - x.z;   // v -> a
+    const float cx = c.x - x.x, cy = c.y - x.y, cz = c.z - x.z;   // v -> b
+    g.q = make_float3(ay * cz - az * cy, az * cx - ax * cz, ax * cy - ay * cx);
+    g.dbl = len3(g.q.x, g.q.y, g.q.z);
+    g.k = make_float3(0.f, 0.f, 0.f);
+    if (g.dbl > 0.f) {
+        // angle at a: between (v - a) and (b - a); at b: between (v - b) and (a - b)
+        const float cot_a = ((-ax) * (cx - ax) + (-ay) * (cy - ay) + (-az) * (cz - az)) / g.dbl;
+        const float cot_b = ((-cx) * (ax - cx) + (-cy) * (ay - cy) + (-cz) * (az - cz)) / g.dbl;
+        g.k = make_float3(cot_b * ax + cot_a * cx, cot_b * ay + cot_a * cy, cot_b * az + cot_a * cz);
+    }
+    return g;
+}
+
 // Network inputs (x0, x1, x2) and the scale l per internal position; w = -1
 // marks positions with no feature (unreachable vertices).
 __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const int* row, const int2* wedge,
@@ -102,34 +127,38 @@ __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const in
             const float4 s = xyz[v0 + i];
             f1 = fminf(f1, len3(x.x - s.x, x.y - s.y, x.z - s.z));
         }
-        float kx = 0.f, ky = 0.f, kz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f, area = 0.f;
-        for (int e = row[p]; e < row[p + 1]; ++e) {
-            const int2 w = wedge[e];
-            const float4 a = xyz[w.x], c = xyz[w.y];
-            const float ax = a.x - x.x, ay = a.y - x.y, az = a.z - x.z;   // v -> a
-            const float cx = c.x - x.x, cy = c.y - x.y, cz = c.z - x.z;   // v -> b
-            const float qx = ay * cz - az * cy, qy = az * cx - ax * cz, qz = ax * cy - ay * cx;
-            const float dbl = len3(qx, qy, qz);                           // 2 * area
-            nx += qx;
-            ny += qy;
-            nz += qz;
-            area += dbl / 6.f;
-            if (dbl > 0.f) {
-                // angle at a: between (v - a) and (b - a); at b: (v - b) and (a - b)
-                const float cot_a = ((-ax) * (cx - ax) + (-ay) * (cy - ay) + (-az) * (cz - az)) / dbl;
-                const float cot_b = ((-cx) * (ax - cx) + (-cy) * (ay - cy) + (-cz) * (az - cz)) / dbl;
-                kx += cot_b * ax + cot_a * cx;
-                ky += cot_b * ay + cot_a * cy;
-                kz += cot_b * az + cot_a * cz;
-            }
+        // The incidence order of a vertex's triangles is not fixed (it comes
+        // from atomics), so the sums are taken in fixed point: a first pass
+        // finds the largest magnitude, the second adds integers scaled to it.
+        const int e0 = row[p], e1 = row[p + 1];
+        float mk = 0.f, mq = 0.f;
+        for (int e = e0; e < e1; ++e) {
+            const WedgeGeo g = wedge_geo(x, xyz[wedge[e].x], xyz[wedge[e].y]);
+            mk = fmaxf(mk, fmaxf(fabsf(g.k.x), fmaxf(fabsf(g.k.y), fabsf(g.k.z))));
+            mq = fmaxf(mq, fmaxf(g.dbl, fmaxf(fabsf(g.q.x), fmaxf(fabsf(g.q.y), fabsf(g.q.z)))));
+        }
+        const double deg = (double)max(1, e1 - e0);
+        const double sk = mk > 0.f ? 4611686018427387904.0 / ((double)mk * deg) : 0.0;   // 2^62
+        const double sq = mq > 0.f ? 4611686018427387904.0 / ((double)mq * deg) : 0.0;
+        long long Kx = 0, Ky = 0, Kz = 0, Nx = 0, Ny = 0, Nz = 0, A = 0;
+        for (int e = e0; e < e1; ++e) {
+            const WedgeGeo g = wedge_geo(x, xyz[wedge[e].x], xyz[wedge[e].y]);
+            Kx += llrint((double)g.k.x * sk);
+            Ky += llrint((double)g.k.y * sk);
+            Kz += llrint((double)g.k.z * sk);
+            Nx += llrint((double)g.q.x * sq);
+            Ny += llrint((double)g.q.y * sq);
+            Nz += llrint((double)g.q.z * sq);
+            A += llrint((double)g.dbl * sq);
         }
         float H = 0.f;
-        if (area > 0.f) {
-            kx /= 2.f * area;
-            ky /= 2.f * area;
-            kz /= 2.f * area;
-            H = 0.5f * len3(kx, ky, kz);
-            if (kx * nx + ky * ny + kz * nz < 0.f) H = -H;
+        if (A > 0 && sk > 0.0) {
+            const double area = (double)A / sq / 6.0;      // a third of the incident areas
+            const double kx = (double)Kx / sk / (2.0 * area);
+            const double ky = (double)Ky / sk / (2.0 * area);
+            const double kz = (double)Kz / sk / (2.0 * area);
+            H = (float)(0.5 * sqrt(kx * kx + ky * ky + kz * kz));
+            if (kx * (double)Nx + ky * (double)Ny + kz * (double)Nz < 0.0) H = -H;
         }
         feat[p] = make_float4(f1 / l * kInScale, (float)hop * kInScale, H * l, l);
     }

@@ -1,0 +1,87 @@
+"""What the trained warm-start network gains over the plain method.
+
+On held-out meshes (the training recipe with another seed, and the noisy
+icosphere of level 6) this reports, for the plain run and for the warm
+start (features + network + certification + run): iterations K, vertex
+updates U, ms to converge, the fraction of predicted bounds the
+certification withdrew, and the network's relative error.  It asserts what
+must hold whatever the gain: the warm result equals the plain one within
+1e-4, the trained network's mean relative error stays below 5% on meshes
+it has not seen (the Euclidean distance to the nearest source is reported
+beside it), and the warm start never needs more iterations than the plain
+run.  The gain itself is reported, not asserted:
+a start inflated by 5% is above the plain run's own intermediate values
+wherever the front has passed, so it can only help where the plain band
+has not yet arrived.
+"""
+import numpy as np
+import pytest
+
+import paper_1810_08218_amd as P
+from gpu_util import rel_errors, say, to_dev
+from paper_1810_08218_amd import inputs as I
+from paper_1810_08218_amd import train_warmstart
+
+pytestmark = pytest.mark.gpu
+
+
+def _time(fn, reps=5):
+    import torch
+    fn()
+    ts = []
+    for _ in range(reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        z.record()
+        z.synchronize()
+        ts.append(a.elapsed_time(z))
+    return float(np.median(ts))
+
+
+def test_trained_network_gain_report(cuda):
+    import torch
+    params = train_warmstart.load_params()
+    meshes = [I.training_mesh(t, seed=6) for t in (0, 1, 2, 3, 4, 5)]
+    meshes.append(I.noisy_icosphere(level=6, seed=9))
+    rows = []
+    for m in meshes:
+        V, F, S = to_dev(m)
+        plan = P.Plan(m.n, m.f, m.m, 1e-4)
+        plan.prepare(V, F, S)
+        plain = torch.empty(m.n, device="cuda")
+        warm = torch.empty(m.n, device="cuda")
+        pred = torch.empty(m.n, device="cuda")
+        ms_p = _time(lambda: plan.run(plain))
+        sp = plan.stats()
+
+        def run_warm():
+            plan.warm_predict(params, warm)
+            plan.run_warm(warm, warm)
+
+        ms_w = _time(run_warm)
+        sw = plan.stats()
+        plan.warm_predict(params, pred, inflate=1.0)
+        X, scale = plan.warm_features()
+        d = plain.cpu().numpy().astype(np.float64)
+        w = warm.cpu().numpy().astype(np.float64)
+        pr = pred.cpu().numpy().astype(np.float64)
+        eu = (X[:, 0] * 64 * scale).cpu().numpy().astype(np.float64)
+        mask = np.isfinite(d) & (d > 0)
+        net_err = float(np.mean(np.abs(pr[mask] - d[mask]) / d[mask]))
+        euc_err = float(np.mean(np.abs(eu[mask] - d[mask]) / d[mask]))
+        e, _ = rel_errors(w, d, m.S)
+        rej = sw["certify_rejected"] / max(1, sw["reachable"] - m.m)
+        rows.append((m.name, m.n, sp["iterations"], sw["iterations"], sp["vertex_updates"],
+                     sw["vertex_updates"], ms_p, ms_w, rej, net_err, euc_err))
+        say(f"[gain] {m.name:18s} n={m.n:6d} K {sp['iterations']}->{sw['iterations']} "
+            f"U {sp['vertex_updates']}->{sw['vertex_updates']} ms {ms_p:.3f}->{ms_w:.3f} "
+            f"(x{ms_p / ms_w:.2f}) rejected {rej:.1%} net err {net_err:.2%} "
+            f"euclid err {euc_err:.2%} warm-vs-plain {e:.1e}")
+        assert sw["status"] == P.PTP_OK and e <= 1e-4
+        assert sw["iterations"] <= sp["iterations"]
+        assert net_err < 0.05
+    tot_p = sum(r[6] for r in rows)
+    tot_w = sum(r[7] for r in rows)
+    say(f"[gain] total ms plain {tot_p:.3f} warm {tot_w:.3f} (x{tot_p / tot_w:.2f}); "
+        f"K {sum(r[2] for r in rows)} -> {sum(r[3] for r in rows)}")
