@@ -127,12 +127,16 @@ def bench_warm(obj, n_out, stream, reps):
         rej, reach, rounds = sw["certify_rejected"], sw["reachable"], sw["certify_rounds"]
     p, w = plain.double(), warm.double()
     fin = torch.isfinite(p) & (p > 0)
-    rel = float(((w[fin] - p[fin]).abs() / p[fin]).max())
+    diff = (w[fin] - p[fin]) / p[fin]
+    rel = float(diff.abs().max())
+    lower = float((diff < -1e-4).double().mean())     # warm clearly below (closer to the fixed point)
+    higher = float((diff > 1e-4).double().mean())
     return {"ms_to_converge_plain": round(ms_plain, 3), "ms_to_converge_warm": round(ms_warm, 3),
             "speedup": round(ms_plain / ms_warm, 3), "iterations_plain": kp,
             "iterations_warm": kw, "vertex_updates_plain": int(up), "vertex_updates_warm": int(uw),
             "certify_rejected_frac": round(rej / max(1, reach), 4), "certify_rounds_max": rounds,
-            "max_rel_diff_warm_vs_plain": rel, "inflate": 1.05,
+            "max_rel_diff_warm_vs_plain": rel, "frac_warm_below_plain_1e-4": round(lower, 6),
+            "frac_warm_above_plain_1e-4": round(higher, 6), "inflate": 1.05,
             "timed": f"3 warm-ups, median of {reps}; warm includes features, network and "
                      f"certification"}
 
