@@ -61,6 +61,10 @@ typedef struct {
                                0: unbounded, the paper's rule                  */
     int32_t want_labels;    /* nonzero: compute Voronoi labels                  */
     int32_t workgroups;     /* persistent grid size; 0 -> chosen by the library */
+    int32_t lds_bfs_max;    /* meshes of at most this many vertices run their
+                               BFS in one workgroup with LDS bitmaps: 0 -> as
+                               large as the device's LDS allows, -1 -> never
+                               (tuning only: the toplesets are the same)     */
 } ptp_options;
 
 typedef struct {

@@ -182,6 +182,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(unsigned) * kLine * 2 * G,      // barrier lines
         sizeof(float4) * N,                    // feat
         sizeof(unsigned long long) * 2 * B,    // edge_acc (sums, maxima)
+        sizeof(int) * B,                       // lds_mesh
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -224,6 +225,7 @@ Work carve(void* base, const Layout& L) {
     w.bar = reinterpret_cast<unsigned*>(b + L.off[26]);
     w.feat = reinterpret_cast<float4*>(b + L.off[27]);
     w.edge_acc = reinterpret_cast<unsigned long long*>(b + L.off[28]);
+    w.lds_mesh = reinterpret_cast<int*>(b + L.off[29]);
     return w;
 }
 
@@ -236,7 +238,8 @@ struct Solver {
     Sizes z{};
     ptp_options opt{};
     bool single = false;
-    int device = 0, cus = 0, max_prep = 0, max_run = 0;
+    int device = 0, cus = 0, max_prep = 0, max_run = 0, lds_max = 0;
+    std::vector<int> lds_list, grid_list;   // meshes of the one-workgroup / grid BFS
     ptp_schedule sched{};
     Sched s_prep, s_run;
     Layout layout{};
@@ -267,8 +270,10 @@ struct Solver {
             opt.window = 0;
             opt.want_labels = 0;
             opt.workgroups = 0;
+            opt.lds_bfs_max = 0;
         }
-        if (!(opt.tol > 0.f) || opt.max_iters < 0 || opt.window < 0 || opt.workgroups < 0)
+        if (!(opt.tol > 0.f) || opt.max_iters < 0 || opt.window < 0 || opt.workgroups < 0 ||
+            opt.lds_bfs_max < -1)
             return PTP_EINVAL;
         long long N = 0, F = 0, Sn = 0, W = 0;
         h_vo.assign(1, 0);
@@ -309,6 +314,18 @@ struct Solver {
         if (e != hipSuccess || !coop || cus < 1) return PTP_EDEVICE;
         max_prep = max_coop_blocks_bfs(cus);
         max_run = max_coop_blocks_run(cus, opt.want_labels != 0);
+        lds_max = opt.lds_bfs_max < 0 ? 0 : bfs_lds_max_vertices(device);
+        if (opt.lds_bfs_max > 0) lds_max = std::min(lds_max, opt.lds_bfs_max);
+        long long lds_words = 0;
+        for (int b = 0; b < count; ++b) {
+            if (mesh[b].n <= lds_max) {
+                lds_list.push_back(b);
+                lds_words = std::max<long long>(lds_words, (mesh[b].n + 31) / 32);
+            } else {
+                grid_list.push_back(b);
+            }
+        }
+        z.lds_words = lds_words;
         z.N = N;
         z.F = F;
         z.S = Sn;
@@ -372,10 +389,20 @@ struct Solver {
         stream = static_cast<hipStream_t>(st);
         work = carve(dWork, layout);
         S = dS;
-        std::vector<long long> rho_est(z.B);
-        for (int b = 0; b < z.B; ++b) rho_est[b] = (long long)(2.0 * std::sqrt((double)mesh[b].n)) + 1;
-        s_prep = make_schedule(mesh, rho_est, sched, max_prep, single,
-                               single ? std::min(cus, max_prep) : 0);
+        // the grid BFS takes the meshes too large for one workgroup's LDS
+        s_prep = Sched{};
+        if (!grid_list.empty()) {
+            std::vector<MeshDesc> gm;
+            std::vector<long long> rho_est;
+            for (int b : grid_list) {
+                gm.push_back(mesh[b]);
+                rho_est.push_back((long long)(2.0 * std::sqrt((double)mesh[b].n)) + 1);
+            }
+            s_prep = make_schedule(gm, rho_est, sched, max_prep, grid_list.size() == 1,
+                                   std::min(cus, max_prep));
+            for (size_t x = s_prep.ngroups + 1; x < s_prep.glist.size(); ++x)
+                s_prep.glist[x] = grid_list[s_prep.glist[x]];
+        }
         hstate.assign(z.B, MeshState{});
         hipError_t e = hipMemcpyAsync(work.mesh, mesh.data(), sizeof(MeshDesc) * z.B,
                                       hipMemcpyHostToDevice, stream);
@@ -388,9 +415,12 @@ struct Solver {
         if (e == hipSuccess)
             e = hipMemcpyAsync(work.state, hstate.data(), sizeof(MeshState) * z.B, hipMemcpyHostToDevice,
                                stream);
-        if (e == hipSuccess) e = upload(s_prep, work.wg_prep, work.glist_prep);
+        if (e == hipSuccess && s_prep.G > 0) e = upload(s_prep, work.wg_prep, work.glist_prep);
+        if (e == hipSuccess && !lds_list.empty())
+            e = hipMemcpyAsync(work.lds_mesh, lds_list.data(), sizeof(int) * lds_list.size(),
+                               hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return hip_fail(e, "prepare upload");
-        e = launch_prepare(work, z, dV, dF, dS, s_prep.G, stream);
+        e = launch_prepare(work, z, dV, dF, dS, s_prep.G, (int)lds_list.size(), stream);
         if (e != hipSuccess) return hip_fail(e, "prepare launch");
         e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess)

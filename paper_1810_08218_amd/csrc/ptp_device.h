@@ -64,7 +64,8 @@ __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "me
 //
 // Ordering: each wave waits for its own coherent stores to complete before
 // the workgroup arrives; loads after the barrier are coherent loads issued
-// after the release line was observed.
+// after the release line was observed.  A group of one workgroup needs only
+// that wait and the block barrier (its coherent accesses meet in L2).
 struct FlagBarrier {
     unsigned* flags;     // [gsize * kLine], zero at launch
     unsigned* release;   // one line, zero at launch
@@ -97,6 +98,10 @@ struct FlagBarrier {
         const unsigned tid = threadIdx.x;
         wait_memory();
         bit = __syncthreads_or(bit) ? 1u : 0u;
+        if (gsize == 1) {            // a group of one workgroup: the block barrier suffices
+            *any = bit;
+            return true;
+        }
         epoch += 1;
         if (tid == 0) st_c(flags + (size_t)rank * kLine, (epoch << 1) | bit);
         if (rank == 0) {
@@ -137,11 +142,12 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
     return lo;
 }
 
-// ---- block-wide scans (kBlock threads) ----------------------------------
-// Exclusive prefix of `v` over the workgroup; *total receives the sum.
-template <typename T>
-__device__ inline T block_exclusive_scan(T v, T* total) {
-    __shared__ T warp_sums[kBlock / kWave];
+// ---- block-wide scans --------------------------------------------------
+// Exclusive prefix of `v` over a workgroup of NT threads; *total receives
+// the sum.
+template <int NT, typename T>
+__device__ inline T block_exclusive_scan_n(T v, T* total) {
+    __shared__ T warp_sums[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     T x = v;
@@ -154,7 +160,7 @@ __device__ inline T block_exclusive_scan(T v, T* total) {
     __syncthreads();
     T wbase = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
         T s = warp_sums[w];
         if (w < wid) wbase += s;
         tot += s;
@@ -162,6 +168,11 @@ __device__ inline T block_exclusive_scan(T v, T* total) {
     __syncthreads();
     *total = tot;
     return wbase + x - v;
+}
+
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T* total) {
+    return block_exclusive_scan_n<kBlock>(v, total);
 }
 
 template <typename T>

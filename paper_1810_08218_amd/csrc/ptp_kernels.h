@@ -66,14 +66,16 @@ struct Work {
     unsigned* bar;      // [32 * 2 * gmax] barrier lines: one per workgroup, then one per group
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
+    int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
 };
 
-constexpr int kLayoutParts = 29;
+constexpr int kLayoutParts = 30;
 
 struct Sizes {
     long long N, F, S;      // internal totals over the batch
     int B;                  // meshes
     long long W;            // bitmap words (sum over meshes)
+    long long lds_words;    // largest bitmap (words) among the one-workgroup BFS meshes
     int gmax;               // largest persistent grid
 };
 
@@ -86,8 +88,12 @@ size_t work_layout(const Sizes& z, Layout* L);
 Work carve(void* base, const Layout& L);
 
 // prepare: every kernel after validation is gated on the batch status word
+// n_lds meshes (ids in w.lds_mesh) take the one-workgroup LDS BFS, the
+// others the persistent grid BFS on g_prep workgroups (0: none).
 hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
-                          const int* S, int g_prep, hipStream_t st);
+                          const int* S, int g_prep, int n_lds, hipStream_t st);
+size_t bfs_lds_bytes(long long words);
+int bfs_lds_max_vertices(int device);
 
 // zero the barrier lines (one per workgroup, one per group) of a launch
 void launch_barrier_reset(const Work& w, int lines, hipStream_t st);

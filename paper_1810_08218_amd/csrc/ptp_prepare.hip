@@ -352,6 +352,132 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     }
 }
 
+// ---- BFS of one mesh in one workgroup, bitmaps in LDS --------------------
+// For a mesh whose two n-bit bitmaps fit in LDS, one workgroup of
+// kLdsBlock threads runs the whole BFS with block barriers only: `vis`
+// marks discovered vertices, `nxt` holds the next topleset.  Per level the
+// set bits of `nxt` are compacted in ascending id order (the canonical
+// order: level, then id) straight into perm / iperm / level, and the level's
+// vertices (kept in an LDS list, or read back from perm beyond its capacity)
+// are expanded with LDS atomics deciding the discoverer.  Same outputs as
+// k_bfs for the meshes it is given.
+constexpr int kLdsBlock = 1024;
+constexpr int kLdsList = 4096;
+
+struct BfsLdsArgs {
+    const int* lmesh;      // mesh ids, one per workgroup
+    const MeshDesc* mesh;
+    MeshState* state;
+    const int* S;
+    const int* row;        // rowO
+    const int2* wedgeO;    // global ids
+    int* level;
+    int* perm;
+    int* iperm;
+    int* offsets;
+    int* ctrl;
+};
+
+__global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
+    if (gated(a.ctrl)) return;
+    extern __shared__ unsigned lds[];
+    const int tid = threadIdx.x;
+    const int b = a.lmesh[blockIdx.x];
+    const MeshDesc d = a.mesh[b];
+    const int n = d.n, vo = d.v_off;
+    const int W = (n + 31) / 32;
+    unsigned* vis = lds;
+    unsigned* nxt = lds + W;
+    int* list = reinterpret_cast<int*>(lds + 2 * W);
+    int* offs = a.offsets + vo + b;
+    for (int x = tid; x < 2 * W; x += kLdsBlock) lds[x] = 0u;
+    __syncthreads();
+    unsigned dup = 0;
+    for (int s = tid; s < d.m; s += kLdsBlock) {
+        const int v = a.S[d.s_in + s];
+        const unsigned bit = 1u << (v & 31);
+        if (atomicOr(vis + (v >> 5), bit) & bit) dup = 1;
+        else atomicOr(nxt + (v >> 5), bit);
+    }
+    if (__syncthreads_or(dup)) {
+        if (tid == 0) {
+            atomicOr(&a.state[b].status, ST_DUP_SOURCE);
+            atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
+        }
+        return;
+    }
+    const int q = (W + kLdsBlock - 1) / kLdsBlock;
+    const int my0 = min(tid * q, W), my1 = min(my0 + q, W);
+    int base = 0, r = 0;
+    for (;; ++r) {
+        int pc = 0;
+        for (int x = my0; x < my1; ++x) pc += __popc(nxt[x]);
+        int total;
+        int rank = block_exclusive_scan_n<kLdsBlock>(pc, &total);
+        if (total == 0) break;
+        if (tid == 0) offs[r] = base;
+        for (int x = my0; x < my1; ++x) {
+            unsigned word = nxt[x];
+            nxt[x] = 0u;                       // each word belongs to one thread
+            while (word) {
+                const int u = x * 32 + __ffs(word) - 1;
+                word &= word - 1;
+                const int pos = base + rank;
+                a.perm[vo + pos] = vo + u;
+                a.iperm[vo + u] = vo + pos;
+                a.level[vo + u] = r;
+                if (rank < kLdsList) list[rank] = u;
+                ++rank;
+            }
+        }
+        if (total > kLdsList) wait_memory();   // perm is read back below
+        __syncthreads();
+        for (int t = tid; t < total; t += kLdsBlock) {
+            const int u = t < kLdsList ? list[t] : ld_c(a.perm + vo + base + t) - vo;
+            for (int e = a.row[vo + u]; e < a.row[vo + u + 1]; ++e) {
+                const int2 nb = a.wedgeO[e];
+                const int xs[2] = {nb.x - vo, nb.y - vo};
+                for (int z = 0; z < 2; ++z) {
+                    const int x = xs[z];
+                    const unsigned bit = 1u << (x & 31);
+                    if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit))
+                        atomicOr(nxt + (x >> 5), bit);
+                }
+            }
+        }
+        __syncthreads();
+        base += total;
+    }
+    const int rho = r, reach = base;
+    // unreachable vertices follow in ascending id order, level -1
+    int pc = 0;
+    for (int x = my0; x < my1; ++x) {
+        unsigned word = ~vis[x];
+        if (x == W - 1 && (n & 31)) word &= (1u << (n & 31)) - 1u;
+        pc += __popc(word);
+    }
+    int total;
+    int rank = block_exclusive_scan_n<kLdsBlock>(pc, &total);
+    for (int x = my0; x < my1; ++x) {
+        unsigned word = ~vis[x];
+        if (x == W - 1 && (n & 31)) word &= (1u << (n & 31)) - 1u;
+        while (word) {
+            const int u = x * 32 + __ffs(word) - 1;
+            word &= word - 1;
+            const int pos = reach + rank;
+            a.perm[vo + pos] = vo + u;
+            a.iperm[vo + u] = vo + pos;
+            a.level[vo + u] = -1;
+            ++rank;
+        }
+    }
+    if (tid == 0) {
+        offs[rho] = reach;
+        a.state[b].rho = rho;
+        a.state[b].reach = reach;
+    }
+}
+
 // degree of each position, into rowN[p + 1]
 __global__ __launch_bounds__(kBlock) void k_degree_new(const int* perm, const int* rowO,
                                                        long long N, int* rowN, const int* ctrl) {
@@ -400,7 +526,7 @@ void launch_barrier_reset(const Work& w, int lines, hipStream_t st) {
 }
 
 hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
-                          const int* S, int g_prep, hipStream_t st) {
+                          const int* S, int g_prep, int n_lds, hipStream_t st) {
     const long long N = z.N, F3 = 3 * z.F;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, st, w.ctrl, (long long)C_WORDS, 0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(N + 1)), dim3(kBlock), 0, st, w.rowO, N + 1, 0);
@@ -433,11 +559,30 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     a.cnt = w.cnt;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
-    launch_barrier_reset(w, 2 * g_prep, st);
-    void* args[] = {&a};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_bfs), dim3(g_prep), dim3(kBlock),
-                                   args, 0, st);
-    if (e != hipSuccess) return e;
+    if (n_lds > 0) {
+        BfsLdsArgs l;
+        l.lmesh = w.lds_mesh;
+        l.mesh = w.mesh;
+        l.state = w.state;
+        l.S = S;
+        l.row = w.rowO;
+        l.wedgeO = w.wedgeO;
+        l.level = w.level;
+        l.perm = w.perm;
+        l.iperm = w.iperm;
+        l.offsets = w.offsets;
+        l.ctrl = w.ctrl;
+        hipLaunchKernelGGL(k_bfs_lds, dim3(n_lds), dim3(kLdsBlock), bfs_lds_bytes(z.lds_words), st, l);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (g_prep > 0) {
+        launch_barrier_reset(w, 2 * g_prep, st);
+        void* args[] = {&a};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_bfs), dim3(g_prep), dim3(kBlock),
+                                       args, 0, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_degree_new, dim3(grid_for(N)), dim3(kBlock), 0, st, w.perm, w.rowO, N,
                        w.rowN, w.ctrl);
     e = scan_inplace(w.rowN + 1, N, w.scan_tmp, w.ctrl, st);
@@ -445,6 +590,25 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo,
                        w.perm, w.iperm, w.rowO, w.wedgeO, w.rowN, N, w.xyz, w.wedge, w.ctrl);
     return hipGetLastError();
+}
+
+size_t bfs_lds_bytes(long long words) {
+    return sizeof(unsigned) * (size_t)(2 * words) + sizeof(int) * kLdsList;
+}
+
+// Largest mesh (vertices) the one-workgroup BFS takes on this device, 0 if
+// none; raises the kernel's dynamic LDS limit to what the device allows.
+int bfs_lds_max_vertices(int device) {
+    int smem = 0;
+    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        return 0;
+    const long long avail = (long long)smem - (long long)sizeof(int) * kLdsList - 1024;   // static
+    if (avail <= 0) return 0;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_lds),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(avail + sizeof(int) * kLdsList)) != hipSuccess)
+        return 0;
+    return (int)(avail / 8) * 32;
 }
 
 int max_coop_blocks_bfs(int cus) {

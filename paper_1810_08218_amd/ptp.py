@@ -46,7 +46,8 @@ class PTPError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("tol", C.c_float), ("max_iters", C.c_int32), ("window", C.c_int32),
-                ("want_labels", C.c_int32), ("workgroups", C.c_int32)]
+                ("want_labels", C.c_int32), ("workgroups", C.c_int32),
+                ("lds_bfs_max", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -189,13 +190,13 @@ class Plan:
     workspace tensor; all device memory is torch's."""
 
     def __init__(self, n: int, f: int, m: int, tol: float, max_iters: int = 0, window: int = 0,
-                 want_labels: bool = False, workgroups: int = 0):
+                 want_labels: bool = False, workgroups: int = 0, lds_bfs_max: int = 0):
         lib = load()
         self._lib = lib
         self.n, self.f, self.m = int(n), int(f), int(m)
         self.want_labels = bool(want_labels)
         opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)),
-                      int(workgroups))
+                      int(workgroups), int(lds_bfs_max))
         h = C.c_void_p()
         rc = lib.ptp_plan_create(C.byref(h), self.n, self.f, self.m, C.byref(opt))
         if rc != PTP_OK:
@@ -383,14 +384,15 @@ class Batch:
     gets exactly the result a Plan would give it alone."""
 
     def __init__(self, descs, tol: float, max_iters: int = 0, window: int = 0,
-                 want_labels: bool = False):
+                 want_labels: bool = False, lds_bfs_max: int = 0):
         lib = load()
         self._lib = lib
         self.count = len(descs)
         self._descs = (MeshDesc * self.count)(*descs)
         self.out_len = max(int(d.out_off) + int(d.n_vertices) for d in descs)
         self.want_labels = bool(want_labels)
-        opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)), 0)
+        opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)), 0,
+                      int(lds_bfs_max))
         h = C.c_void_p()
         rc = lib.ptp_batch_create(C.byref(h), self._descs, self.count, C.byref(opt))
         if rc != PTP_OK:

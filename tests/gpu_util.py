@@ -26,13 +26,14 @@ class GpuResult:
     pass
 
 
-def gpu_run(mesh, tol, labels=False, workgroups=0, max_iters=0, window=0, want_order=True):
+def gpu_run(mesh, tol, labels=False, workgroups=0, max_iters=0, window=0, want_order=True,
+            lds_bfs_max=0):
     import torch
     say(f"[gpu] {mesh.name} n={mesh.n} f={mesh.f} m={mesh.m} tol={tol} labels={labels} "
-        f"wg={workgroups} max_iters={max_iters} window={window}")
+        f"wg={workgroups} max_iters={max_iters} window={window} lds_bfs_max={lds_bfs_max}")
     V, F, S = to_dev(mesh)
     plan = P.Plan(mesh.n, mesh.f, mesh.m, tol, max_iters=max_iters, window=window,
-                  want_labels=labels, workgroups=workgroups)
+                  want_labels=labels, workgroups=workgroups, lds_bfs_max=lds_bfs_max)
     plan.prepare(V, F, S)
     dist = torch.empty(mesh.n, dtype=torch.float32, device="cuda")
     lab = torch.empty(mesh.n, dtype=torch.int32, device="cuda") if labels else None

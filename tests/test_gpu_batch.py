@@ -126,6 +126,26 @@ def test_results_independent_of_schedule_and_autotune(cuda):
     assert np.array_equal(dist.cpu().numpy(), rd) and np.array_equal(lab.cpu().numpy(), rl)
 
 
+def test_batch_bfs_paths_agree(cuda):
+    """Meshes split between the one-workgroup LDS BFS and the grid BFS (by a
+    vertex limit) give the results of either path alone."""
+    import torch
+    meshes, share = small_batch()
+    ref = run_batch(meshes, share, 1e-4)
+    rd, rl = ref[1].cpu().numpy(), ref[2].cpu().numpy()
+    V, F, S, descs, out_len = P.concat(meshes, share)
+    dV, dF, dS = (torch.from_numpy(x).cuda() for x in (V, F, S))
+    for lim in (-1, 1000, 5000):
+        b = P.Batch(descs, 1e-4, want_labels=True, lds_bfs_max=lim)
+        b.prepare(dV, dF, dS)
+        dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
+        lab = torch.empty(out_len, dtype=torch.int32, device="cuda")
+        b.run(dist, lab)
+        rc, stats, status = b.stats()
+        assert rc == P.PTP_OK, lim
+        assert np.array_equal(dist.cpu().numpy(), rd) and np.array_equal(lab.cpu().numpy(), rl), lim
+
+
 def test_invalid_mesh_in_batch(cuda):
     import torch
     meshes, share = small_batch()

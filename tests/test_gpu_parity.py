@@ -120,6 +120,27 @@ def test_toplesets_and_order_bit_exact(cuda, mesh):
     assert np.array_equal(g.offsets, offsets)
 
 
+def _many_sources():
+    """A level 0 of 5,000 vertices: more than the one-workgroup BFS keeps in
+    its LDS list, so the level is read back from the permutation."""
+    g = I.flat_grid(128)
+    S = np.sort(np.random.default_rng(3).choice(g.n, 5000, replace=False)).astype(np.int32)
+    return I.Mesh(g.V, g.F, S, name="grid128_5000_sources")
+
+
+@pytest.mark.parametrize("mesh", _order_cases() + [_many_sources()], ids=lambda m: m.name)
+def test_bfs_paths_agree(cuda, mesh):
+    """The one-workgroup LDS BFS and the persistent grid BFS give the same
+    toplesets, order and distances (and both match the oracle)."""
+    a = gpu_run(mesh, 1e-4, labels=True, lds_bfs_max=0)
+    b = gpu_run(mesh, 1e-4, labels=True, lds_bfs_max=-1)
+    assert np.array_equal(a.perm, b.perm) and np.array_equal(a.offsets, b.offsets)
+    assert np.array_equal(a.dist, b.dist) and np.array_equal(a.label, b.label)
+    assert (a.iterations, a.updates) == (b.iterations, b.updates)
+    level, order, offsets, rho = O.toplesets(mesh.V, mesh.F, mesh.S)
+    assert np.array_equal(a.perm, order) and np.array_equal(a.offsets, offsets)
+
+
 def test_parity_flat_grid_64(cuda):
     check_parity(cuda, I.flat_grid(64), 1e-6)
 
@@ -208,10 +229,11 @@ def test_invalid_inputs_are_rejected(cuda):
     with pytest.raises(P.PTPError) as e:
         plan.prepare(V, F, torch.tensor([m.n], dtype=torch.int32, device="cuda"))
     assert e.value.status == P.PTP_EINVAL
-    plan2 = P.Plan(m.n, m.f, 2, 1e-4)
-    with pytest.raises(P.PTPError) as e:
-        plan2.prepare(V, F, torch.tensor([4, 4], dtype=torch.int32, device="cuda"))
-    assert e.value.status == P.PTP_EINVAL
+    for lds in (0, -1):                  # duplicate source, both BFS paths
+        plan2 = P.Plan(m.n, m.f, 2, 1e-4, lds_bfs_max=lds)
+        with pytest.raises(P.PTPError) as e:
+            plan2.prepare(V, F, torch.tensor([4, 4], dtype=torch.int32, device="cuda"))
+        assert e.value.status == P.PTP_EINVAL
     with pytest.raises(P.PTPError):
         plan2.run(torch.empty(m.n, device="cuda"))
     # the plan stays usable after an error
