@@ -166,6 +166,9 @@ typedef struct {
     int32_t large_limit;
     int32_t medium_group;
     int32_t large_group;
+    int32_t xcd_pack;       /* 1: place each group's workgroups on one XCD
+                               where it fits (launch index i runs on XCD
+                               i mod 8); -1: consecutive indices           */
 } ptp_schedule;
 
 typedef struct ptp_batch ptp_batch;

@@ -207,6 +207,7 @@ struct BfsArgs {
 __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     if (gated(a.ctrl)) return;
     const WgInfo me = a.wg[blockIdx.x];
+    if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize, w = me.rank, tid = threadIdx.x;
     FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)w, 0};

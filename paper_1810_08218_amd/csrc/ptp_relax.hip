@@ -180,6 +180,7 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
 template <bool LABELS, bool WARM>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
+    if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize;
     FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)me.rank, 0};

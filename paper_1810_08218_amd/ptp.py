@@ -72,7 +72,7 @@ class Schedule(C.Structure):
     """Work distribution of a batch (ptp_schedule); 0 fields = defaults."""
     _fields_ = [("workgroups", C.c_int32), ("small_limit", C.c_int32),
                 ("large_limit", C.c_int32), ("medium_group", C.c_int32),
-                ("large_group", C.c_int32)]
+                ("large_group", C.c_int32), ("xcd_pack", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
