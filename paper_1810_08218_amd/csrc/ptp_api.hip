@@ -356,7 +356,7 @@ struct Solver {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
         if (e != hipSuccess || !coop || cus < 1) return PTP_EDEVICE;
         max_prep = max_coop_blocks_bfs(cus);
-        max_run = max_coop_blocks_run(cus, opt.want_labels != 0);
+        max_run = max_coop_blocks_run(cus, opt.want_labels != 0, single);
         lds_max = opt.lds_bfs_max < 0 ? 0 : bfs_lds_max_vertices(device);
         if (opt.lds_bfs_max > 0) lds_max = std::min(lds_max, opt.lds_bfs_max);
         long long lds_words = 0;
@@ -518,7 +518,7 @@ struct Solver {
         rp.upper = dUpper;
         rp.out_d = dDist;
         rp.out_l = labels ? dLabel : nullptr;
-        hipError_t e = launch_run(work, rp, labels, s_run.G, stream);
+        hipError_t e = launch_run(work, rp, labels, single, s_run.G, stream);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         ran = true;
         return PTP_OK;

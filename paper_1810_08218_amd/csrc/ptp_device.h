@@ -52,23 +52,25 @@ __device__ inline void st_c(T* p, T v) {
 __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // ---- group barrier -----------------------------------------------------
-// Flag-array barrier among the gsize consecutive workgroups of a group of a
-// cooperative launch.  Every workgroup publishes (epoch << 1 | bit) in its
-// own 128-byte line; the group's first workgroup polls all lines with its 256
-// threads, ORs the bits and publishes (epoch << 1 | any) in the group's
-// release line, which the others poll.  No counter is contended, so the cost
-// barely grows with the group.  The bit carries a vote (the "not converged"
-// vote of the PTP iteration, a duplicate source in the BFS).  A wall-clock
-// limit turns a barrier that can never complete into an abort flag instead
-// of a hang.
+// Flag-array barrier among the gsize workgroups of a group of a cooperative
+// launch.  Every workgroup publishes (epoch << 1 | bit) in its own 128-byte
+// line and then polls every line of the group (one line per thread), so a
+// barrier costs one store-to-load hop; the OR of the bits (the "not
+// converged" vote of the PTP iteration, a duplicate source in the BFS) comes
+// out the same in every workgroup.  The lines of consecutive epochs
+// alternate between two banks: a workgroup may already publish epoch e + 1
+// while a slower one still reads epoch e, but it cannot reach e + 2 before
+// every workgroup has published e + 1, that is, finished reading e.  No
+// counter is contended.  A wall-clock limit turns a barrier that can never
+// complete into an abort flag instead of a hang.
 //
 // Ordering: each wave waits for its own coherent stores to complete before
-// the workgroup arrives; loads after the barrier are coherent loads issued
-// after the release line was observed.  A group of one workgroup needs only
-// that wait and the block barrier (its coherent accesses meet in L2).
+// the workgroup publishes; loads after the barrier are coherent loads issued
+// after every flag was observed.  A group of one workgroup needs only that
+// wait and the block barrier (its coherent accesses meet in L2).
 struct FlagBarrier {
-    unsigned* flags;     // [gsize * kLine], zero at launch
-    unsigned* release;   // one line, zero at launch
+    unsigned* bank0;     // [gsize * kLine], zero at launch: even epochs
+    unsigned* bank1;     // [gsize * kLine], zero at launch: odd epochs
     int* abort_flag;
     unsigned gsize, rank;
     unsigned epoch;
@@ -93,8 +95,6 @@ struct FlagBarrier {
     // Returns false when the barrier timed out (the kernel must exit);
     // *any receives the OR of `bit` over the group.
     __device__ bool sync(unsigned bit, unsigned* any) {
-        __shared__ unsigned s_any;
-        __shared__ int s_ok;
         const unsigned tid = threadIdx.x;
         wait_memory();
         bit = __syncthreads_or(bit) ? 1u : 0u;
@@ -103,30 +103,21 @@ struct FlagBarrier {
             return true;
         }
         epoch += 1;
-        if (tid == 0) st_c(flags + (size_t)rank * kLine, (epoch << 1) | bit);
-        if (rank == 0) {
-            unsigned acc = 0;
-            int ok = 1;
-            for (unsigned x = tid; x < gsize; x += kBlock) {
-                unsigned v;
-                if (!spin_ge(flags + (size_t)x * kLine, epoch, &v)) {
-                    ok = 0;
-                    break;
-                }
-                acc |= v & 1u;
+        unsigned* lines = (epoch & 1u) ? bank1 : bank0;
+        if (tid == 0) st_c(lines + (size_t)rank * kLine, (epoch << 1) | bit);
+        unsigned acc = 0;
+        int ok = 1;
+        for (unsigned x = tid; x < gsize; x += blockDim.x) {
+            unsigned v;
+            if (!spin_ge(lines + (size_t)x * kLine, epoch, &v)) {
+                ok = 0;
+                break;
             }
-            acc = __syncthreads_or(acc) ? 1u : 0u;
-            ok = __syncthreads_and(ok);
-            if (tid == 0 && ok) st_c(release, (epoch << 1) | acc);
+            acc |= v & 1u;
         }
-        if (tid == 0) {
-            unsigned v = 0;
-            s_ok = spin_ge(release, epoch, &v) ? 1 : 0;
-            s_any = v & 1u;
-        }
-        __syncthreads();
-        *any = s_any;
-        return s_ok && ld_c(abort_flag) == 0;
+        *any = __syncthreads_or(acc) ? 1u : 0u;
+        ok = __syncthreads_and(ok);
+        return ok && ld_c(abort_flag) == 0;
     }
 };
 

@@ -63,7 +63,7 @@ struct Work {
     int* cnt;           // [4 * gmax] per-workgroup chunk counts
     int* retire;        // [N]     last iteration that updated each topleset, mesh b at v_off_b
     int* scan_tmp;      // block sums of the scans
-    unsigned* bar;      // [32 * 2 * gmax] barrier lines: one per workgroup, then one per group
+    unsigned* bar;      // [32 * 2 * gmax] barrier lines: two banks of one line per workgroup
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
@@ -95,7 +95,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
 size_t bfs_lds_bytes(long long words);
 int bfs_lds_max_vertices(int device);
 
-// zero the barrier lines (one per workgroup, one per group) of a launch
+// zero the barrier lines (two banks of one per workgroup) of a launch
 void launch_barrier_reset(const Work& w, int lines, hipStream_t st);
 
 struct RunParams {
@@ -108,7 +108,9 @@ struct RunParams {
     int* out_l;
 };
 
-hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st);
+// cache: use the register-caching relaxation (single meshes)
+hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, int g_run,
+                      hipStream_t st);
 
 // learned warm start
 hipError_t launch_features(const Work& w, const Sizes& z, hipStream_t st);
@@ -124,6 +126,6 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
 size_t mlp_scratch_bytes();
 
 int max_coop_blocks_bfs(int cus);
-int max_coop_blocks_run(int cus, bool labels);
+int max_coop_blocks_run(int cus, bool labels, bool cache);
 
 }  // namespace ptp

@@ -192,6 +192,8 @@ struct BfsArgs {
     unsigned* bar;
 };
 
+constexpr int kExpandG = 6;    // wedges loaded together per expanded vertex
+
 // One group handles one mesh at a time.  The mesh's bitmap of V_r is split
 // into gsize equal chunks of words, one per workgroup of the group.  Per
 // level r, each workgroup
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize, w = me.rank, tid = threadIdx.x;
-    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
+    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.first) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)w, 0};
     unsigned any = 0;
     const long long gsz = (long long)gs * kBlock;
@@ -301,12 +303,24 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                 const int lvl = r + 1;
                 for (int t = tid; t < cntl; t += kBlock) {
                     const int u = vo + list[t];
-                    for (int e = a.row[u]; e < a.row[u + 1]; ++e) {
-                        const int2 nb = a.wedgeO[e];
-                        const int xs[2] = {nb.x, nb.y};
-                        for (int z = 0; z < 2; ++z) {
-                            const int x = xs[z];
-                            if (ld_c(a.level + x) < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
+                    const int e0 = a.row[u], e1 = a.row[u + 1];
+                    for (int eb = e0; eb < e1; eb += kExpandG) {
+                        // wedges, then their neighbours' levels (independent
+                        // loads), then a CAS for the unvisited ones
+                        const int cnt = min(kExpandG, e1 - eb);
+                        int2 nb[kExpandG];
+                        int lv[2 * kExpandG];
+#pragma unroll
+                        for (int q = 0; q < kExpandG; ++q) nb[q] = q < cnt ? a.wedgeO[eb + q] : make_int2(u, u);
+#pragma unroll
+                        for (int q = 0; q < kExpandG; ++q) {
+                            lv[2 * q] = ld_c(a.level + nb[q].x);
+                            lv[2 * q + 1] = ld_c(a.level + nb[q].y);
+                        }
+#pragma unroll
+                        for (int q = 0; q < 2 * kExpandG; ++q) {
+                            const int x = (q & 1) ? nb[q >> 1].y : nb[q >> 1].x;
+                            if (lv[q] < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
                                 const int xl = x - vo;
                                 atomicOr(nxt + (xl >> 5), 1u << (xl & 31));
                                 atomicAdd(cn + (xl >> 5) / cw, 1);
@@ -364,6 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
 // k_bfs for the meshes it is given.
 constexpr int kLdsBlock = 1024;
 constexpr int kLdsList = 4096;
+constexpr int kExpand = 8;     // wedges loaded together per expanded vertex
 
 struct BfsLdsArgs {
     const int* lmesh;      // mesh ids, one per workgroup
@@ -435,14 +450,22 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
         __syncthreads();
         for (int t = tid; t < total; t += kLdsBlock) {
             const int u = t < kLdsList ? list[t] : ld_c(a.perm + vo + base + t) - vo;
-            for (int e = a.row[vo + u]; e < a.row[vo + u + 1]; ++e) {
-                const int2 nb = a.wedgeO[e];
-                const int xs[2] = {nb.x - vo, nb.y - vo};
-                for (int z = 0; z < 2; ++z) {
-                    const int x = xs[z];
-                    const unsigned bit = 1u << (x & 31);
-                    if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit))
-                        atomicOr(nxt + (x >> 5), bit);
+            const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
+            for (int eb = e0; eb < e1; eb += kExpand) {
+                // the wedges' loads first (independent), then the LDS marks
+                const int cnt = min(kExpand, e1 - eb);
+                int2 nb[kExpand];
+#pragma unroll
+                for (int q = 0; q < kExpand; ++q) nb[q] = q < cnt ? a.wedgeO[eb + q] : make_int2(vo + u, vo + u);
+#pragma unroll
+                for (int q = 0; q < kExpand; ++q) {
+                    const int xs[2] = {nb[q].x - vo, nb[q].y - vo};
+                    for (int z = 0; z < 2; ++z) {
+                        const int x = xs[z];
+                        const unsigned bit = 1u << (x & 31);
+                        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit))
+                            atomicOr(nxt + (x >> 5), bit);
+                    }
                 }
             }
         }

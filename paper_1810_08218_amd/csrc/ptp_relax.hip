@@ -124,10 +124,43 @@ struct RelaxArgs {
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
-// Smallest planar update of position v over its incident triangles, reading
-// distances (and labels) from dold / lold: first up to kChunk wedges, then
-// every neighbour distance and coordinate of those wedges at once
-// (independent loads), then the updates.  (value, label) lexicographic min.
+// Smallest planar update over the given wedges of a vertex at x0 (cnt <= C
+// valid entries), reading distances (and labels) from dold / lold: every
+// neighbour distance and coordinate at once (independent loads), then the
+// updates.  (value, label) lexicographic minimum folded into best / bl.
+template <bool LABELS, int C>
+__device__ inline void eval_wedges(const RelaxArgs& a, const float4 x0, const int2* wv, int cnt,
+                                   const float* dold, const int* lold, float& best, int& bl) {
+    float da[C], db[C];
+    float4 xa[C], xb[C];
+    int la[C], lb[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        da[q] = ld_c(dold + wv[q].x);
+        db[q] = ld_c(dold + wv[q].y);
+        xa[q] = a.xyz[wv[q].x];
+        xb[q] = a.xyz[wv[q].y];
+        if (LABELS) {
+            la[q] = ld_c(lold + wv[q].x);
+            lb[q] = ld_c(lold + wv[q].y);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        if (q < cnt && fminf(da[q], db[q]) < kInf) {
+            int l = 0;
+            const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
+                                                 LABELS ? lb[q] : 0, l);
+            if (u < best || (LABELS && u == best && l < bl)) {
+                best = u;
+                bl = l;
+            }
+        }
+    }
+}
+
+// Smallest planar update of position v over all its incident triangles,
+// kChunk wedges at a time (their ids first, then their data).
 template <bool LABELS, int kChunk>
 __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const float* dold,
                                    const int* lold, float& best, int& bl) {
@@ -137,34 +170,9 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
     for (int base = e0; base < e1; base += kChunk) {
         const int cnt = min(kChunk, e1 - base);
         int2 wv[kChunk];
-        float da[kChunk], db[kChunk];
-        float4 xa[kChunk], xb[kChunk];
-        int la[kChunk], lb[kChunk];
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
-#pragma unroll
-        for (int q = 0; q < kChunk; ++q) {
-            da[q] = ld_c(dold + wv[q].x);
-            db[q] = ld_c(dold + wv[q].y);
-            xa[q] = a.xyz[wv[q].x];
-            xb[q] = a.xyz[wv[q].y];
-            if (LABELS) {
-                la[q] = ld_c(lold + wv[q].x);
-                lb[q] = ld_c(lold + wv[q].y);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kChunk; ++q) {
-            if (q < cnt && fminf(da[q], db[q]) < kInf) {
-                int l = 0;
-                const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
-                                                     LABELS ? lb[q] : 0, l);
-                if (u < best || (LABELS && u == best && l < bl)) {
-                    best = u;
-                    bl = l;
-                }
-            }
-        }
+        eval_wedges<LABELS, kChunk>(a, x0, wv, cnt, dold, lold, best, bl);
     }
 }
 
@@ -177,12 +185,12 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
 // wedges, then every neighbour distance and coordinate of those wedges at
 // once (independent loads), then evaluates the planar updates.  Distances and
 // labels are exchanged between workgroups through coherent loads and stores.
-template <bool LABELS, bool WARM>
+template <bool LABELS, bool WARM, bool CACHE>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize;
-    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.group) * kLine,
+    FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.first) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)me.rank, 0};
     unsigned any = 0;
     const long long gsz = (long long)gs * kBlock;
@@ -272,6 +280,15 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
         int i = 1, lo_prev = 1, k = 0, runstat = 0;
         long long upd = 0;
+        // CACHE: the incidence of the vertex this thread handled last.  While
+        // the band is no wider than the group's threads, a band vertex keeps
+        // its thread for every iteration it spends in the band, so after its
+        // first update only the neighbour distances are loaded.  (Costs
+        // registers, hence occupancy: used for single meshes.)
+        constexpr int kCache = kChunk;
+        int cv = -1, ccnt = 0;
+        float4 cx0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        int2 cw[kCache];
         while (i < rho) {
             if (k >= kmax) {
                 runstat = 1;
@@ -298,11 +315,27 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     if (LABELS) st_c(lnew + v, ld_c(lold + v));
                     continue;
                 }
-                const float4 x0 = a.xyz[v];
+                const bool cached = CACHE && be - cb <= gsz;   // one position per thread
+                if (cached && v != cv) {        // a vertex new to this thread
+                    cx0 = a.xyz[v];
+                    const int e0 = a.row[v];
+                    ccnt = a.row[v + 1] - e0;
+                    cv = ccnt <= kCache ? v : -1;
+                    if (cv >= 0) {
+#pragma unroll
+                        for (int q = 0; q < kCache; ++q)
+                            cw[q] = q < ccnt ? a.wedge[e0 + q] : make_int2(v, v);
+                    }
+                }
                 const float dv = ld_c(dold + v);
-                float best;
-                int bl;
-                best_update<LABELS, WARM ? 4 : kChunk>(a, v, x0, dold, lold, best, bl);
+                float best = kInf;
+                int bl = 0x7fffffff;
+                if (cached && cv == v) {
+                    eval_wedges<LABELS, kCache>(a, cx0, cw, ccnt, dold, lold, best, bl);
+                } else {
+                    const float4 x0 = cached ? cx0 : a.xyz[v];
+                    best_update<LABELS, WARM ? 4 : kChunk>(a, v, x0, dold, lold, best, bl);
+                }
                 float dn = dv;
                 if (best < dv) {
                     dn = best;
@@ -359,7 +392,8 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
 
 }  // namespace
 
-hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run, hipStream_t st) {
+hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, int g_run,
+                      hipStream_t st) {
     hipLaunchKernelGGL(k_run_reset, dim3((p.B + 255) / 256), dim3(256), 0, st, w.ctrl, w.state, p.B);
     launch_barrier_reset(w, 2 * g_run, st);
     RelaxArgs a;
@@ -388,23 +422,32 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, int g_run,
     a.out_d = p.out_d;
     a.out_l = p.out_l;
     void* args[] = {&a};
-    const void* fn = labels    ? reinterpret_cast<const void*>(&k_relax<true, false>)
-                     : p.upper ? reinterpret_cast<const void*>(&k_relax<false, true>)
-                               : reinterpret_cast<const void*>(&k_relax<false, false>);
+    const void* fn;
+    if (labels)
+        fn = cache ? reinterpret_cast<const void*>(&k_relax<true, false, true>)
+                   : reinterpret_cast<const void*>(&k_relax<true, false, false>);
+    else if (p.upper)
+        fn = reinterpret_cast<const void*>(&k_relax<false, true, false>);
+    else
+        fn = cache ? reinterpret_cast<const void*>(&k_relax<false, false, true>)
+                   : reinterpret_cast<const void*>(&k_relax<false, false, false>);
     return hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
 }
 
 // Co-resident workgroups of the relaxation kernels a plan may launch: the
-// labelled one, or (without labels) the plain and the warm-start one.
-int max_coop_blocks_run(int cus, bool labels) {
-    int nb = 0, nw = 0;
+// labelled one, or (without labels) the plain and the warm-start one; with
+// `cache`, the register-caching variants instead of the plain ones.
+int max_coop_blocks_run(int cus, bool labels, bool cache) {
+    int nb = 0, nw = 1 << 20;
     hipError_t e;
     if (labels) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false>, kBlock, 0);
-        nw = nb;
+        e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false, true>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false, false>, kBlock, 0);
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false>, kBlock, 0);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true>, kBlock, 0);
+        e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, true>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, false>, kBlock, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, false>, kBlock, 0);
     }
     nb = std::min(nb, nw);
     if (e != hipSuccess || nb < 1) nb = 1;
