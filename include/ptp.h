@@ -166,9 +166,11 @@ typedef struct {
     int32_t large_limit;
     int32_t medium_group;
     int32_t large_group;
-    int32_t xcd_pack;       /* 1: place each group's workgroups on one XCD
-                               where it fits (launch index i runs on XCD
-                               i mod 8); -1: consecutive indices           */
+    int32_t xcd_pack;       /* > 0: place each group of at most max(32,
+                               xcd_pack) workgroups on one XCD (launch
+                               index i runs on XCD i mod 8; such a group
+                               then exchanges its data through that XCD's
+                               L2); -1: consecutive indices                */
 } ptp_schedule;
 
 typedef struct ptp_batch ptp_batch;

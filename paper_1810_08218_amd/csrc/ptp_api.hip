@@ -155,8 +155,9 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
         s.G = first;
         return s;
     }
-    constexpr int kXcd = 8, kXcdGroup = 32;
+    constexpr int kXcd = 8;
     const int cap = std::max(1, gmax / kXcd);
+    const int xcd_group = p.xcd_pack > 1 ? p.xcd_pack : 32;
     int used[kXcd] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<int> ord(s.ngroups);
     for (int g = 0; g < s.ngroups; ++g) ord[g] = g;
@@ -172,7 +173,7 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
         int best = 0;
         for (int x = 1; x < kXcd; ++x)
             if (used[x] < used[best]) best = x;
-        if (gsz[g] <= kXcdGroup && used[best] + gsz[g] <= cap) {
+        if (gsz[g] <= xcd_group && used[best] + gsz[g] <= cap) {
             for (int r = 0; r < gsz[g]; ++r) put(best, WgInfo{g, r, gsz[g], firsts[g]});
         } else {
             for (int r = 0; r < gsz[g]; ++r) {
@@ -399,18 +400,20 @@ struct Solver {
             if (s->large_limit > 0) d.large_limit = s->large_limit;
             if (s->medium_group > 0) d.medium_group = s->medium_group;
             if (s->large_group > 0) d.large_group = s->large_group;
-            if (s->xcd_pack != 0) d.xcd_pack = s->xcd_pack > 0 ? 1 : 0;
+            if (s->xcd_pack != 0) d.xcd_pack = s->xcd_pack > 0 ? s->xcd_pack : 0;
         }
         sched = d;
     }
 
     // Single mesh: one group; about one workgroup per 1024 reachable vertices
     // within [16, 512] (the per-iteration cost is flat from ~n/2048 to ~n/512
-    // workgroups on the icosphere workloads and rises outside).
+    // workgroups on the icosphere workloads and rises outside).  Up to ~48
+    // of them, 32 workgroups placed on one XCD do better (the group then
+    // exchanges its data through one L2).
     int single_group(int gmax, long long reach) const {
         if (opt.workgroups > 0) return std::min(opt.workgroups, gmax);
         long long g = reach / 1024;
-        g = std::max(16ll, std::min(512ll, g));
+        g = g <= 48 ? 32 : std::min(512ll, g);
         return (int)std::min<long long>(g, gmax);
     }
 

@@ -47,6 +47,24 @@ template <typename T>
 __device__ inline void st_c(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Store for data shared inside a group.  When every workgroup of the group
+// runs on one XCD (`local`), a plain store suffices: it writes through the
+// CU's L1 into the XCD's L2, where the readers' coherent loads find it; an
+// agent-scope store has to travel to memory, which costs several times more
+// when it follows coherent loads of the same lines.  Otherwise agent scope.
+template <typename T>
+__device__ inline void st_g(T* p, T v, bool local) {
+    if (local) *p = v;
+    else st_c(p, v);
+}
+
+// Index of the XCD (accelerator complex die) this workgroup runs on.
+__device__ inline unsigned xcc_id() {
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xfu;
+}
 // Wait until this wave's outstanding memory operations have completed.  Also
 // a compiler barrier: no access moves across it.
 __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -62,7 +80,10 @@ __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "me
 // while a slower one still reads epoch e, but it cannot reach e + 2 before
 // every workgroup has published e + 1, that is, finished reading e.  No
 // counter is contended.  A wall-clock limit turns a barrier that can never
-// complete into an abort flag instead of a hang.
+// complete into an abort flag instead of a hang: the workgroups whose wait
+// times out raise the flag and leave; the flag is not read on the way (every
+// workgroup of a stuck group times out by itself), which saves a memory
+// round trip per barrier.
 //
 // Ordering: each wave waits for its own coherent stores to complete before
 // the workgroup publishes; loads after the barrier are coherent loads issued
@@ -74,6 +95,7 @@ struct FlagBarrier {
     int* abort_flag;
     unsigned gsize, rank;
     unsigned epoch;
+    bool local = false;  // the whole group runs on one XCD: plain flag stores
 
     static constexpr long long kTimeoutTicks = 400000000ll;   // seconds at 100 MHz
 
@@ -104,7 +126,7 @@ struct FlagBarrier {
         }
         epoch += 1;
         unsigned* lines = (epoch & 1u) ? bank1 : bank0;
-        if (tid == 0) st_c(lines + (size_t)rank * kLine, (epoch << 1) | bit);
+        if (tid == 0) st_g(lines + (size_t)rank * kLine, (epoch << 1) | bit, local);
         unsigned acc = 0;
         int ok = 1;
         for (unsigned x = tid; x < gsize; x += blockDim.x) {
@@ -117,7 +139,7 @@ struct FlagBarrier {
         }
         *any = __syncthreads_or(acc) ? 1u : 0u;
         ok = __syncthreads_and(ok);
-        return ok && ld_c(abort_flag) == 0;
+        return ok;   // a timed-out wait raised the abort flag itself
     }
 };
 

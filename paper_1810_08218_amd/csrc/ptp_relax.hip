@@ -102,6 +102,7 @@ struct RelaxArgs {
     const int* glist;      // per group: starts [ngroups + 1], then mesh ids
     const int* S;
     const float* upper;    // warm start: caller-order upper bound, or null
+    int* xpost;            // [G] XCD of each workgroup (scratch)
     const int* perm;
     const int* iperm;
     const int* offsets;
@@ -201,6 +202,20 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     int* lA = a.lab;
     int* lB = a.lab + a.N;
 
+    // A group whose workgroups all run on one XCD exchanges its data through
+    // that XCD's L2 with plain stores.  Every workgroup posts its XCD, the
+    // group syncs, and each compares all posts, so all agree on the mode.
+    bool local = true;
+    if (gs > 1) {
+        if (threadIdx.x == 0) st_c(a.xpost + me.first + me.rank, (int)xcc_id());
+        if (!gb.sync(0, &any)) return;
+        const int x0 = ld_c(a.xpost + me.first);
+        int same = 1;
+        for (int x = threadIdx.x; x < gs; x += kBlock) same &= ld_c(a.xpost + me.first + x) == x0;
+        local = __syncthreads_and(same) != 0;
+    }
+    gb.local = local;
+
     const int* lst = a.glist + a.glist[me.group];
     const int nlst = a.glist[me.group + 1] - a.glist[me.group];
     for (int li = 0; li < nlst; ++li) {
@@ -221,18 +236,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 const float w = a.upper[md.out_off + (v - vo)];
                 d = w >= 0.f ? w : kInf;                 // NaN or negative: no bound
             }
-            st_c(dA + vo + p, d);
-            st_c(dB + vo + p, d);
+            st_g(dA + vo + p, d, local);
+            st_g(dB + vo + p, d, local);
             if (LABELS && p >= m0) {
-                st_c(lA + vo + p, -1);
-                st_c(lB + vo + p, -1);
+                st_g(lA + vo + p, -1, local);
+                st_g(lB + vo + p, -1, local);
             }
         }
         if (LABELS)
             for (long long s = g0; s < md.m; s += gsz) {
                 const int p = a.iperm[vo + a.S[md.s_in + s]];
-                st_c(lA + p, (int)s);
-                st_c(lB + p, (int)s);
+                st_g(lA + p, (int)s, local);
+                st_g(lB + p, (int)s, local);
             }
         for (long long r = g0; r < rho; r += gsz) retire[r] = r == 0 ? 0 : -1;
         if (!gb.sync(0, &any)) return;
@@ -257,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     int ul;
                     best_update<false, 4>(a, v, a.xyz[v], dA, nullptr, u, ul);
                     if (w < u) {
-                        st_c(dA + v, kInf);
+                        st_g(dA + v, kInf, local);
                         changed = 1;
                         ++rejected;
                     }
@@ -265,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 if (!gb.sync(changed, &any)) return;
                 if (!any) break;
                 if (round == kCertifyRounds) {           // no closure in time: no bound
-                    for (long long pp = firstc; pp < reach; pp += gsz) st_c(dA + vo + pp, kInf);
+                    for (long long pp = firstc; pp < reach; pp += gsz) st_g(dA + vo + pp, kInf, local);
                     if (!gb.sync(0, &any)) return;
                     rejected = 0;
                     if (leader) rejected = reach - m0;
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             }
             if (rejected) atomicAdd(&a.state[b].cert_rejected, rejected);
             if (leader) a.state[b].cert_rounds = round + 1;
-            for (long long pp = firstc; pp < reach; pp += gsz) st_c(dB + vo + pp, ld_c(dA + vo + pp));
+            for (long long pp = firstc; pp < reach; pp += gsz) st_g(dB + vo + pp, ld_c(dA + vo + pp), local);
             if (!gb.sync(0, &any)) return;
         }
 
@@ -311,8 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             for (long long pp = first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    st_c(dnew + v, ld_c(dold + v));
-                    if (LABELS) st_c(lnew + v, ld_c(lold + v));
+                    st_g(dnew + v, ld_c(dold + v), local);
+                    if (LABELS) st_g(lnew + v, ld_c(lold + v), local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -339,11 +354,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 float dn = dv;
                 if (best < dv) {
                     dn = best;
-                    if (LABELS) st_c(lnew + v, bl);
+                    if (LABELS) st_g(lnew + v, bl, local);
                 } else if (LABELS) {
-                    st_c(lnew + v, ld_c(lold + v));
+                    st_g(lnew + v, ld_c(lold + v), local);
                 }
-                st_c(dnew + v, dn);
+                st_g(dnew + v, dn, local);
                 if (pp < tb) {
                     const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
                     notconv |= conv ? 0u : 1u;
@@ -407,6 +422,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.glist = w.glist_run;
     a.S = p.S;
     a.upper = p.upper;
+    a.xpost = w.cnt;
     a.perm = w.perm;
     a.iperm = w.iperm;
     a.offsets = w.offsets;
