@@ -155,10 +155,17 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
     return lo;
 }
 
+// Workgroup barrier that orders LDS only: each wave waits for its own LDS
+// operations, not for its outstanding global stores (__syncthreads waits for
+// those too, a full memory round trip when they are scattered).
+__device__ inline void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---- block-wide scans --------------------------------------------------
 // Exclusive prefix of `v` over a workgroup of NT threads; *total receives
-// the sum.
-template <int NT, typename T>
+// the sum.  LDS_ONLY: its barriers order LDS only (see lds_barrier).
+template <int NT, typename T, bool LDS_ONLY = false>
 __device__ inline T block_exclusive_scan_n(T v, T* total) {
     __shared__ T warp_sums[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -170,7 +177,8 @@ __device__ inline T block_exclusive_scan_n(T v, T* total) {
         if (lane >= off) x += y;
     }
     if (lane == kWave - 1) warp_sums[wid] = x;
-    __syncthreads();
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
     T wbase = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < NT / kWave; ++w) {
@@ -178,7 +186,8 @@ __device__ inline T block_exclusive_scan_n(T v, T* total) {
         if (w < wid) wbase += s;
         tot += s;
     }
-    __syncthreads();
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
     *total = tot;
     return wbase + x - v;
 }

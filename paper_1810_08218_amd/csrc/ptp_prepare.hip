@@ -268,8 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                 part += c;
                 if (x < w) partpre += c;
             }
-            const int total = block_sum(part);
-            const int chunk_pre = block_sum(partpre);
+            int total, chunk_pre;
+            (void)block_exclusive_scan_n<kBlock, int, true>(part, &total);
+            (void)block_exclusive_scan_n<kBlock, int, true>(partpre, &chunk_pre);
             if (total == 0) break;
             if (w == 0 && tid == 0) offs[r] = base;
             if (tid == 0) st_c(cntg + ((r + 2) % 3) * gs + w, 0);
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
             int pc = 0;
             for (int x = my0; x < my1; ++x) pc += __popc(ld_c(cur + x));
             int tot_w;
-            const int pre = block_exclusive_scan(pc, &tot_w);
+            const int pre = block_exclusive_scan_n<kBlock, int, true>(pc, &tot_w);
             for (int done = 0; done < tot_w; done += kListCap) {
                 int rank = pre;
                 for (int x = my0; x < my1 && rank < done + kListCap; ++x) {
@@ -288,19 +289,18 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                     while (word) {
                         const int bt = __ffs(word) - 1;
                         word &= word - 1;
-                        const int u = x * 32 + bt;
-                        if (rank >= done && rank < done + kListCap) {
-                            list[rank - done] = u;
-                            const int pos = base + chunk_pre + rank;
-                            a.perm[vo + pos] = vo + u;
-                            a.iperm[vo + u] = vo + pos;
-                        }
+                        if (rank >= done && rank < done + kListCap) list[rank - done] = x * 32 + bt;
                         ++rank;
                     }
                 }
-                __syncthreads();
+                lds_barrier();
                 const int cntl = min(kListCap, tot_w - done);
                 const int lvl = r + 1;
+                for (int t = tid; t < cntl; t += kBlock) {      // the chunk's slice of the order
+                    const int pos = base + chunk_pre + done + t;
+                    a.perm[vo + pos] = vo + list[t];
+                    a.iperm[vo + list[t]] = vo + pos;
+                }
                 for (int t = tid; t < cntl; t += kBlock) {
                     const int u = vo + list[t];
                     const int e0 = a.row[u], e1 = a.row[u + 1];
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                         }
                     }
                 }
-                __syncthreads();
+                lds_barrier();
             }
             for (int x = my0; x < my1; ++x) st_c(cur + x, 0u);
             base += total;
@@ -404,7 +404,8 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
     const int W = (n + 31) / 32;
     unsigned* vis = lds;
     unsigned* nxt = lds + W;
-    int* list = reinterpret_cast<int*>(lds + 2 * W);
+    int* wpre = reinterpret_cast<int*>(lds + 2 * W);          // [W + 1]
+    int* list = reinterpret_cast<int*>(lds + 3 * W + 1);
     int* offs = a.offsets + vo + b;
     for (int x = tid; x < 2 * W; x += kLdsBlock) lds[x] = 0u;
     __syncthreads();
@@ -429,25 +430,49 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
         int pc = 0;
         for (int x = my0; x < my1; ++x) pc += __popc(nxt[x]);
         int total;
-        int rank = block_exclusive_scan_n<kLdsBlock>(pc, &total);
+        int run = block_exclusive_scan_n<kLdsBlock, int, true>(pc, &total);
         if (total == 0) break;
         if (tid == 0) offs[r] = base;
+        // rank of the first vertex of every word (ascending id order)
         for (int x = my0; x < my1; ++x) {
-            unsigned word = nxt[x];
-            nxt[x] = 0u;                       // each word belongs to one thread
-            while (word) {
-                const int u = x * 32 + __ffs(word) - 1;
-                word &= word - 1;
-                const int pos = base + rank;
-                a.perm[vo + pos] = vo + u;
-                a.iperm[vo + u] = vo + pos;
-                a.level[vo + u] = r;
-                if (rank < kLdsList) list[rank] = u;
-                ++rank;
+            wpre[x] = run;
+            run += __popc(nxt[x]);
+        }
+        if (tid == 0) wpre[W] = total;
+        lds_barrier();
+        // vertex of rank t: the word holding it by binary search over the
+        // word ranks, then the matching set bit; one vertex per thread, so a
+        // dense run of ids costs no more than a sparse one
+        for (int t = tid; t < total; t += kLdsBlock) {
+            int lo = 0, hi = W;                 // wpre[lo] <= t < wpre[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (wpre[mid] <= t) lo = mid;
+                else hi = mid;
             }
+            unsigned w = nxt[lo];
+            int k = t - wpre[lo], bit = 0;
+            for (int step = 16; step >= 1; step >>= 1) {   // k-th set bit of w
+                const unsigned low = w & ((1u << step) - 1u);
+                const int c = __popc(low);
+                if (k >= c) {
+                    k -= c;
+                    w >>= step;
+                    bit += step;
+                } else {
+                    w = low;
+                }
+            }
+            const int u = lo * 32 + bit;
+            if (t < kLdsList) list[t] = u;
+            a.perm[vo + base + t] = vo + u;
+            a.iperm[vo + u] = vo + base + t;
+            a.level[vo + u] = r;
         }
         if (total > kLdsList) wait_memory();   // perm is read back below
-        __syncthreads();
+        lds_barrier();                          // perm / iperm / level stores need not land
+        for (int x = my0; x < my1; ++x) nxt[x] = 0u;
+        lds_barrier();
         for (int t = tid; t < total; t += kLdsBlock) {
             const int u = t < kLdsList ? list[t] : ld_c(a.perm + vo + base + t) - vo;
             const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
@@ -469,7 +494,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         base += total;
     }
     const int rho = r, reach = base;
@@ -481,7 +506,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
         pc += __popc(word);
     }
     int total;
-    int rank = block_exclusive_scan_n<kLdsBlock>(pc, &total);
+    int rank = block_exclusive_scan_n<kLdsBlock, int, true>(pc, &total);
     for (int x = my0; x < my1; ++x) {
         unsigned word = ~vis[x];
         if (x == W - 1 && (n & 31)) word &= (1u << (n & 31)) - 1u;
@@ -617,7 +642,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
 }
 
 size_t bfs_lds_bytes(long long words) {
-    return sizeof(unsigned) * (size_t)(2 * words) + sizeof(int) * kLdsList;
+    return sizeof(unsigned) * (size_t)(3 * words + 1) + sizeof(int) * kLdsList;
 }
 
 // Largest mesh (vertices) the one-workgroup BFS takes on this device, 0 if
@@ -632,7 +657,7 @@ int bfs_lds_max_vertices(int device) {
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(avail + sizeof(int) * kLdsList)) != hipSuccess)
         return 0;
-    return (int)(avail / 8) * 32;
+    return (int)((avail - 4) / 12) * 32;     // three words per 32 vertices
 }
 
 int max_coop_blocks_bfs(int cus) {
