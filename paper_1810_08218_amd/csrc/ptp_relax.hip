@@ -177,6 +177,91 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
     }
 }
 
+// Band positions p, p + gsz, ... (< be) of one thread, software-pipelined:
+// while the neighbour data of position p are in flight, the wedges of the
+// next position and the row of the one after are loaded, so a thread that
+// owns several band vertices waits for about one memory round per vertex
+// instead of three.  Without labels.  Returns the "not converged" vote of
+// the positions below tb.
+template <int C>
+__device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
+                                                long long tb, long long gsz, const float* dold,
+                                                float* dnew, bool local) {
+    unsigned notconv = 0;
+    if (p >= be) return 0;
+    int r0 = a.row[vo + p];
+    int cnt = a.row[vo + p + 1] - r0;
+    int2 w[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) w[q] = q < cnt ? a.wedge[r0 + q] : make_int2(vo + (int)p, vo + (int)p);
+    long long pn = p + gsz;
+    int rn0 = 0, rn1 = 0;
+    if (pn < be) {
+        rn0 = a.row[vo + pn];
+        rn1 = a.row[vo + pn + 1];
+    }
+    for (;;) {
+        const int v = vo + (int)p;
+        const float4 x0 = a.xyz[v];
+        const float dv = ld_c(dold + v);
+        float da[C], db[C];
+        float4 xa[C], xb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            da[q] = ld_c(dold + w[q].x);
+            db[q] = ld_c(dold + w[q].y);
+            xa[q] = a.xyz[w[q].x];
+            xb[q] = a.xyz[w[q].y];
+        }
+        // the next position's wedges and the row of the one after
+        const long long pnn = pn + gsz;
+        const int cntn = rn1 - rn0;
+        int2 wn[C];
+        int rnn0 = 0, rnn1 = 0;
+        if (pn < be) {
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                wn[q] = q < cntn ? a.wedge[rn0 + q] : make_int2(vo + (int)pn, vo + (int)pn);
+        }
+        if (pnn < be) {
+            rnn0 = a.row[vo + pnn];
+            rnn1 = a.row[vo + pnn + 1];
+        }
+        float best = kInf;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            if (q < cnt && fminf(da[q], db[q]) < kInf) {
+                int l = 0;
+                best = fminf(best, local_update<false>(x0, xa[q], xb[q], da[q], db[q], 0, 0, l));
+            }
+        }
+        for (int base = r0 + C; base < r0 + cnt; base += C) {     // degree above C
+            const int c2 = min(C, r0 + cnt - base);
+            int2 wv[C];
+#pragma unroll
+            for (int q = 0; q < C; ++q) wv[q] = q < c2 ? a.wedge[base + q] : make_int2(v, v);
+            int bl = 0;
+            eval_wedges<false, C>(a, x0, wv, c2, dold, nullptr, best, bl);
+        }
+        const float dn = best < dv ? best : dv;
+        st_g(dnew + v, dn, local);
+        if (p < tb) {
+            const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
+            notconv |= conv ? 0u : 1u;
+        }
+        if (pn >= be) break;
+        p = pn;
+        pn = pnn;
+        r0 = rn0;
+        cnt = cntn;
+#pragma unroll
+        for (int q = 0; q < C; ++q) w[q] = wn[q];
+        rn0 = rnn0;
+        rn1 = rnn1;
+    }
+    return notconv;
+}
+
 // Groups of consecutive workgroups run the whole iteration of one mesh at a
 // time, with a barrier of their own.  Per iteration k every thread of the
 // group takes band vertices in a strided loop; position p of the mesh is
@@ -323,7 +408,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const int tb = offs[lo + 1];    // tested topleset V_lo = [bb, tb)
             unsigned notconv = 0;
             const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
-            for (long long pp = first; pp < be; pp += gsz) {
+            constexpr bool kPipe = !LABELS && !WARM && !CACHE;
+            if (kPipe) {
+                for (long long pp = first; pp < bb; pp += gsz)
+                    st_g(dnew + vo + (int)pp, ld_c(dold + vo + (int)pp), local);
+                const long long firstb = bb + ((g0 - bb % gsz) + gsz) % gsz;
+                notconv |= relax_band_pipelined<kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew, local);
+            }
+            for (long long pp = kPipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
                     st_g(dnew + v, ld_c(dold + v), local);
