@@ -181,12 +181,12 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
 // while the neighbour data of position p are in flight, the wedges of the
 // next position and the row of the one after are loaded, so a thread that
 // owns several band vertices waits for about one memory round per vertex
-// instead of three.  Without labels.  Returns the "not converged" vote of
-// the positions below tb.
-template <int C>
+// instead of three.  Returns the "not converged" vote of the positions
+// below tb.
+template <bool LABELS, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
                                                 long long tb, long long gsz, const float* dold,
-                                                float* dnew, bool local) {
+                                                float* dnew, const int* lold, int* lnew, bool local) {
     unsigned notconv = 0;
     if (p >= be) return 0;
     int r0 = a.row[vo + p];
@@ -206,12 +206,17 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
         const float dv = ld_c(dold + v);
         float da[C], db[C];
         float4 xa[C], xb[C];
+        int la[C], lb[C];
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             da[q] = ld_c(dold + w[q].x);
             db[q] = ld_c(dold + w[q].y);
             xa[q] = a.xyz[w[q].x];
             xb[q] = a.xyz[w[q].y];
+            if (LABELS) {
+                la[q] = ld_c(lold + w[q].x);
+                lb[q] = ld_c(lold + w[q].y);
+            }
         }
         // the next position's wedges and the row of the one after
         const long long pnn = pn + gsz;
@@ -228,11 +233,17 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
             rnn1 = a.row[vo + pnn + 1];
         }
         float best = kInf;
+        int bl = 0x7fffffff;
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             if (q < cnt && fminf(da[q], db[q]) < kInf) {
                 int l = 0;
-                best = fminf(best, local_update<false>(x0, xa[q], xb[q], da[q], db[q], 0, 0, l));
+                const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
+                                                     LABELS ? lb[q] : 0, l);
+                if (u < best || (LABELS && u == best && l < bl)) {
+                    best = u;
+                    bl = l;
+                }
             }
         }
         for (int base = r0 + C; base < r0 + cnt; base += C) {     // degree above C
@@ -240,10 +251,15 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
             int2 wv[C];
 #pragma unroll
             for (int q = 0; q < C; ++q) wv[q] = q < c2 ? a.wedge[base + q] : make_int2(v, v);
-            int bl = 0;
-            eval_wedges<false, C>(a, x0, wv, c2, dold, nullptr, best, bl);
+            eval_wedges<LABELS, C>(a, x0, wv, c2, dold, lold, best, bl);
         }
-        const float dn = best < dv ? best : dv;
+        float dn = dv;
+        if (best < dv) {
+            dn = best;
+            if (LABELS) st_g(lnew + v, bl, local);
+        } else if (LABELS) {
+            st_g(lnew + v, ld_c(lold + v), local);
+        }
         st_g(dnew + v, dn, local);
         if (p < tb) {
             const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
@@ -408,14 +424,21 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const int tb = offs[lo + 1];    // tested topleset V_lo = [bb, tb)
             unsigned notconv = 0;
             const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
-            constexpr bool kPipe = !LABELS && !WARM && !CACHE;
-            if (kPipe) {
-                for (long long pp = first; pp < bb; pp += gsz)
+            // pipelined unless the register cache serves (one position per
+            // thread) or this is the warm-start variant
+            const bool pipe = !WARM && !(CACHE && be - cb <= gsz);
+            if (pipe) {
+                for (long long pp = first; pp < bb; pp += gsz) {
                     st_g(dnew + vo + (int)pp, ld_c(dold + vo + (int)pp), local);
+                    if (LABELS) st_g(lnew + vo + (int)pp, ld_c(lold + vo + (int)pp), local);
+                }
                 const long long firstb = bb + ((g0 - bb % gsz) + gsz) % gsz;
-                notconv |= relax_band_pipelined<kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew, local);
+                if (!WARM)
+                    notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
+                                                                    lold, lnew, local);
+                cv = -1;
             }
-            for (long long pp = kPipe ? be : first; pp < be; pp += gsz) {
+            for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
                     st_g(dnew + v, ld_c(dold + v), local);
