@@ -22,7 +22,7 @@ def candidates() -> list:
     out = []
     for G in (512, 1024):
         for sl, ll in ((8192, 131072), (32768, 262144), (65536, 524288)):
-            for mg, lg in ((4, 16), (8, 32), (16, 64)):
+            for mg, lg in ((4, 16), (8, 32), (16, 64), (16, 96), (32, 128)):
                 out.append(dict(workgroups=G, small_limit=sl, large_limit=ll, medium_group=mg,
                                 large_group=lg))
     return out

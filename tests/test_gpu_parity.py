@@ -153,12 +153,30 @@ def test_parity_multisource_labels(cuda):
     check_parity(cuda, I.bumpy_icosphere(level=6, seed=3, n_sources=32), 1e-4, labels=True)
 
 
-@pytest.mark.parametrize("t", [1, 260, 301])
+@pytest.mark.parametrize("t", [3, 260, 301])
 def test_parity_batch_meshes(cuda, t):
-    mesh = I.batch_mesh(t)
-    if mesh.n > 300000:
-        pytest.skip("mesh too large for the in-test oracle")
-    check_parity(cuda, mesh, 1e-4, labels=True)
+    """Jittered grid (319 x 319, obtuse triangles) and tori of the batch."""
+    check_parity(cuda, I.batch_mesh(t), 1e-4, labels=True)
+
+
+def test_bounds_largest_batch_grid(cuda):
+    """The 912,025-vertex jittered grid of the batch at full size, where the
+    oracle would take minutes: the properties that hold at any size.  The
+    geodesic on a plane is at least the Euclidean distance to the nearest
+    source, at most the shortest edge path (Dijkstra), zero at the sources."""
+    from meshtools import dijkstra
+    m = I.batch_mesh(1)
+    g = gpu_run(m, 1e-4, want_order=False)
+    assert g.status == P.PTP_OK
+    d = g.dist.astype(np.float64)
+    X = m.V.astype(np.float64)
+    eu = np.min(np.linalg.norm(X[:, None, :] - X[m.S][None, :, :], axis=2), axis=1)
+    dj = dijkstra(m.V, m.F, m.S)
+    assert (d[m.S] == 0).all() and np.isfinite(d).all()
+    assert (d >= eu * (1 - 1e-5) - 1e-7).all()
+    assert (d <= dj * (1 + 1e-5) + 1e-7).all()
+    say(f"  {m.name}: K {g.iterations} rho {g.rho} U {g.updates}; d/euclid mean "
+        f"{np.mean(d[eu > 0] / eu[eu > 0]):.5f}, d/dijkstra mean {np.mean(d[dj > 0] / dj[dj > 0]):.5f}")
 
 
 def test_parity_window_and_cap(cuda):
