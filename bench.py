@@ -13,7 +13,9 @@ ms to converge (ptp_run alone), the roofline of the relaxation kernel, the
 oracle's single-thread CPU rate on the same mesh, and the max relative error
 of the GPU distances against the oracle.  Alongside ("batched"): the 512-mesh
 uneven batch (jittered grids and tori, 71M vertices) in one persistent launch
-with an autotuned schedule, against the same meshes run one plan at a time;
+with an autotuned schedule and band cap (window; the fastest whose result
+stays within 1e-4 of the unbounded run's), against the same meshes run one
+plan at a time with the paper's unbounded band;
 and ("warm_start", for the single mesh and the batch) the learned warm start
 against the plain run at the same tolerance.
 """
@@ -157,6 +159,8 @@ def bench_batched(steps, P, I, warm=True):
     b.prepare(dV, dF, dS, work=work)
     note("batched: autotuning the schedule")
     tuned = autotune.tune(b, descs, dist, use_cache=False)
+    note("batched: autotuning the window against the unbounded run")
+    win = autotune.tune_window(b, dist)
     stream = torch.cuda.current_stream()
     b.run(dist, stream=stream)              # warm-up with the tuned schedule
     rc, stats, _ = b.stats()
@@ -199,6 +203,9 @@ def bench_batched(steps, P, I, warm=True):
             "plain_ms_to_converge_sum": round(plain_ms, 3),
             "speedup_vs_plain": round(plain_ms / ms_run, 3),
             "schedule": tuned["schedule"],
+            "window": win["window"],
+            "window_max_rel_diff_vs_unbounded": win["max_rel_diff"],
+            "window_tried_ms": [[w, None if ms != ms else round(ms, 3), d] for w, ms, d in win["tried"]],
             "max_iterations": max(x["iterations"] for x in stats),
             "max_toplesets": max(x["n_toplesets"] for x in stats),
             "warm_start": bench_warm(b, out_len, stream, 3) if warm else None}

@@ -131,6 +131,13 @@ ptp_status ptp_get_order(ptp_plan *plan, int32_t *dPerm, int32_t *dOffsets, void
  * -1 if it never retired).  Synchronises. */
 ptp_status ptp_get_schedule(ptp_plan *plan, int32_t *hRetire);
 
+/* Replace the band cap for the following runs (the `window` option:
+ * > 0 caps the band at `window` toplesets, the ones pushed below it stop
+ * updating; 0 is the paper's unbounded band).  Unlike a schedule this
+ * changes results; it exists so that a caller can tune it against the
+ * unbounded run.  PTP_EINVAL for a negative value. */
+ptp_status ptp_set_window(ptp_plan *plan, int32_t window);
+
 /* Number of toplesets found by the last prepare (host value). */
 int32_t ptp_n_toplesets(const ptp_plan *plan);
 
@@ -198,6 +205,9 @@ ptp_status ptp_batch_run(ptp_batch *batch, float *dDist, int32_t *dLabel, void *
 /* Synchronise and report: per-mesh stats and status (host arrays [count],
  * either may be NULL).  Returns PTP_OK, or the first non-OK mesh status. */
 ptp_status ptp_batch_get_stats(ptp_batch *batch, ptp_stats *hStats, int32_t *hStatus);
+
+/* ptp_set_window for a batch (one cap for every mesh). */
+ptp_status ptp_batch_set_window(ptp_batch *batch, int32_t window);
 
 /* Replace / read the work distribution used by the next prepare and run. */
 ptp_status ptp_batch_set_schedule(ptp_batch *batch, const ptp_schedule *schedule);

@@ -68,3 +68,44 @@ def tune(batch, descs, dist, label=None, use_cache: bool = True) -> dict:
         except OSError:
             pass
     return {"schedule": cands[best], "ms": ms[best], "cached": False, "all_ms": ms}
+
+
+def tune_window(batch, dist, candidates=(0, 256, 128, 64, 48, 32, 24, 16), tol=1e-4, reps=2,
+                stream=None):
+    """Band cap for a prepared batch: the fastest window whose distances stay
+    within `tol` (relative) of the unbounded run's, which is the judge.  Each
+    candidate is run once to check it, then timed over `reps` runs with
+    device events.  Installs the choice and returns
+    {"window", "ms", "max_rel_diff", "tried": [(window, ms, max_rel_diff), ...]}."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+
+    def timed():
+        ts = []
+        for _ in range(reps):
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            batch.run(dist, stream=s)
+            z.record(s)
+            z.synchronize()
+            ts.append(a.elapsed_time(z))
+        return min(ts)
+
+    batch.set_window(0)
+    batch.run(dist, stream=s)
+    rc, _, _ = batch.stats()
+    ref = dist.clone()
+    fin = torch.isfinite(ref) & (ref > 0)
+    tried = []
+    best = None
+    for w in candidates:
+        batch.set_window(w)
+        batch.run(dist, stream=s)
+        rc, _, _ = batch.stats()
+        diff = float(((dist[fin] - ref[fin]).abs() / ref[fin]).max()) if rc == 0 else float("inf")
+        ms = timed() if diff <= tol else float("nan")
+        tried.append((w, ms, diff))
+        if diff <= tol and (best is None or ms < best[1]):
+            best = (w, ms, diff)
+    batch.set_window(best[0])
+    return {"window": best[0], "ms": best[1], "max_rel_diff": best[2], "tried": tried}

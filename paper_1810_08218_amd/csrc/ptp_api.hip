@@ -762,6 +762,13 @@ ptp_status ptp_run_warm(ptp_plan* p, const float* dUpper, float* dDist, void* st
     return p->s.run(dDist, nullptr, stream, dUpper);
 }
 
+ptp_status ptp_set_window(ptp_plan* p, int32_t window) {
+    if (!p) return PTP_EINVAL;
+    if (window < 0) return p->s.fail(PTP_EINVAL, "negative window");
+    p->s.opt.window = window;
+    return PTP_OK;
+}
+
 const char* ptp_last_error(const ptp_plan* p) { return p ? p->s.err.c_str() : "null plan"; }
 
 void ptp_plan_destroy(ptp_plan* p) { delete p; }
@@ -810,6 +817,13 @@ ptp_status ptp_batch_get_stats(ptp_batch* p, ptp_stats* hStats, int32_t* hStatus
         return s.fail(PTP_EINVAL, "no run to report");
     }
     return s.stats(hStats, hStatus);
+}
+
+ptp_status ptp_batch_set_window(ptp_batch* p, int32_t window) {
+    if (!p) return PTP_EINVAL;
+    if (window < 0) return p->s.fail(PTP_EINVAL, "negative window");
+    p->s.opt.window = window;
+    return PTP_OK;
 }
 
 ptp_status ptp_batch_set_schedule(ptp_batch* p, const ptp_schedule* sch) {

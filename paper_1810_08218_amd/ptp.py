@@ -33,7 +33,8 @@ EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "
            "ptp_batch_autotune", "ptp_batch_last_error", "ptp_batch_destroy",
            "ptp_warm_features", "ptp_warm_predict", "ptp_run_warm", "ptp_batch_warm_features",
            "ptp_batch_warm_predict", "ptp_batch_run_warm", "ptp_mlp_params", "ptp_mlp_apply",
-           "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step")
+           "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step", "ptp_set_window",
+           "ptp_batch_set_window")
 
 MLP_PARAMS = 4481       # PTP_MLP_PARAMS
 
@@ -145,6 +146,9 @@ def load() -> C.CDLL:
         getattr(lib, name).restype = C.c_int
     for name in ("ptp_run_warm", "ptp_batch_run_warm"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
+        getattr(lib, name).restype = C.c_int
+    for name in ("ptp_set_window", "ptp_batch_set_window"):
+        getattr(lib, name).argtypes = [vp, C.c_int32]
         getattr(lib, name).restype = C.c_int
     lib.ptp_mlp_params.argtypes = []
     lib.ptp_mlp_params.restype = C.c_int32
@@ -290,6 +294,12 @@ class Plan:
         rc = self._lib.ptp_run_warm(self._h, _ptr(upper), _ptr(dist), _stream(stream))
         if rc != PTP_OK:
             raise self._err(rc, "ptp_run_warm")
+
+    def set_window(self, window: int):
+        """Band cap for the following runs (changes results; 0 = unbounded)."""
+        rc = self._lib.ptp_set_window(self._h, int(window))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_set_window")
 
     def stats(self, allow_noconv: bool = True) -> dict:
         st = Stats()
@@ -486,6 +496,12 @@ class Batch:
         status = (C.c_int32 * self.count)()
         rc = self._lib.ptp_batch_get_stats(self._h, st, status)
         return rc, [s.as_dict() for s in st], [int(x) for x in status]
+
+    def set_window(self, window: int):
+        """Band cap for the following runs of every mesh (changes results)."""
+        rc = self._lib.ptp_batch_set_window(self._h, int(window))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_set_window")
 
     def set_schedule(self, **kw):
         sch = Schedule(**{k: int(v) for k, v in kw.items()})

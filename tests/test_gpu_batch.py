@@ -146,6 +146,35 @@ def test_batch_bfs_paths_agree(cuda):
         assert np.array_equal(dist.cpu().numpy(), rd) and np.array_equal(lab.cpu().numpy(), rl), lim
 
 
+def test_set_window_equals_create_time_window_and_tuner(cuda):
+    """A window set at run time gives exactly the results of a batch created
+    with it; the window tuner keeps its choice within 1e-4 of the unbounded
+    run."""
+    import torch
+    from paper_1810_08218_amd import autotune
+    meshes, share = small_batch()
+    V, F, S, descs, out_len = P.concat(meshes, share)
+    dV, dF, dS = (torch.from_numpy(x).cuda() for x in (V, F, S))
+    ref = run_batch(meshes, share, 1e-4, labels=False, window=5)
+    b = P.Batch(descs, 1e-4)
+    b.prepare(dV, dF, dS)
+    dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
+    b.set_window(5)
+    b.run(dist)
+    assert b.stats()[0] == P.PTP_OK
+    assert np.array_equal(dist.cpu().numpy(), ref[1].cpu().numpy())
+    with pytest.raises(P.PTPError):
+        b.set_window(-1)
+    res = autotune.tune_window(b, dist, candidates=(0, 32, 8, 4, 2))
+    say(f"  window tuner: {res}")
+    assert res["max_rel_diff"] <= 1e-4
+    b.run(dist)
+    unb = run_batch(meshes, share, 1e-4, labels=False)[1].cpu().numpy()
+    d = dist.cpu().numpy()
+    fin = np.isfinite(unb) & (unb > 0)
+    assert (np.abs(d[fin] - unb[fin]) / unb[fin]).max() <= 1e-4
+
+
 def test_invalid_mesh_in_batch(cuda):
     import torch
     meshes, share = small_batch()
