@@ -143,6 +143,41 @@ def bench_warm(obj, n_out, stream, reps):
                      f"certification"}
 
 
+def bench_other_configs(P, I, reps=10):
+    """The flat 64 x 64 grid (tol 1e-6) and the 2.6M-vertex bumpy icosphere
+    with 32 sources and Voronoi labels (tol 1e-4): ms to converge (ptp_run,
+    median of reps after warm-up), ms to prepare, vertex updates per second
+    of the run."""
+    import torch
+    out = {}
+    for name, mesh, tol, labels in (("flat_grid_64_tol1e-6", I.flat_grid(64), 1e-6, False),
+                                    ("bumpy_icosphere_l9_32src_labels_tol1e-4",
+                                     I.bumpy_icosphere(level=9, seed=3, n_sources=32), 1e-4, True)):
+        note(f"config {name}")
+        V, F, S = (torch.from_numpy(x).cuda() for x in (mesh.V, mesh.F, mesh.S))
+        plan = P.Plan(mesh.n, mesh.f, mesh.m, tol, want_labels=labels)
+        work = plan.workspace()
+        stream = torch.cuda.current_stream()
+        dist = torch.empty(mesh.n, dtype=torch.float32, device="cuda")
+        lab = torch.empty(mesh.n, dtype=torch.int32, device="cuda") if labels else None
+        t0 = time.perf_counter()
+        plan.prepare(V, F, S, work=work, stream=stream)
+        prep = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            plan.prepare(V, F, S, work=work, stream=stream)
+            prep.append((time.perf_counter() - t0) * 1e3)
+        ms = _timed(lambda: plan.run(dist, lab, stream=stream), stream, reps)
+        st = plan.stats()
+        out[name] = {"n_vertices": mesh.n, "n_sources": mesh.m, "labels": labels, "tol": tol,
+                     "ms_to_converge": round(ms, 4), "ms_prepare_and_sync": round(min(prep), 4),
+                     "iterations": st["iterations"], "toplesets": st["n_toplesets"],
+                     "vertex_updates": st["vertex_updates"],
+                     "vertex_updates_per_s": round(st["vertex_updates"] / (ms * 1e-3), 1),
+                     "workgroups": st["workgroups"]}
+    return out
+
+
 def bench_batched(steps, P, I, warm=True):
     """512 uneven meshes in one persistent launch vs one plan per mesh."""
     import torch
@@ -221,6 +256,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start legs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the flat-grid and bumpy-icosphere timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 256 MiB (a kernel of known traffic for "
                          "scaling the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -330,6 +367,7 @@ def main():
     if cpu is not None:
         line["schedule_matches_oracle"] = same_sched
     line["warm_start"] = warm
+    line["other_configs"] = None if args.no_configs else bench_other_configs(P, I)
     line["batched"] = batched
     print(json.dumps(line), flush=True)
 

@@ -119,8 +119,7 @@ struct RelaxArgs {
     int* out_l;
 };
 
-// Wedges gathered together per vertex (mean degree 6); the warm-start
-// variant gathers 4 at a time to stay within 128 registers (the minimum over
+// Wedges gathered together per vertex (mean degree 6; the minimum over
 // wedges does not depend on the grouping).
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
@@ -278,6 +277,88 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     return notconv;
 }
 
+// One certification sweep over positions p, p + gsz, ... (< end) of one
+// thread, pipelined like relax_band_pipelined: a bound below the planar
+// update from the neighbours' bounds is withdrawn (+inf), in place.  Returns
+// whether this thread withdrew any; counts them into *rejected.
+template <int C>
+__device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long long p, long long end,
+                                             long long gsz, float* d, bool local, int* rejected) {
+    unsigned changed = 0;
+    if (p >= end) return 0;
+    int r0 = a.row[vo + p];
+    int cnt = a.row[vo + p + 1] - r0;
+    int2 w[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) w[q] = q < cnt ? a.wedge[r0 + q] : make_int2(vo + (int)p, vo + (int)p);
+    long long pn = p + gsz;
+    int rn0 = 0, rn1 = 0;
+    if (pn < end) {
+        rn0 = a.row[vo + pn];
+        rn1 = a.row[vo + pn + 1];
+    }
+    for (;;) {
+        const int v = vo + (int)p;
+        const float4 x0 = a.xyz[v];
+        const float wv = ld_c(d + v);
+        float da[C], db[C];
+        float4 xa[C], xb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            da[q] = ld_c(d + w[q].x);
+            db[q] = ld_c(d + w[q].y);
+            xa[q] = a.xyz[w[q].x];
+            xb[q] = a.xyz[w[q].y];
+        }
+        const long long pnn = pn + gsz;
+        const int cntn = rn1 - rn0;
+        int2 wn[C];
+        int rnn0 = 0, rnn1 = 0;
+        if (pn < end) {
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                wn[q] = q < cntn ? a.wedge[rn0 + q] : make_int2(vo + (int)pn, vo + (int)pn);
+        }
+        if (pnn < end) {
+            rnn0 = a.row[vo + pnn];
+            rnn1 = a.row[vo + pnn + 1];
+        }
+        if (wv < kInf) {
+            float best = kInf;
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                if (q < cnt && fminf(da[q], db[q]) < kInf) {
+                    int l = 0;
+                    best = fminf(best, local_update<false>(x0, xa[q], xb[q], da[q], db[q], 0, 0, l));
+                }
+            }
+            for (int base = r0 + C; base < r0 + cnt; base += C) {     // degree above C
+                const int c2 = min(C, r0 + cnt - base);
+                int2 wv2[C];
+#pragma unroll
+                for (int q = 0; q < C; ++q) wv2[q] = q < c2 ? a.wedge[base + q] : make_int2(v, v);
+                int bl = 0;
+                eval_wedges<false, C>(a, x0, wv2, c2, d, nullptr, best, bl);
+            }
+            if (wv < best) {
+                st_g(d + v, kInf, local);
+                changed = 1;
+                ++*rejected;
+            }
+        }
+        if (pn >= end) break;
+        p = pn;
+        pn = pnn;
+        r0 = rn0;
+        cnt = cntn;
+#pragma unroll
+        for (int q = 0; q < C; ++q) w[q] = wn[q];
+        rn0 = rnn0;
+        rn1 = rnn1;
+    }
+    return changed;
+}
+
 // Groups of consecutive workgroups run the whole iteration of one mesh at a
 // time, with a barrier of their own.  Per iteration k every thread of the
 // group takes band vertices in a strided loop; position p of the mesh is
@@ -364,20 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const long long firstc = m0 + ((g0 - m0 % gsz) + gsz) % gsz;
             int rejected = 0, round = 0;
             for (;; ++round) {
-                unsigned changed = 0;
-                for (long long pp = firstc; pp < reach; pp += gsz) {
-                    const int v = vo + (int)pp;
-                    const float w = ld_c(dA + v);
-                    if (!(w < kInf)) continue;
-                    float u;
-                    int ul;
-                    best_update<false, 4>(a, v, a.xyz[v], dA, nullptr, u, ul);
-                    if (w < u) {
-                        st_g(dA + v, kInf, local);
-                        changed = 1;
-                        ++rejected;
-                    }
-                }
+                const unsigned changed =
+                    certify_pipelined<kChunk>(a, vo, firstc, reach, gsz, dA, local, &rejected);
                 if (!gb.sync(changed, &any)) return;
                 if (!any) break;
                 if (round == kCertifyRounds) {           // no closure in time: no bound
@@ -425,17 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             unsigned notconv = 0;
             const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
             // pipelined unless the register cache serves (one position per
-            // thread) or this is the warm-start variant
-            const bool pipe = !WARM && !(CACHE && be - cb <= gsz);
+            // thread)
+            const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
                 for (long long pp = first; pp < bb; pp += gsz) {
                     st_g(dnew + vo + (int)pp, ld_c(dold + vo + (int)pp), local);
                     if (LABELS) st_g(lnew + vo + (int)pp, ld_c(lold + vo + (int)pp), local);
                 }
                 const long long firstb = bb + ((g0 - bb % gsz) + gsz) % gsz;
-                if (!WARM)
-                    notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
-                                                                    lold, lnew, local);
+                notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
+                                                                lold, lnew, local);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
@@ -464,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     eval_wedges<LABELS, kCache>(a, cx0, cw, ccnt, dold, lold, best, bl);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
-                    best_update<LABELS, WARM ? 4 : kChunk>(a, v, x0, dold, lold, best, bl);
+                    best_update<LABELS, kChunk>(a, v, x0, dold, lold, best, bl);
                 }
                 float dn = dv;
                 if (best < dv) {

@@ -33,19 +33,37 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 // depend on the order of the atomics: first the largest term of each mesh
 // (a maximum is order-free), then the terms scaled to 2^31 / max, which keeps
 // a sum of up to 2^31 terms inside 64 bits.
+// One atomic per wave where the wave's positions all lie in one mesh (nearly
+// always), otherwise one per lane: a single counter per mesh hit by every
+// vertex would serialise the kernel.
+__device__ inline bool wave_uniform(int b) {
+    const int b0 = __shfl(b, 0, kWave);
+    return __all(b == b0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_edge_max(const float4* xyz, const int* row, const int2* wedge,
                                                      const int* vo, int B, long long N,
                                                      unsigned long long* emax) {
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int b = mesh_of(vo, B, p);
-        const float4 x = xyz[p];
+    const long long span = (N + gsz - 1) / gsz * gsz;          // every lane runs the same trips
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < span; p += gsz) {
+        const bool in = p < N;
+        const int b = in ? mesh_of(vo, B, p) : -1;
         float mx = 0.f;
-        for (int e = row[p]; e < row[p + 1]; ++e) {
-            const float4 a = xyz[wedge[e].x];
-            mx = fmaxf(mx, len3(a.x - x.x, a.y - x.y, a.z - x.z));
+        if (in) {
+            const float4 x = xyz[p];
+            for (int e = row[p]; e < row[p + 1]; ++e) {
+                const float4 a = xyz[wedge[e].x];
+                mx = fmaxf(mx, len3(a.x - x.x, a.y - x.y, a.z - x.z));
+            }
         }
-        if (mx > 0.f) atomicMax(emax + b, (unsigned long long)__float_as_uint(mx));
+        if (wave_uniform(b)) {
+            for (int m = 1; m < kWave; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, kWave));
+            if ((threadIdx.x & (kWave - 1)) == 0 && b >= 0 && mx > 0.f)
+                atomicMax(emax + b, (unsigned long long)__float_as_uint(mx));
+        } else if (in && mx > 0.f) {
+            atomicMax(emax + b, (unsigned long long)__float_as_uint(mx));
+        }
     }
 }
 
@@ -54,18 +72,29 @@ __global__ __launch_bounds__(kBlock) void k_edge_sum(const float4* xyz, const in
                                                      const unsigned long long* emax,
                                                      unsigned long long* acc) {
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int b = mesh_of(vo, B, p);
-        const float mx = __uint_as_float((unsigned)emax[b]);
-        if (!(mx > 0.f)) continue;
-        const double scale = 2147483648.0 / (double)mx;
-        const float4 x = xyz[p];
+    const long long span = (N + gsz - 1) / gsz * gsz;
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < span; p += gsz) {
+        const bool in = p < N;
+        const int b = in ? mesh_of(vo, B, p) : -1;
         unsigned long long s = 0;
-        for (int e = row[p]; e < row[p + 1]; ++e) {
-            const float4 a = xyz[wedge[e].x];
-            s += (unsigned long long)llrint((double)len3(a.x - x.x, a.y - x.y, a.z - x.z) * scale);
+        if (in) {
+            const float mx = __uint_as_float((unsigned)emax[b]);
+            if (mx > 0.f) {
+                const double scale = 2147483648.0 / (double)mx;
+                const float4 x = xyz[p];
+                for (int e = row[p]; e < row[p + 1]; ++e) {
+                    const float4 a = xyz[wedge[e].x];
+                    s += (unsigned long long)llrint((double)len3(a.x - x.x, a.y - x.y, a.z - x.z) * scale);
+                }
+            }
         }
-        if (s) atomicAdd(acc + b, s);
+        // integer sums do not depend on the order of the additions
+        if (wave_uniform(b)) {
+            for (int m = 1; m < kWave; m <<= 1) s += __shfl_xor(s, m, kWave);
+            if ((threadIdx.x & (kWave - 1)) == 0 && b >= 0 && s) atomicAdd(acc + b, s);
+        } else if (in && s) {
+            atomicAdd(acc + b, s);
+        }
     }
 }
 
