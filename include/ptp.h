@@ -82,7 +82,7 @@ typedef struct ptp_plan ptp_plan;
 
 /* Create a plan for a mesh with n_vertices, n_faces and n_sources.  `opt` is
  * copied; NULL means tol = 1e-3 (the paper's epsilon) and defaults elsewhere.
- * Sizes: 1 <= n_vertices < 2^31 / 4, 0 <= n_faces, 3 * n_faces < 2^31,
+ * Sizes: 1 <= n_vertices < 2^31 / 4, 0 <= n_faces, 6 * n_faces < 2^31,
  * 1 <= n_sources <= n_vertices.  Returns PTP_EINVAL / PTP_EUNSUPPORTED on
  * bad sizes or options; *out is NULL then. */
 ptp_status ptp_plan_create(ptp_plan **out, int32_t n_vertices, int32_t n_faces,
@@ -183,7 +183,7 @@ typedef struct {
 typedef struct ptp_batch ptp_batch;
 
 /* Create a batch plan.  `meshes` (host, [count]) is copied.  Sizes as for
- * ptp_plan_create, per mesh; totals must stay below 2^29 vertices and 2^31 / 3
+ * ptp_plan_create, per mesh; totals must stay below 2^29 vertices and 2^31 / 6
  * faces.  Returns PTP_EINVAL on bad descriptors or options. */
 ptp_status ptp_batch_create(ptp_batch **out, const ptp_mesh *meshes, int32_t count,
                             const ptp_options *opt);

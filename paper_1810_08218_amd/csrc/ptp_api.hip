@@ -227,6 +227,8 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(float4) * N,                    // feat
         sizeof(unsigned long long) * 2 * B,    // edge_acc (sums, maxima)
         sizeof(int) * B,                       // lds_mesh
+        sizeof(int) * (N + 1),                 // fanrow
+        sizeof(int) * (2 * F3 + 1),            // fan
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -270,6 +272,8 @@ Work carve(void* base, const Layout& L) {
     w.feat = reinterpret_cast<float4*>(b + L.off[27]);
     w.edge_acc = reinterpret_cast<unsigned long long*>(b + L.off[28]);
     w.lds_mesh = reinterpret_cast<int*>(b + L.off[29]);
+    w.fanrow = reinterpret_cast<int*>(b + L.off[30]);
+    w.fan = reinterpret_cast<int*>(b + L.off[31]);
     return w;
 }
 
@@ -345,7 +349,7 @@ struct Solver {
             F += d.n_faces;
             Sn += d.n_sources;
             W += (d.n_vertices + 31) / 32;
-            if (N > (1ll << 29) || 3 * F >= (1ll << 31) || Sn >= (1ll << 31)) return PTP_EUNSUPPORTED;
+            if (N > (1ll << 29) || 6 * F >= (1ll << 31) || Sn >= (1ll << 31)) return PTP_EUNSUPPORTED;
             mesh.push_back(md);
             h_vo.push_back((int)N);
             h_fo3.push_back((int)(3 * F));

@@ -67,9 +67,24 @@ struct Work {
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
+    int* fanrow;        // [N + 1] fan CSR over positions
+    int* fan;           // [6F]    fans of the incident triangles, positions and flags
 };
 
-constexpr int kLayoutParts = 30;
+constexpr int kLayoutParts = 32;
+
+// Fan of a position: its incident triangles as chains of neighbours.  Wedges
+// (a, b) and (b, c) of triangles adjacent around the vertex share b, so a
+// chain a, b, c, ... names every neighbour once and the triangles are its
+// consecutive pairs, each in its wedge's own orientation.  An entry is a
+// position with flags: kFanStart opens a chain (no triangle with the entry
+// before it); kFanClosed on entry 0 of a fan that is one closed chain stands
+// for the triangle (last entry, entry 0).  A fan has at most 2 * degree
+// entries (every wedge a chain of its own).
+constexpr int kFanStart = (int)0x80000000u;
+constexpr int kFanClosed = 1 << 30;
+constexpr int kFanId = kFanClosed - 1;
+constexpr int kFanChainMax = 16;     // above this degree every wedge is a chain of its own
 
 struct Sizes {
     long long N, F, S;      // internal totals over the batch

@@ -4,7 +4,9 @@
 //   at each of its corners as the opposite edge ("wedge"),
 //   toplesets V_r of each mesh by a level-synchronous BFS from its sources
 //   (Sec. 4.1), emitted in the canonical order (topleset, then ascending id),
-//   reorder of coordinates and incidence into that order (Sec. 4.3).
+//   reorder of coordinates and incidence into that order (Sec. 4.3), and the
+//   incidence as fans of neighbours (each neighbour named once) for the
+//   relaxation.
 #include "ptp_device.h"
 #include "ptp_kernels.h"
 
@@ -560,6 +562,98 @@ __global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const MeshDe
     }
 }
 
+// The chains of one position's wedges wd[0..c) (see kFanStart): a chain
+// starts at a wedge that no unused wedge leads into (the lowest unused one
+// if every unused wedge has a predecessor: a closed fan), and follows
+// (a, b) -> (b, c) while an unused wedge continues it.  Entry q goes to
+// emit(q, value); returns the number of entries.  Every wedge is used
+// exactly once, as a consecutive pair of one chain or as the closing pair.
+template <class Emit>
+__device__ inline int build_fan(const int2* wd, int c, Emit emit) {
+    if (c > kFanChainMax) {
+        for (int q = 0; q < c; ++q) {
+            const int2 t = wd[q];
+            emit(2 * q, t.x | kFanStart);
+            emit(2 * q + 1, t.y);
+        }
+        return 2 * c;
+    }
+    unsigned left = c == 32 ? ~0u : (1u << c) - 1u;
+    int len = 0;
+    while (left) {
+        int s = __ffs(left) - 1;
+        for (unsigned m = left; m; m &= m - 1) {
+            const int i = __ffs(m) - 1;
+            const int ai = wd[i].x;
+            bool pred = false;
+            for (unsigned m2 = left; m2 && !pred; m2 &= m2 - 1) {
+                const int j = __ffs(m2) - 1;
+                pred = j != i && wd[j].y == ai;
+            }
+            if (!pred) {
+                s = i;
+                break;
+            }
+        }
+        left &= ~(1u << s);
+        const int first = wd[s].x;
+        const bool whole = len == 0;
+        emit(len++, first | kFanStart);
+        int cur = wd[s].y;
+        emit(len++, cur);
+        for (;;) {
+            int nx = -1;
+            for (unsigned m = left; m; m &= m - 1) {
+                const int j = __ffs(m) - 1;
+                if (wd[j].x == cur) {
+                    nx = j;
+                    break;
+                }
+            }
+            if (nx < 0) break;
+            left &= ~(1u << nx);
+            cur = wd[nx].y;
+            if (whole && !left && cur == first) {     // one closed chain: no repeat
+                emit(0, first | kFanStart | kFanClosed);
+                break;
+            }
+            emit(len++, cur);
+        }
+    }
+    return len;
+}
+
+struct NoEmit {
+    __device__ void operator()(int, int) const {}
+};
+
+struct FanEmit {
+    int* out;
+    __device__ void operator()(int q, int v) const { out[q] = v; }
+};
+
+// fan length of each position, into fanrow[p + 1]
+__global__ __launch_bounds__(kBlock) void k_fan_count(const int* rowN, const int2* wedge, long long N,
+                                                      int* fanrow, const int* ctrl) {
+    if (gated(ctrl)) return;
+    const long long gsz = (long long)gridDim.x * kBlock;
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
+        const int r0 = rowN[p];
+        fanrow[p + 1] = build_fan(wedge + r0, rowN[p + 1] - r0, NoEmit{});
+        if (p == 0) fanrow[0] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fan_fill(const int* rowN, const int2* wedge, long long N,
+                                                     const int* fanrow, int* fan, const int* ctrl) {
+    if (gated(ctrl)) return;
+    const long long gsz = (long long)gridDim.x * kBlock;
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
+        const int r0 = rowN[p];
+        build_fan(wedge + r0, rowN[p + 1] - r0, FanEmit{fan + fanrow[p]});
+    }
+}
+
 int grid_for(long long work) {
     long long g = (work + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -638,6 +732,12 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo,
                        w.perm, w.iperm, w.rowO, w.wedgeO, w.rowN, N, w.xyz, w.wedge, w.ctrl);
+    hipLaunchKernelGGL(k_fan_count, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowN, w.wedge, N, w.fanrow,
+                       w.ctrl);
+    e = scan_inplace(w.fanrow + 1, N, w.scan_tmp, w.ctrl, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fan_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowN, w.wedge, N, w.fanrow,
+                       w.fan, w.ctrl);
     return hipGetLastError();
 }
 

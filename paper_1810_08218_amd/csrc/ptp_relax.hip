@@ -106,8 +106,8 @@ struct RelaxArgs {
     const int* perm;
     const int* iperm;
     const int* offsets;
-    const int* row;
-    const int2* wedge;
+    const int* fanrow;
+    const int* fan;
     const float4* xyz;
     float* dist;           // [2N]
     int* lab;              // [2N]
@@ -119,139 +119,165 @@ struct RelaxArgs {
     int* out_l;
 };
 
-// Wedges gathered together per vertex (mean degree 6; the minimum over
-// wedges does not depend on the grouping).
+// Fan entries held in registers per band vertex (closed fans of degree <= 6
+// and open ones of degree <= 5 in one go; longer fans continue in chunks).
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
-// Smallest planar update over the given wedges of a vertex at x0 (cnt <= C
-// valid entries), reading distances (and labels) from dold / lold: every
-// neighbour distance and coordinate at once (independent loads), then the
-// updates.  (value, label) lexicographic minimum folded into best / bl.
-template <bool LABELS, int C>
-__device__ inline void eval_wedges(const RelaxArgs& a, const float4 x0, const int2* wv, int cnt,
-                                   const float* dold, const int* lold, float& best, int& bl) {
-    float da[C], db[C];
-    float4 xa[C], xb[C];
-    int la[C], lb[C];
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        da[q] = ld_c(dold + wv[q].x);
-        db[q] = ld_c(dold + wv[q].y);
-        xa[q] = a.xyz[wv[q].x];
-        xb[q] = a.xyz[wv[q].y];
-        if (LABELS) {
-            la[q] = ld_c(lold + wv[q].x);
-            lb[q] = ld_c(lold + wv[q].y);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        if (q < cnt && fminf(da[q], db[q]) < kInf) {
-            int l = 0;
-            const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
-                                                 LABELS ? lb[q] : 0, l);
-            if (u < best || (LABELS && u == best && l < bl)) {
-                best = u;
-                bl = l;
-            }
+// Planar update of x0 from one triangle, folded into the (value, label)
+// lexicographic minimum best / bl, which does not depend on the order in
+// which the triangles come.
+template <bool LABELS>
+__device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, float d1, float d2,
+                                   int l1, int l2, float& best, int& bl) {
+    if (fminf(d1, d2) < kInf) {
+        int l = 0;
+        const float u = local_update<LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
+        if (u < best || (LABELS && u == best && l < bl)) {
+            best = u;
+            bl = l;
         }
     }
 }
 
-// Smallest planar update of position v over all its incident triangles,
-// kChunk wedges at a time (their ids first, then their data).
-template <bool LABELS, int kChunk>
+// The triangles of the first C entries of a fan of L entries (e: entries
+// with flags, entries past L repeat entry 0; d / x / l: their distances,
+// coordinates and labels).  Slot q (1 <= q <= C) is the pair (entry q-1,
+// entry q) for q < L unless entry q opens a chain, and the closing pair
+// (entry L-1, entry 0) for q = L on a closed fan.
+template <bool LABELS, int C>
+__device__ inline void eval_fan_first(const float4 x0, const int* e, const float* d, const float4* x,
+                                      const int* l, int L, float& best, int& bl) {
+    const bool closed = (e[0] & kFanClosed) != 0;
+#pragma unroll
+    for (int q = 1; q <= C; ++q) {
+        const int q2 = q < C ? q : 0;
+        const bool valid = q < C ? (q < L ? (e[q] & kFanStart) == 0 : (q == L && closed)) : (L == C && closed);
+        if (valid)
+            fold_update<LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0,
+                                LABELS ? l[q2] : 0, best, bl);
+    }
+}
+
+// The rest of a fan longer than C entries: chunks of C entries overlapping
+// by one, then the closing pair with entry 0 (d0 / xf / l0) on a closed fan.
+template <bool LABELS, int C>
+__device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0, int f0, int L,
+                                     bool closed, float d0, float4 xf, int l0, const float* dold,
+                                     const int* lold, float& best, int& bl) {
+    for (int base = C - 1; base < L - 1; base += C - 1) {
+        const int cnt = min(C, L - base);
+        int e[C], l[C];
+        float d[C];
+        float4 x[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) e[q] = q < cnt ? a.fan[f0 + base + q] : v;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int id = e[q] & kFanId;
+            d[q] = ld_c(dold + id);
+            x[q] = a.xyz[id];
+            l[q] = LABELS ? ld_c(lold + id) : 0;
+        }
+#pragma unroll
+        for (int q = 1; q < C; ++q)
+            if (q < cnt && (e[q] & kFanStart) == 0)
+                fold_update<LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl);
+        if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
+            const int id = a.fan[f0 + L - 1] & kFanId;
+            const float dl = ld_c(dold + id);
+            const float4 xl = a.xyz[id];
+            const int ll = LABELS ? ld_c(lold + id) : 0;
+            fold_update<LABELS>(x0, xl, xf, dl, d0, ll, l0, best, bl);
+        }
+    }
+}
+
+// First C entries of the fan at [f0, f0 + L) of position v, padded with
+// entry 0 (with v for an empty fan).
+template <bool LABELS, int C>
+__device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e) {
+    e[0] = L > 0 ? a.fan[f0] : v;
+#pragma unroll
+    for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
+}
+
+template <bool LABELS, int C>
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const float* dold, const int* lold,
+                                  float* d, float4* x, int* l) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int id = e[q] & kFanId;
+        d[q] = ld_c(dold + id);
+        x[q] = a.xyz[id];
+        if (LABELS) l[q] = ld_c(lold + id);
+    }
+}
+
+// Smallest planar update of position v over all its incident triangles.
+template <bool LABELS, int C>
 __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const float* dold,
                                    const int* lold, float& best, int& bl) {
     best = kInf;
     bl = 0x7fffffff;
-    const int e0 = a.row[v], e1 = a.row[v + 1];
-    for (int base = e0; base < e1; base += kChunk) {
-        const int cnt = min(kChunk, e1 - base);
-        int2 wv[kChunk];
-#pragma unroll
-        for (int q = 0; q < kChunk; ++q) wv[q] = q < cnt ? a.wedge[base + q] : make_int2(v, v);
-        eval_wedges<LABELS, kChunk>(a, x0, wv, cnt, dold, lold, best, bl);
-    }
+    const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
+    int e[C], l[C];
+    float d[C];
+    float4 x[C];
+    load_fan<LABELS, C>(a, v, f0, L, e);
+    gather_fan<LABELS, C>(a, e, dold, lold, d, x, l);
+    eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
+    if (L > C)
+        eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], LABELS ? l[0] : 0,
+                                 dold, lold, best, bl);
 }
 
 // Band positions p, p + gsz, ... (< be) of one thread, software-pipelined:
-// while the neighbour data of position p are in flight, the wedges of the
-// next position and the row of the one after are loaded, so a thread that
-// owns several band vertices waits for about one memory round per vertex
-// instead of three.  Returns the "not converged" vote of the positions
-// below tb.
+// while the neighbour data of position p are in flight, the fan entries of
+// the next position and the fan row of the one after are loaded, so a thread
+// that owns several band vertices waits for about one memory round per
+// vertex instead of three.  Returns the "not converged" vote of the
+// positions below tb.
 template <bool LABELS, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
                                                 long long tb, long long gsz, const float* dold,
                                                 float* dnew, const int* lold, int* lnew, bool local) {
     unsigned notconv = 0;
     if (p >= be) return 0;
-    int r0 = a.row[vo + p];
-    int cnt = a.row[vo + p + 1] - r0;
-    int2 w[C];
-#pragma unroll
-    for (int q = 0; q < C; ++q) w[q] = q < cnt ? a.wedge[r0 + q] : make_int2(vo + (int)p, vo + (int)p);
+    int f0 = a.fanrow[vo + p];
+    int L = a.fanrow[vo + p + 1] - f0;
+    int e[C];
+    load_fan<LABELS, C>(a, vo + (int)p, f0, L, e);
     long long pn = p + gsz;
-    int rn0 = 0, rn1 = 0;
+    int fn0 = 0, fn1 = 0;
     if (pn < be) {
-        rn0 = a.row[vo + pn];
-        rn1 = a.row[vo + pn + 1];
+        fn0 = a.fanrow[vo + pn];
+        fn1 = a.fanrow[vo + pn + 1];
     }
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
         const float dv = ld_c(dold + v);
-        float da[C], db[C];
-        float4 xa[C], xb[C];
-        int la[C], lb[C];
-#pragma unroll
-        for (int q = 0; q < C; ++q) {
-            da[q] = ld_c(dold + w[q].x);
-            db[q] = ld_c(dold + w[q].y);
-            xa[q] = a.xyz[w[q].x];
-            xb[q] = a.xyz[w[q].y];
-            if (LABELS) {
-                la[q] = ld_c(lold + w[q].x);
-                lb[q] = ld_c(lold + w[q].y);
-            }
-        }
-        // the next position's wedges and the row of the one after
+        int l[C];
+        float d[C];
+        float4 x[C];
+        gather_fan<LABELS, C>(a, e, dold, lold, d, x, l);
+        // the next position's fan entries and the fan row of the one after
         const long long pnn = pn + gsz;
-        const int cntn = rn1 - rn0;
-        int2 wn[C];
-        int rnn0 = 0, rnn1 = 0;
-        if (pn < be) {
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                wn[q] = q < cntn ? a.wedge[rn0 + q] : make_int2(vo + (int)pn, vo + (int)pn);
-        }
+        const int Ln = fn1 - fn0;
+        int en[C];
+        int fnn0 = 0, fnn1 = 0;
+        if (pn < be) load_fan<LABELS, C>(a, vo + (int)pn, fn0, Ln, en);
         if (pnn < be) {
-            rnn0 = a.row[vo + pnn];
-            rnn1 = a.row[vo + pnn + 1];
+            fnn0 = a.fanrow[vo + pnn];
+            fnn1 = a.fanrow[vo + pnn + 1];
         }
         float best = kInf;
         int bl = 0x7fffffff;
-#pragma unroll
-        for (int q = 0; q < C; ++q) {
-            if (q < cnt && fminf(da[q], db[q]) < kInf) {
-                int l = 0;
-                const float u = local_update<LABELS>(x0, xa[q], xb[q], da[q], db[q], LABELS ? la[q] : 0,
-                                                     LABELS ? lb[q] : 0, l);
-                if (u < best || (LABELS && u == best && l < bl)) {
-                    best = u;
-                    bl = l;
-                }
-            }
-        }
-        for (int base = r0 + C; base < r0 + cnt; base += C) {     // degree above C
-            const int c2 = min(C, r0 + cnt - base);
-            int2 wv[C];
-#pragma unroll
-            for (int q = 0; q < C; ++q) wv[q] = q < c2 ? a.wedge[base + q] : make_int2(v, v);
-            eval_wedges<LABELS, C>(a, x0, wv, c2, dold, lold, best, bl);
-        }
+        eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
+        if (L > C)
+            eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0],
+                                     LABELS ? l[0] : 0, dold, lold, best, bl);
         float dn = dv;
         if (best < dv) {
             dn = best;
@@ -267,12 +293,12 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
         if (pn >= be) break;
         p = pn;
         pn = pnn;
-        r0 = rn0;
-        cnt = cntn;
+        f0 = fn0;
+        L = Ln;
 #pragma unroll
-        for (int q = 0; q < C; ++q) w[q] = wn[q];
-        rn0 = rnn0;
-        rn1 = rnn1;
+        for (int q = 0; q < C; ++q) e[q] = en[q];
+        fn0 = fnn0;
+        fn1 = fnn1;
     }
     return notconv;
 }
@@ -286,60 +312,40 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
                                              long long gsz, float* d, bool local, int* rejected) {
     unsigned changed = 0;
     if (p >= end) return 0;
-    int r0 = a.row[vo + p];
-    int cnt = a.row[vo + p + 1] - r0;
-    int2 w[C];
-#pragma unroll
-    for (int q = 0; q < C; ++q) w[q] = q < cnt ? a.wedge[r0 + q] : make_int2(vo + (int)p, vo + (int)p);
+    int f0 = a.fanrow[vo + p];
+    int L = a.fanrow[vo + p + 1] - f0;
+    int e[C];
+    load_fan<false, C>(a, vo + (int)p, f0, L, e);
     long long pn = p + gsz;
-    int rn0 = 0, rn1 = 0;
+    int fn0 = 0, fn1 = 0;
     if (pn < end) {
-        rn0 = a.row[vo + pn];
-        rn1 = a.row[vo + pn + 1];
+        fn0 = a.fanrow[vo + pn];
+        fn1 = a.fanrow[vo + pn + 1];
     }
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
         const float wv = ld_c(d + v);
-        float da[C], db[C];
-        float4 xa[C], xb[C];
-#pragma unroll
-        for (int q = 0; q < C; ++q) {
-            da[q] = ld_c(d + w[q].x);
-            db[q] = ld_c(d + w[q].y);
-            xa[q] = a.xyz[w[q].x];
-            xb[q] = a.xyz[w[q].y];
-        }
+        int l[C];
+        float dd[C];
+        float4 x[C];
+        gather_fan<false, C>(a, e, d, nullptr, dd, x, l);
         const long long pnn = pn + gsz;
-        const int cntn = rn1 - rn0;
-        int2 wn[C];
-        int rnn0 = 0, rnn1 = 0;
-        if (pn < end) {
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                wn[q] = q < cntn ? a.wedge[rn0 + q] : make_int2(vo + (int)pn, vo + (int)pn);
-        }
+        const int Ln = fn1 - fn0;
+        int en[C];
+        int fnn0 = 0, fnn1 = 0;
+        if (pn < end) load_fan<false, C>(a, vo + (int)pn, fn0, Ln, en);
         if (pnn < end) {
-            rnn0 = a.row[vo + pnn];
-            rnn1 = a.row[vo + pnn + 1];
+            fnn0 = a.fanrow[vo + pnn];
+            fnn1 = a.fanrow[vo + pnn + 1];
         }
         if (wv < kInf) {
             float best = kInf;
-#pragma unroll
-            for (int q = 0; q < C; ++q) {
-                if (q < cnt && fminf(da[q], db[q]) < kInf) {
-                    int l = 0;
-                    best = fminf(best, local_update<false>(x0, xa[q], xb[q], da[q], db[q], 0, 0, l));
-                }
-            }
-            for (int base = r0 + C; base < r0 + cnt; base += C) {     // degree above C
-                const int c2 = min(C, r0 + cnt - base);
-                int2 wv2[C];
-#pragma unroll
-                for (int q = 0; q < C; ++q) wv2[q] = q < c2 ? a.wedge[base + q] : make_int2(v, v);
-                int bl = 0;
-                eval_wedges<false, C>(a, x0, wv2, c2, d, nullptr, best, bl);
-            }
+            int bl = 0;
+            eval_fan_first<false, C>(x0, e, dd, x, l, L, best, bl);
+            if (L > C)
+                eval_fan_rest<false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d,
+                                        nullptr, best, bl);
             if (wv < best) {
                 st_g(d + v, kInf, local);
                 changed = 1;
@@ -349,12 +355,12 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         if (pn >= end) break;
         p = pn;
         pn = pnn;
-        r0 = rn0;
-        cnt = cntn;
+        f0 = fn0;
+        L = Ln;
 #pragma unroll
-        for (int q = 0; q < C; ++q) w[q] = wn[q];
-        rn0 = rnn0;
-        rn1 = rnn1;
+        for (int q = 0; q < C; ++q) e[q] = en[q];
+        fn0 = fnn0;
+        fn1 = fnn1;
     }
     return changed;
 }
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 st_g(lA + p, (int)s, local);
                 st_g(lB + p, (int)s, local);
             }
-        for (long long r = g0; r < rho; r += gsz) retire[r] = r == 0 ? 0 : -1;
+        for (long long r = g0; r < rho; r += gsz) st_g(retire + r, r == 0 ? 0 : -1, local);
         if (!gb.sync(0, &any)) return;
 
         if (WARM) {
@@ -465,15 +471,15 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
         int i = 1, lo_prev = 1, k = 0, runstat = 0;
         long long upd = 0;
-        // CACHE: the incidence of the vertex this thread handled last.  While
-        // the band is no wider than the group's threads, a band vertex keeps
-        // its thread for every iteration it spends in the band, so after its
-        // first update only the neighbour distances are loaded.  (Costs
-        // registers, hence occupancy: used for single meshes.)
+        // CACHE: the fan of the vertex this thread handled last.  While the
+        // band is no wider than the group's threads, a band vertex keeps its
+        // thread for every iteration it spends in the band, so after its first
+        // update only the neighbour distances and coordinates are loaded.
+        // (Costs registers, hence occupancy: used for single meshes.)
         constexpr int kCache = kChunk;
-        int cv = -1, ccnt = 0;
+        int cv = -1, cL = 0;
         float4 cx0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        int2 cw[kCache];
+        int ce[kCache];
         while (i < rho) {
             if (k >= kmax) {
                 runstat = 1;
@@ -516,20 +522,20 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
                 if (cached && v != cv) {        // a vertex new to this thread
                     cx0 = a.xyz[v];
-                    const int e0 = a.row[v];
-                    ccnt = a.row[v + 1] - e0;
-                    cv = ccnt <= kCache ? v : -1;
-                    if (cv >= 0) {
-#pragma unroll
-                        for (int q = 0; q < kCache; ++q)
-                            cw[q] = q < ccnt ? a.wedge[e0 + q] : make_int2(v, v);
-                    }
+                    const int f0 = a.fanrow[v];
+                    cL = a.fanrow[v + 1] - f0;
+                    cv = cL <= kCache ? v : -1;
+                    if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
                 }
                 const float dv = ld_c(dold + v);
                 float best = kInf;
                 int bl = 0x7fffffff;
                 if (cached && cv == v) {
-                    eval_wedges<LABELS, kCache>(a, cx0, cw, ccnt, dold, lold, best, bl);
+                    int l[kCache];
+                    float d[kCache];
+                    float4 x[kCache];
+                    gather_fan<LABELS, kCache>(a, ce, dold, lold, d, x, l);
+                    eval_fan_first<LABELS, kCache>(cx0, ce, d, x, l, cL, best, bl);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
                     best_update<LABELS, kChunk>(a, v, x0, dold, lold, best, bl);
@@ -550,12 +556,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             upd += be - bb;
             if (!gb.sync(notconv, &any)) return;
             if (leader)
-                for (int r = i; r < lo; ++r) retire[r] = k - 1;      // pushed out by the window
+                for (int r = i; r < lo; ++r) st_g(retire + r, k - 1, local);   // pushed out by the window
             // Eq. lower_band.  V_lo may retire only after its second update
             // (k > lo): from +inf that is automatic, and a warm start keeps the
             // same causality, so the band never runs ahead of the front.
             if (!any && k > lo) {
-                if (leader) retire[lo] = k;
+                if (leader) st_g(retire + lo, k, local);
                 i = lo + 1;
             } else {
                 i = lo;
@@ -609,8 +615,8 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.perm = w.perm;
     a.iperm = w.iperm;
     a.offsets = w.offsets;
-    a.row = w.rowN;
-    a.wedge = w.wedge;
+    a.fanrow = w.fanrow;
+    a.fan = w.fan;
     a.xyz = w.xyz;
     a.dist = w.dist;
     a.lab = w.lab;

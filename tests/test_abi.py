@@ -37,9 +37,10 @@ def test_plan_rejects_bad_sizes(n, f, m, tol):
     assert e.value.status == P.PTP_EINVAL
 
 
-def test_plan_rejects_unsupported_sizes():
+@pytest.mark.parametrize("n,f", [((1 << 29) + 1, 4), (10, (1 << 31) // 6 + 1)])
+def test_plan_rejects_unsupported_sizes(n, f):
     with pytest.raises(P.PTPError) as e:
-        P.Plan((1 << 29) + 1, 4, 1, 1e-3)
+        P.Plan(n, f, 1, 1e-3)
     assert e.value.status == P.PTP_EUNSUPPORTED
 
 

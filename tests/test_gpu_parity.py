@@ -229,6 +229,39 @@ def test_edge_cases(cuda):
     assert g.dist[3] == 0 and np.isinf(np.delete(g.dist, 3)).all()
 
 
+def _irregular_fans_mesh():
+    """Fans of every shape the relaxation's incidence layout distinguishes:
+    a Delaunay triangulation of random points (degrees 3 to about 10, open
+    fans along the boundary) with a fifth of its faces flipped (wedges of
+    one fan in both orientations), a wheel of 24 triangles (a fan longer than
+    the chain limit) glued to it at one vertex (a non-manifold vertex with
+    two fans), and a duplicated face."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(17)
+    P2 = rng.random((2500, 2))
+    tri = Delaunay(P2)
+    F = tri.simplices.astype(np.int64)
+    flip = rng.random(F.shape[0]) < 0.2
+    F[flip] = F[flip][:, [0, 2, 1]]
+    V = np.column_stack([P2, 0.05 * np.sin(6 * P2[:, 0]) * np.cos(5 * P2[:, 1])])
+    hub = int(np.argmin(np.abs(P2 - 0.5).sum(axis=1)))      # shared with the wheel
+    k = 24
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    rim = np.column_stack([0.5 + 0.05 * np.cos(ang), 0.5 + 0.05 * np.sin(ang), 0.2 + 0.01 * np.sin(3 * ang)])
+    base = V.shape[0]
+    V = np.concatenate([V, rim])
+    W = np.array([[hub, base + i, base + (i + 1) % k] for i in range(k)])
+    F = np.concatenate([F, W, F[:1]])
+    S = np.array([0, hub, base + 5], np.int32)
+    return I.Mesh(V.astype(np.float32), F.astype(np.int32), S, name="irregular_fans")
+
+
+def test_parity_irregular_fans(cuda):
+    m = _irregular_fans_mesh()
+    check_parity(cuda, m, 1e-4, labels=True)
+    check_parity(cuda, m, 1e-4)
+
+
 def test_invalid_inputs_are_rejected(cuda):
     import torch
     m = I.flat_grid(8)
