@@ -69,6 +69,33 @@ __device__ inline unsigned xcc_id() {
 // a compiler barrier: no access moves across it.
 __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Workgroup barrier that orders LDS only: each wave waits for its own LDS
+// operations, not for its outstanding global stores (__syncthreads waits for
+// those too, a full memory round trip when they are scattered).
+__device__ inline void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// OR of `v` (bits 0 and 1) over the workgroup: ballots per wave, one LDS
+// word per wave, one LDS-only barrier.  `slots` holds two sets of one word
+// per wave, used in turn (`par` flips on every call), so that a wave writing
+// the words of the next call cannot overwrite those another wave is still
+// reading (it can only get there after the next call's barrier, which every
+// wave reaches after its reads).
+__device__ inline unsigned block_or(unsigned v, unsigned* slots, unsigned& par) {
+    constexpr int kWaves = kBlock / kWave;
+    unsigned* set = slots + par * kWaves;
+    par ^= 1u;
+    const unsigned long long b0 = __ballot((v & 1u) != 0);
+    const unsigned long long b1 = __ballot((v & 2u) != 0);
+    if ((threadIdx.x & (kWave - 1)) == 0) set[threadIdx.x / kWave] = (b0 ? 1u : 0u) | (b1 ? 2u : 0u);
+    lds_barrier();
+    unsigned r = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) r |= set[w];
+    return r;
+}
+
 // ---- group barrier -----------------------------------------------------
 // Flag-array barrier among the gsize workgroups of a group of a cooperative
 // launch.  Every workgroup publishes (epoch << 1 | bit) in its own 128-byte
@@ -83,7 +110,9 @@ __device__ inline void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "me
 // complete into an abort flag instead of a hang: the workgroups whose wait
 // times out raise the flag and leave; the flag is not read on the way (every
 // workgroup of a stuck group times out by itself), which saves a memory
-// round trip per barrier.
+// round trip per barrier.  The votes inside the workgroup go through LDS
+// words and LDS-only barriers (block_or), not through __syncthreads_or /
+// __syncthreads_and, which cost several times more.
 //
 // Ordering: each wave waits for its own coherent stores to complete before
 // the workgroup publishes; loads after the barrier are coherent loads issued
@@ -96,18 +125,28 @@ struct FlagBarrier {
     unsigned gsize, rank;
     unsigned epoch;
     bool local = false;  // the whole group runs on one XCD: plain flag stores
+    unsigned* slots = nullptr;   // LDS: 2 * kBlock / kWave words (block_or)
+    unsigned par = 0;
 
     static constexpr long long kTimeoutTicks = 400000000ll;   // seconds at 100 MHz
 
+    // Wait until the line at p holds an epoch >= want.  The clock is read
+    // every 64 polls only, the first time after 64 (a read costs a scalar
+    // memory round trip, which would delay the next poll).
     __device__ bool spin_ge(const unsigned* p, unsigned want, unsigned* seen) {
-        const long long t0 = wall_clock64();
+        long long t0 = 0;
         unsigned v;
-        while (((v = ld_c(p)) >> 1) < want) {
+        for (unsigned n = 1; ((v = ld_c(p)) >> 1) < want; ++n) {
             __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > kTimeoutTicks) {
-                __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *seen = 0;
-                return false;
+            if ((n & 63u) == 0) {
+                const long long t = wall_clock64();
+                if (n == 64) {
+                    t0 = t;
+                } else if (t - t0 > kTimeoutTicks) {
+                    __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    *seen = 0;
+                    return false;
+                }
             }
         }
         *seen = v;
@@ -119,7 +158,7 @@ struct FlagBarrier {
     __device__ bool sync(unsigned bit, unsigned* any) {
         const unsigned tid = threadIdx.x;
         wait_memory();
-        bit = __syncthreads_or(bit) ? 1u : 0u;
+        bit = block_or(bit ? 1u : 0u, slots, par);
         if (gsize == 1) {            // a group of one workgroup: the block barrier suffices
             *any = bit;
             return true;
@@ -128,18 +167,17 @@ struct FlagBarrier {
         unsigned* lines = (epoch & 1u) ? bank1 : bank0;
         if (tid == 0) st_g(lines + (size_t)rank * kLine, (epoch << 1) | bit, local);
         unsigned acc = 0;
-        int ok = 1;
         for (unsigned x = tid; x < gsize; x += blockDim.x) {
             unsigned v;
             if (!spin_ge(lines + (size_t)x * kLine, epoch, &v)) {
-                ok = 0;
+                acc |= 2u;
                 break;
             }
             acc |= v & 1u;
         }
-        *any = __syncthreads_or(acc) ? 1u : 0u;
-        ok = __syncthreads_and(ok);
-        return ok;   // a timed-out wait raised the abort flag itself
+        const unsigned r = block_or(acc, slots, par);
+        *any = r & 1u;
+        return (r & 2u) == 0;   // a timed-out wait raised the abort flag itself
     }
 };
 
@@ -153,13 +191,6 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
         else hi = mid;
     }
     return lo;
-}
-
-// Workgroup barrier that orders LDS only: each wave waits for its own LDS
-// operations, not for its outstanding global stores (__syncthreads waits for
-// those too, a full memory round trip when they are scattered).
-__device__ inline void lds_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // ---- block-wide scans --------------------------------------------------

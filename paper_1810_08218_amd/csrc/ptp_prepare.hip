@@ -213,8 +213,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize, w = me.rank, tid = threadIdx.x;
+    __shared__ unsigned bar_slots[2 * kBlock / kWave];
     FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.first) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)w, 0};
+    gb.slots = bar_slots;
     unsigned any = 0;
     const long long gsz = (long long)gs * kBlock;
     const long long g0 = (long long)w * kBlock + tid;

@@ -31,7 +31,7 @@ __device__ inline float dot3(float ax, float ay, float az, float bx, float by, f
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Planar update of x0 from (x1, d1), (x2, d2), at least one of d1, d2 finite.
+// Planar update of x0 from (x1, d1), (x2, d2).
 //
 // With e_i = x_i - x0, a = e1.e1, b = e1.e2, c = e2.e2, det = |e1 x e2|^2,
 // A = |x1 - x2|^2, delta = d2 - d1, the plane front through (x1, d1), (x2, d2)
@@ -44,6 +44,12 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // (Q X^T n < 0, both components):  q (c - b) + b delta > 0  and
 // q (a - b) > a delta; otherwise the edge updates d_i + |e_i| give the value.
 // Label: edge update -> its vertex; planar value -> its smaller input.
+//
+// Written without branches: every term is computed and the result selected,
+// so the updates of a vertex's triangles interleave instead of running one
+// after the other.  An infinite input needs no case of its own: its edge
+// update is infinite and the discriminant is -inf or NaN, so the finite edge
+// update is selected (both infinite: +inf).
 template <bool LABELS>
 __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, float d2, int l1,
                                      int l2, int& lab) {
@@ -51,27 +57,8 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
     const float e2x = x2.x - x0.x, e2y = x2.y - x0.y, e2z = x2.z - x0.z;
     const float a = dot3(e1x, e1y, e1z, e1x, e1y, e1z);
     const float c = dot3(e2x, e2y, e2z, e2x, e2y, e2z);
-    if (!(d2 < kInf)) {
-        if (LABELS) lab = l1;
-        return d1 + fsqrt(a);
-    }
-    if (!(d1 < kInf)) {
-        if (LABELS) lab = l2;
-        return d2 + fsqrt(c);
-    }
     const float p1 = d1 + fsqrt(a), p2 = d2 + fsqrt(c);
-    float pe;
-    int le = 0;
-    if (p1 < p2) {
-        pe = p1;
-        if (LABELS) le = l1;
-    } else if (p2 < p1) {
-        pe = p2;
-        if (LABELS) le = l2;
-    } else {
-        pe = p1;
-        if (LABELS) le = min(l1, l2);
-    }
+    const float pe = p2 < p1 ? p2 : p1;
     const float b = dot3(e1x, e1y, e1z, e2x, e2y, e2z);
     const float cx = e1y * e2z - e1z * e2y;
     const float cy = e1z * e2x - e1x * e2z;
@@ -81,15 +68,16 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
     const float A = dot3(fx, fy, fz, fx, fy, fz);
     const float delta = d2 - d1;
     const float disc = det * (A - delta * delta);
-    if (det > 1e-12f * a * c && disc >= 0.f) {
-        const float q = (delta * (a - b) + fsqrt(disc)) * frcp(A);
-        if (q * (c - b) + b * delta > 0.f && q * (a - b) > a * delta) {
-            if (LABELS) lab = d1 < d2 ? l1 : (d2 < d1 ? l2 : min(l1, l2));
-            return d1 + q;
-        }
+    const float q = (delta * (a - b) + fsqrt(disc)) * frcp(A);
+    const bool planar = det > 1e-12f * a * c && disc >= 0.f && q * (c - b) + b * delta > 0.f &&
+                        q * (a - b) > a * delta;
+    if (LABELS) {
+        const int lmin = min(l1, l2);
+        const int le = p1 < p2 ? l1 : (p2 < p1 ? l2 : lmin);
+        const int lp = d1 < d2 ? l1 : (d2 < d1 ? l2 : lmin);
+        lab = planar ? lp : le;
     }
-    if (LABELS) lab = le;
-    return pe;
+    return planar ? d1 + q : pe;
 }
 
 struct RelaxArgs {
@@ -129,15 +117,12 @@ constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 // which the triangles come.
 template <bool LABELS>
 __device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, float d1, float d2,
-                                   int l1, int l2, float& best, int& bl) {
-    if (fminf(d1, d2) < kInf) {
-        int l = 0;
-        const float u = local_update<LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
-        if (u < best || (LABELS && u == best && l < bl)) {
-            best = u;
-            bl = l;
-        }
-    }
+                                   int l1, int l2, float& best, int& bl, bool valid = true) {
+    int l = 0;
+    const float u = local_update<LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
+    const bool take = valid && (u < best || (LABELS && u == best && l < bl && u < kInf));
+    best = take ? u : best;
+    if (LABELS) bl = take ? l : bl;
 }
 
 // The triangles of the first C entries of a fan of L entries (e: entries
@@ -153,9 +138,8 @@ __device__ inline void eval_fan_first(const float4 x0, const int* e, const float
     for (int q = 1; q <= C; ++q) {
         const int q2 = q < C ? q : 0;
         const bool valid = q < C ? (q < L ? (e[q] & kFanStart) == 0 : (q == L && closed)) : (L == C && closed);
-        if (valid)
-            fold_update<LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0,
-                                LABELS ? l[q2] : 0, best, bl);
+        fold_update<LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0,
+                            LABELS ? l[q2] : 0, best, bl, valid);
     }
 }
 
@@ -181,8 +165,8 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
         }
 #pragma unroll
         for (int q = 1; q < C; ++q)
-            if (q < cnt && (e[q] & kFanStart) == 0)
-                fold_update<LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl);
+            fold_update<LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl,
+                                q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
             const float dl = ld_c(dold + id);
@@ -365,6 +349,18 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
     return changed;
 }
 
+// The smallest position >= c that group thread g (of gsz) owns, c >= 0, in
+// 32-bit arithmetic (positions stay below 2^29, groups below 2^18 threads).
+__device__ inline int first_owned(int c, int g, int gsz) {
+    int r = g - c % gsz;
+    if (r < 0) r += gsz;
+    return c + r;
+}
+
+// Topleset starts staged in LDS for meshes with at most this many toplesets
+// (read four times per iteration on the critical path).
+constexpr int kOffsLds = 4096;
+
 // Groups of consecutive workgroups run the whole iteration of one mesh at a
 // time, with a barrier of their own.  Per iteration k every thread of the
 // group takes band vertices in a strided loop; position p of the mesh is
@@ -379,9 +375,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize;
+    __shared__ unsigned bar_slots[2 * kBlock / kWave];
+    __shared__ int s_offs[kOffsLds];
     FlagBarrier gb{a.bar + (size_t)me.first * kLine, a.bar + (size_t)(a.G + me.first) * kLine,
                    a.ctrl + C_ABORT, (unsigned)gs, (unsigned)me.rank, 0};
+    gb.slots = bar_slots;
     unsigned any = 0;
+    const int gsz32 = gs * kBlock;
+    const int g032 = me.rank * kBlock + (int)threadIdx.x;
     const long long gsz = (long long)gs * kBlock;
     const long long g0 = (long long)me.rank * kBlock + threadIdx.x;
     const bool leader = me.rank == 0 && threadIdx.x == 0;
@@ -415,6 +416,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         int* retire = a.retire + vo;
         const int kmax = a.kmax_fixed > 0 ? a.kmax_fixed : 4 * rho + 16;
         const int m0 = offs[1];                  // |V_0|: the sources occupy [0, m0)
+        // every read of s_offs of the previous mesh came before its last barrier
+        const bool offs_lds = rho < kOffsLds;
+        if (offs_lds)
+            for (int r = threadIdx.x; r <= rho; r += kBlock) s_offs[r] = offs[r];
 
         const int reach = a.state[b].reach;
         for (long long p = g0; p < n; p += gsz) {
@@ -448,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             // so the min-relaxation from it descends to the same fixed point.
             // Marking only raises U elsewhere, so the closure is unique and the
             // order of the in-place updates does not matter.
-            const long long firstc = m0 + ((g0 - m0 % gsz) + gsz) % gsz;
+            const long long firstc = first_owned(m0, g032, gsz32);
             int rejected = 0, round = 0;
             for (;; ++round) {
                 const unsigned changed =
@@ -475,11 +480,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         // band is no wider than the group's threads, a band vertex keeps its
         // thread for every iteration it spends in the band, so after its first
         // update only the neighbour distances and coordinates are loaded.
+        // The thread's next position (the first it owns past the band) is
+        // fetched ahead, one dependent step per iteration (fan row and
+        // coordinates, then fan entries), while the band works: a vertex
+        // entering the band then costs one memory round trip, not three.
         // (Costs registers, hence occupancy: used for single meshes.)
         constexpr int kCache = kChunk;
         int cv = -1, cL = 0;
         float4 cx0 = make_float4(0.f, 0.f, 0.f, 0.f);
         int ce[kCache];
+        int nv = -1, ns = 0, nf0 = 0, nL = 0;        // next position: 1 row read, 2 entries read
+        float4 nx0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        int ne[kCache];
         while (i < rho) {
             if (k >= kmax) {
                 runstat = 1;
@@ -493,12 +505,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             float* dnew = (k & 1) ? dB : dA;
             const int* lold = (k & 1) ? lA : lB;
             int* lnew = (k & 1) ? lB : lA;
-            const int cb = offs[lo_prev];   // retired since last iteration: copy
-            const int bb = offs[lo];        // band
-            const int be = offs[j + 1];
-            const int tb = offs[lo + 1];    // tested topleset V_lo = [bb, tb)
+            const int cb = offs_lds ? s_offs[lo_prev] : offs[lo_prev];   // retired since last iteration: copy
+            const int bb = offs_lds ? s_offs[lo] : offs[lo];             // band
+            const int be = offs_lds ? s_offs[j + 1] : offs[j + 1];
+            const int tb = offs_lds ? s_offs[lo + 1] : offs[lo + 1];     // tested topleset V_lo = [bb, tb)
             unsigned notconv = 0;
-            const long long first = cb + ((g0 - cb % gsz) + gsz) % gsz;
+            const long long first = first_owned(cb, g032, gsz32);
             // pipelined unless the register cache serves (one position per
             // thread)
             const bool pipe = !(CACHE && be - cb <= gsz);
@@ -507,10 +519,30 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     st_g(dnew + vo + (int)pp, ld_c(dold + vo + (int)pp), local);
                     if (LABELS) st_g(lnew + vo + (int)pp, ld_c(lold + vo + (int)pp), local);
                 }
-                const long long firstb = bb + ((g0 - bb % gsz) + gsz) % gsz;
+                const long long firstb = first_owned(bb, g032, gsz32);
                 notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
                                                                 lold, lnew, local);
                 cv = -1;
+                nv = -1;
+            } else if (CACHE) {
+                // one step of the fetch-ahead of the next position
+                const int tq = first_owned(be, g032, gsz32);
+                const int tv = tq < reach ? vo + tq : -1;
+                if (tv != nv) {
+                    nv = tv;
+                    ns = 0;
+                }
+                if (nv >= 0) {
+                    if (ns == 0) {
+                        nx0 = a.xyz[nv];
+                        nf0 = a.fanrow[nv];
+                        nL = a.fanrow[nv + 1] - nf0;
+                        ns = 1;
+                    } else if (ns == 1 && nL <= kCache) {
+                        load_fan<LABELS, kCache>(a, nv, nf0, nL, ne);
+                        ns = 2;
+                    }
+                }
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
@@ -521,11 +553,23 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
                 if (cached && v != cv) {        // a vertex new to this thread
-                    cx0 = a.xyz[v];
-                    const int f0 = a.fanrow[v];
-                    cL = a.fanrow[v + 1] - f0;
-                    cv = cL <= kCache ? v : -1;
-                    if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
+                    if (v == nv && ns >= 1) {   // fetched ahead
+                        cx0 = nx0;
+                        cL = nL;
+                        cv = cL <= kCache ? v : -1;
+                        if (ns == 2) {
+#pragma unroll
+                            for (int q = 0; q < kCache; ++q) ce[q] = ne[q];
+                        } else if (cv >= 0) {
+                            load_fan<LABELS, kCache>(a, v, nf0, cL, ce);
+                        }
+                    } else {
+                        cx0 = a.xyz[v];
+                        const int f0 = a.fanrow[v];
+                        cL = a.fanrow[v + 1] - f0;
+                        cv = cL <= kCache ? v : -1;
+                        if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
+                    }
                 }
                 const float dv = ld_c(dold + v);
                 float best = kInf;
