@@ -480,18 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         // band is no wider than the group's threads, a band vertex keeps its
         // thread for every iteration it spends in the band, so after its first
         // update only the neighbour distances and coordinates are loaded.
-        // The thread's next position (the first it owns past the band) is
-        // fetched ahead, one dependent step per iteration (fan row and
-        // coordinates, then fan entries), while the band works: a vertex
-        // entering the band then costs one memory round trip, not three.
         // (Costs registers, hence occupancy: used for single meshes.)
         constexpr int kCache = kChunk;
         int cv = -1, cL = 0;
         float4 cx0 = make_float4(0.f, 0.f, 0.f, 0.f);
         int ce[kCache];
-        int nv = -1, ns = 0, nf0 = 0, nL = 0;        // next position: 1 row read, 2 entries read
-        float4 nx0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        int ne[kCache];
         while (i < rho) {
             if (k >= kmax) {
                 runstat = 1;
@@ -523,26 +516,6 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
                                                                 lold, lnew, local);
                 cv = -1;
-                nv = -1;
-            } else if (CACHE) {
-                // one step of the fetch-ahead of the next position
-                const int tq = first_owned(be, g032, gsz32);
-                const int tv = tq < reach ? vo + tq : -1;
-                if (tv != nv) {
-                    nv = tv;
-                    ns = 0;
-                }
-                if (nv >= 0) {
-                    if (ns == 0) {
-                        nx0 = a.xyz[nv];
-                        nf0 = a.fanrow[nv];
-                        nL = a.fanrow[nv + 1] - nf0;
-                        ns = 1;
-                    } else if (ns == 1 && nL <= kCache) {
-                        load_fan<LABELS, kCache>(a, nv, nf0, nL, ne);
-                        ns = 2;
-                    }
-                }
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
@@ -553,23 +526,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
                 if (cached && v != cv) {        // a vertex new to this thread
-                    if (v == nv && ns >= 1) {   // fetched ahead
-                        cx0 = nx0;
-                        cL = nL;
-                        cv = cL <= kCache ? v : -1;
-                        if (ns == 2) {
-#pragma unroll
-                            for (int q = 0; q < kCache; ++q) ce[q] = ne[q];
-                        } else if (cv >= 0) {
-                            load_fan<LABELS, kCache>(a, v, nf0, cL, ce);
-                        }
-                    } else {
-                        cx0 = a.xyz[v];
-                        const int f0 = a.fanrow[v];
-                        cL = a.fanrow[v + 1] - f0;
-                        cv = cL <= kCache ? v : -1;
-                        if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
-                    }
+                    cx0 = a.xyz[v];
+                    const int f0 = a.fanrow[v];
+                    cL = a.fanrow[v + 1] - f0;
+                    cv = cL <= kCache ? v : -1;
+                    if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
                 }
                 const float dv = ld_c(dold + v);
                 float best = kInf;
