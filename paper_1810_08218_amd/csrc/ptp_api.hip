@@ -229,6 +229,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * B,                       // lds_mesh
         sizeof(int) * (N + 1),                 // fanrow
         sizeof(int) * (2 * F3 + 1),            // fan
+        sizeof(int) * kEll * N,                // ellO
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -274,6 +275,7 @@ Work carve(void* base, const Layout& L) {
     w.lds_mesh = reinterpret_cast<int*>(b + L.off[29]);
     w.fanrow = reinterpret_cast<int*>(b + L.off[30]);
     w.fan = reinterpret_cast<int*>(b + L.off[31]);
+    w.ellO = reinterpret_cast<int*>(b + L.off[32]);
     return w;
 }
 
@@ -409,14 +411,14 @@ struct Solver {
         sched = d;
     }
 
-    // Single mesh: one group; about one workgroup per 1024 reachable vertices
-    // within [16, 512] (the per-iteration cost is flat from ~n/2048 to ~n/512
+    // Single mesh: one group; about one workgroup per 1536 reachable vertices
+    // up to 512 (the per-iteration cost is flat from ~n/2048 to ~n/1024
     // workgroups on the icosphere workloads and rises outside).  Up to ~48
     // of them, 32 workgroups placed on one XCD do better (the group then
     // exchanges its data through one L2).
     int single_group(int gmax, long long reach) const {
         if (opt.workgroups > 0) return std::min(opt.workgroups, gmax);
-        long long g = reach / 1024;
+        long long g = reach / 1536;
         g = g <= 48 ? 32 : std::min(512ll, g);
         return (int)std::min<long long>(g, gmax);
     }

@@ -69,9 +69,16 @@ struct Work {
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
     int* fanrow;        // [N + 1] fan CSR over positions
     int* fan;           // [6F]    fans of the incident triangles, positions and flags
+    int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
 };
 
-constexpr int kLayoutParts = 32;
+constexpr int kLayoutParts = 33;
+
+// Neighbour rows of the BFS: the distinct neighbours of a vertex in one
+// 32-byte row, padded with -1; a vertex with more keeps kEllMore in its last
+// entry and is expanded from its incidence instead.
+constexpr int kEll = 8;
+constexpr int kEllMore = -2;
 
 // Fan of a position: its incident triangles as chains of neighbours.  Wedges
 // (a, b) and (b, c) of triangles adjacent around the vertex share b, so a

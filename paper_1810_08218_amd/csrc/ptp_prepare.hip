@@ -103,6 +103,41 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
     }
 }
 
+// Distinct neighbours of every vertex from its wedges, into its row of ellO.
+__global__ __launch_bounds__(kBlock) void k_ell(const int* row, const int2* wedgeO, long long N, int* ellO,
+                                                const int* ctrl) {
+    if (gated(ctrl)) return;
+    const long long gsz = (long long)gridDim.x * kBlock;
+    for (long long v = blockIdx.x * (long long)kBlock + threadIdx.x; v < N; v += gsz) {
+        int nb[kEll];
+#pragma unroll
+        for (int q = 0; q < kEll; ++q) nb[q] = -1;
+        int cnt = 0;
+        const int e0 = row[v], e1 = row[v + 1];
+        for (int e = e0; e < e1 && cnt <= kEll; ++e) {
+            const int2 t = wedgeO[e];
+            const int xs[2] = {t.x, t.y};
+            for (int z = 0; z < 2; ++z) {
+                bool seen = false;
+#pragma unroll
+                for (int q = 0; q < kEll; ++q) seen |= nb[q] == xs[z];
+                if (!seen) {
+                    if (cnt < kEll) {
+#pragma unroll
+                        for (int q = 0; q < kEll; ++q)
+                            if (q == cnt) nb[q] = xs[z];
+                    }
+                    ++cnt;
+                }
+            }
+        }
+        if (cnt > kEll) nb[kEll - 1] = kEllMore;
+        int4* out = reinterpret_cast<int4*>(ellO + kEll * v);
+        out[0] = make_int4(nb[0], nb[1], nb[2], nb[3]);
+        out[1] = make_int4(nb[4], nb[5], nb[6], nb[7]);
+    }
+}
+
 // ---- in-place inclusive scan of a[0..len) (three passes) ----------------
 __device__ inline int tile_load_scan(int* a, long long len, long long base, int* tile_sum,
                                      int* vals) {
@@ -391,6 +426,7 @@ struct BfsLdsArgs {
     const int* S;
     const int* row;        // rowO
     const int2* wedgeO;    // global ids
+    const int* ellO;       // neighbour rows, global ids
     int* level;
     int* perm;
     int* iperm;
@@ -479,6 +515,21 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
         lds_barrier();
         for (int t = tid; t < total; t += kLdsBlock) {
             const int u = t < kLdsList ? list[t] : ld_c(a.perm + vo + base + t) - vo;
+            // the neighbour row in one round trip (two 16-byte loads)
+            const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + u));
+            const int4 r0 = er[0], r1 = er[1];
+            const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+            if (ev[kEll - 1] != kEllMore) {
+#pragma unroll
+                for (int q = 0; q < kEll; ++q) {
+                    if (ev[q] < 0) continue;
+                    const int x = ev[q] - vo;
+                    const unsigned bit = 1u << (x & 31);
+                    if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit))
+                        atomicOr(nxt + (x >> 5), bit);
+                }
+                continue;
+            }
             const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
             for (int eb = e0; eb < e1; eb += kExpand) {
                 // the wedges' loads first (independent), then the LDS marks
@@ -684,6 +735,8 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
                        w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
+    if (n_lds > 0)
+        hipLaunchKernelGGL(k_ell, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -712,6 +765,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
         l.S = S;
         l.row = w.rowO;
         l.wedgeO = w.wedgeO;
+        l.ellO = w.ellO;
         l.level = w.level;
         l.perm = w.perm;
         l.iperm = w.iperm;
