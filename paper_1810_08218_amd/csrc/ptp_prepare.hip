@@ -219,6 +219,7 @@ struct BfsArgs {
     const int* S;
     const int* row;
     const int2* wedgeO;
+    const int* ellO;       // neighbour rows, global ids
     int* level;
     int* perm;
     int* iperm;
@@ -342,6 +343,26 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsArgs a) {
                 }
                 for (int t = tid; t < cntl; t += kBlock) {
                     const int u = vo + list[t];
+                    // the neighbour row, then the neighbours' levels
+                    // (independent loads), then a CAS for the unvisited ones
+                    const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * u);
+                    const int4 r0 = er[0], r1 = er[1];
+                    const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+                    if (ev[kEll - 1] != kEllMore) {
+                        int lv[kEll];
+#pragma unroll
+                        for (int q = 0; q < kEll; ++q) lv[q] = ld_c(a.level + (ev[q] >= 0 ? ev[q] : u));
+#pragma unroll
+                        for (int q = 0; q < kEll; ++q) {
+                            const int x = ev[q];
+                            if (x >= 0 && lv[q] < 0 && atomicCAS(a.level + x, -1, lvl) == -1) {
+                                const int xl = x - vo;
+                                atomicOr(nxt + (xl >> 5), 1u << (xl & 31));
+                                atomicAdd(cn + (xl >> 5) / cw, 1);
+                            }
+                        }
+                        continue;
+                    }
                     const int e0 = a.row[u], e1 = a.row[u + 1];
                     for (int eb = e0; eb < e1; eb += kExpandG) {
                         // wedges, then their neighbours' levels (independent
@@ -735,8 +756,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
                        w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
-    if (n_lds > 0)
-        hipLaunchKernelGGL(k_ell, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
+    hipLaunchKernelGGL(k_ell, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -749,6 +769,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     a.S = S;
     a.row = w.rowO;
     a.wedgeO = w.wedgeO;
+    a.ellO = w.ellO;
     a.level = w.level;
     a.perm = w.perm;
     a.iperm = w.iperm;
