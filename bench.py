@@ -246,6 +246,75 @@ def bench_batched(steps, P, I, warm=True):
             "warm_start": bench_warm(b, out_len, stream, 3) if warm else None}
 
 
+def bench_source_sets(P, I, sets=64, steps=3):
+    """The 2.6M-vertex bumpy icosphere with 64 seeded sets of 32 sources
+    (Voronoi labels, tol 1e-4): one batch whose meshes share the V and F rows,
+    against one plan re-prepared per source set (run time summed)."""
+    import torch
+    note(f"source sets: bumpy icosphere level 9 x {sets} source sets")
+    base = I.bumpy_icosphere(level=9, seed=3, n_sources=32)
+    rng = np.random.default_rng(31)
+    meshes = [I.Mesh(base.V, base.F, rng.choice(base.n, 32, replace=False).astype(np.int32),
+                     name=f"set{k}") for k in range(sets)]
+    V, F, S, descs, out_len = P.concat(meshes, [None] + [0] * (sets - 1))
+    dV, dF, dS = (torch.from_numpy(x).cuda() for x in (V, F, S))
+    tol = 1e-4
+    b = P.Batch(descs, tol, want_labels=True)
+    work = b.workspace()
+    dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
+    lab = torch.empty(out_len, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    b.prepare(dV, dF, dS, work=work, stream=stream)
+    best = None
+    for lg in (16, 32, 64):
+        b.set_schedule(workgroups=1 << 20, small_limit=1, large_limit=1, large_group=lg)
+        ms = _timed(lambda: b.run(dist, lab, stream=stream), stream, 1)
+        if best is None or ms < best[0]:
+            best = (ms, lg)
+    b.set_schedule(workgroups=1 << 20, small_limit=1, large_limit=1, large_group=best[1])
+    prep, runs = [], []
+    for _ in range(steps):
+        a0, a1, a2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a0.record(stream)
+        b.prepare(dV, dF, dS, work=work, stream=stream)
+        a1.record(stream)
+        b.run(dist, lab, stream=stream)
+        a2.record(stream)
+        rc, stats, _ = b.stats()
+        prep.append(a0.elapsed_time(a1))
+        runs.append(a1.elapsed_time(a2))
+    ms_run = statistics.median(runs)
+    U = sum(x["vertex_updates"] for x in stats)
+    note("source sets: one plan per source set")
+    plan = P.Plan(base.n, base.f, 32, tol, want_labels=True)
+    d1 = torch.empty(base.n, dtype=torch.float32, device="cuda")
+    l1 = torch.empty(base.n, dtype=torch.int32, device="cuda")
+    single_ms, same = 0.0, True
+    for k, m in enumerate(meshes):
+        plan.prepare(dV[:base.n], dF[:base.f], torch.from_numpy(m.S).cuda(), stream=stream)
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.run(d1, l1, stream=stream)
+        z.record(stream)
+        plan.stats()
+        single_ms += a.elapsed_time(z)
+        if k < 4:
+            o0 = int(descs[k].out_off)
+            same &= bool(torch.equal(d1, dist[o0:o0 + base.n]) and torch.equal(l1, lab[o0:o0 + base.n]))
+    alg = U * (BYTES_PER_UPDATE + 8)
+    return {"workload": f"bumpy icosphere level 9 (2,621,442 vertices) x {sets} source sets of 32, "
+                        "labels, tol 1e-4, seed 31",
+            "status": rc, "ms_to_converge": round(ms_run, 3), "ms_prepare": round(statistics.median(prep), 3),
+            "vertex_updates": int(U), "vertex_updates_per_s": round(U / (ms_run * 1e-3), 1),
+            "alg_GBps": round(alg / (ms_run * 1e-3) / 1e9, 1),
+            "alg_frac_of_hbm": round(alg / (ms_run * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_update": BYTES_PER_UPDATE + 8, "large_group": best[1],
+            "single_plan_ms_to_converge_sum": round(single_ms, 3),
+            "speedup_vs_single_plans": round(single_ms / ms_run, 3),
+            "first_4_sets_identical_to_single_plans": same,
+            "workspace_GB": round(work.numel() / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +327,8 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start legs")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the flat-grid and bumpy-icosphere timings")
+    ap.add_argument("--no-source-sets", action="store_true",
+                    help="skip the 64-source-set batch on the level-9 icosphere")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 device copies of 256 MiB (a kernel of known traffic for "
                          "scaling the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -369,6 +440,7 @@ def main():
     line["warm_start"] = warm
     line["other_configs"] = None if args.no_configs else bench_other_configs(P, I)
     line["batched"] = batched
+    line["source_sets"] = None if (args.no_source_sets or args.no_batched) else bench_source_sets(P, I)
     print(json.dumps(line), flush=True)
 
 
