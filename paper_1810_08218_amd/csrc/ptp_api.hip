@@ -222,7 +222,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int2) * (F3 + 1),               // wedge
         sizeof(float4) * N,                    // xyz
         sizeof(float) * 2 * N,                 // dist
-        sizeof(int) * 2 * N,                   // lab
+        sizeof(unsigned long long) * 2 * N,    // dl
         sizeof(unsigned) * 2 * (size_t)z.W,    // bits
         sizeof(int) * 4 * G,                   // cnt
         sizeof(int) * N,                       // retire
@@ -268,7 +268,7 @@ Work carve(void* base, const Layout& L) {
     w.wedge = reinterpret_cast<int2*>(b + L.off[18]);
     w.xyz = reinterpret_cast<float4*>(b + L.off[19]);
     w.dist = reinterpret_cast<float*>(b + L.off[20]);
-    w.lab = reinterpret_cast<int*>(b + L.off[21]);
+    w.dl = reinterpret_cast<unsigned long long*>(b + L.off[21]);
     w.bits = reinterpret_cast<unsigned*>(b + L.off[22]);
     w.cnt = reinterpret_cast<int*>(b + L.off[23]);
     w.retire = reinterpret_cast<int*>(b + L.off[24]);

@@ -58,7 +58,7 @@ struct Work {
     int2* wedge;        // [3F]    opposite edge, positions
     float4* xyz;        // [N]     coordinates by position (w unused)
     float* dist;        // [2N]    Jacobi double buffer
-    int* lab;           // [2N]    label double buffer
+    unsigned long long* dl;   // [2N] (distance, label) double buffer of the labelled run
     unsigned* bits;     // [2 * W] frontier bitmaps, mesh b at 2 * w_off_b
     int* cnt;           // [4 * gmax] per-workgroup chunk counts
     int* retire;        // [N]     last iteration that updated each topleset, mesh b at v_off_b

@@ -98,7 +98,7 @@ struct RelaxArgs {
     const int* fan;
     const float4* xyz;
     float* dist;           // [2N]
-    int* lab;              // [2N]
+    unsigned long long* dl;   // [2N] (distance, label) pairs, with labels
     int* retire;
     int* ctrl;
     unsigned* bar;
@@ -111,6 +111,30 @@ struct RelaxArgs {
 // and open ones of degree <= 5 in one go; longer fans continue in chunks).
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
+
+// The iteration state of a position: its distance (float), or with labels
+// its (distance, label) pair in one 8-byte word, so that a neighbour costs
+// one coherent load and a position one store.
+__device__ inline unsigned long long pack_dl(float d, int l) {
+    return (unsigned long long)__float_as_uint(d) | ((unsigned long long)(unsigned)l << 32);
+}
+
+template <bool LABELS>
+__device__ inline void ld_s(const void* s, int id, float& d, int& l) {
+    if (LABELS) {
+        const unsigned long long x = ld_c(static_cast<const unsigned long long*>(s) + id);
+        d = __uint_as_float((unsigned)x);
+        l = (int)(unsigned)(x >> 32);
+    } else {
+        d = ld_c(static_cast<const float*>(s) + id);
+    }
+}
+
+template <bool LABELS>
+__device__ inline void st_s(void* s, int id, float d, int l, bool local) {
+    if (LABELS) st_g(static_cast<unsigned long long*>(s) + id, pack_dl(d, l), local);
+    else st_g(static_cast<float*>(s) + id, d, local);
+}
 
 // Planar update of x0 from one triangle, folded into the (value, label)
 // lexicographic minimum best / bl, which does not depend on the order in
@@ -147,8 +171,8 @@ __device__ inline void eval_fan_first(const float4 x0, const int* e, const float
 // by one, then the closing pair with entry 0 (d0 / xf / l0) on a closed fan.
 template <bool LABELS, int C>
 __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0, int f0, int L,
-                                     bool closed, float d0, float4 xf, int l0, const float* dold,
-                                     const int* lold, float& best, int& bl) {
+                                     bool closed, float d0, float4 xf, int l0, const void* sold,
+                                     float& best, int& bl) {
     for (int base = C - 1; base < L - 1; base += C - 1) {
         const int cnt = min(C, L - base);
         int e[C], l[C];
@@ -159,9 +183,9 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             const int id = e[q] & kFanId;
-            d[q] = ld_c(dold + id);
+            l[q] = 0;
+            ld_s<LABELS>(sold, id, d[q], l[q]);
             x[q] = a.xyz[id];
-            l[q] = LABELS ? ld_c(lold + id) : 0;
         }
 #pragma unroll
         for (int q = 1; q < C; ++q)
@@ -169,9 +193,10 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
                                 q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
-            const float dl = ld_c(dold + id);
+            float dl;
+            int ll = 0;
+            ld_s<LABELS>(sold, id, dl, ll);
             const float4 xl = a.xyz[id];
-            const int ll = LABELS ? ld_c(lold + id) : 0;
             fold_update<LABELS>(x0, xl, xf, dl, d0, ll, l0, best, bl);
         }
     }
@@ -187,21 +212,22 @@ __device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e
 }
 
 template <bool LABELS, int C>
-__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const float* dold, const int* lold,
-                                  float* d, float4* x, int* l) {
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const void* sold, float* d, float4* x,
+                                  int* l) {
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int id = e[q] & kFanId;
-        d[q] = ld_c(dold + id);
+        int lq = 0;
+        ld_s<LABELS>(sold, id, d[q], lq);
+        if (LABELS) l[q] = lq;
         x[q] = a.xyz[id];
-        if (LABELS) l[q] = ld_c(lold + id);
     }
 }
 
 // Smallest planar update of position v over all its incident triangles.
 template <bool LABELS, int C>
-__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const float* dold,
-                                   const int* lold, float& best, int& bl) {
+__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const void* sold, float& best,
+                                   int& bl) {
     best = kInf;
     bl = 0x7fffffff;
     const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
@@ -209,11 +235,11 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
     float d[C];
     float4 x[C];
     load_fan<LABELS, C>(a, v, f0, L, e);
-    gather_fan<LABELS, C>(a, e, dold, lold, d, x, l);
+    gather_fan<LABELS, C>(a, e, sold, d, x, l);
     eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
     if (L > C)
         eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], LABELS ? l[0] : 0,
-                                 dold, lold, best, bl);
+                                 sold, best, bl);
 }
 
 // Band positions p, p + gsz, ... (< be) of one thread, software-pipelined:
@@ -224,8 +250,8 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
 // positions below tb.
 template <bool LABELS, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
-                                                long long tb, long long gsz, const float* dold,
-                                                float* dnew, const int* lold, int* lnew, bool local) {
+                                                long long tb, long long gsz, const void* sold, void* snew,
+                                                bool local) {
     unsigned notconv = 0;
     if (p >= be) return 0;
     int f0 = a.fanrow[vo + p];
@@ -241,11 +267,13 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
-        const float dv = ld_c(dold + v);
+        float dv;
+        int lv = 0;
+        ld_s<LABELS>(sold, v, dv, lv);
         int l[C];
         float d[C];
         float4 x[C];
-        gather_fan<LABELS, C>(a, e, dold, lold, d, x, l);
+        gather_fan<LABELS, C>(a, e, sold, d, x, l);
         // the next position's fan entries and the fan row of the one after
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
@@ -261,15 +289,10 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
         eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
         if (L > C)
             eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0],
-                                     LABELS ? l[0] : 0, dold, lold, best, bl);
-        float dn = dv;
-        if (best < dv) {
-            dn = best;
-            if (LABELS) st_g(lnew + v, bl, local);
-        } else if (LABELS) {
-            st_g(lnew + v, ld_c(lold + v), local);
-        }
-        st_g(dnew + v, dn, local);
+                                     LABELS ? l[0] : 0, sold, best, bl);
+        const bool better = best < dv;
+        const float dn = better ? best : dv;
+        st_s<LABELS>(snew, v, dn, better ? bl : lv, local);
         if (p < tb) {
             const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
             notconv |= conv ? 0u : 1u;
@@ -313,7 +336,7 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         int l[C];
         float dd[C];
         float4 x[C];
-        gather_fan<false, C>(a, e, d, nullptr, dd, x, l);
+        gather_fan<false, C>(a, e, d, dd, x, l);
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
         int en[C];
@@ -328,8 +351,8 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
             int bl = 0;
             eval_fan_first<false, C>(x0, e, dd, x, l, L, best, bl);
             if (L > C)
-                eval_fan_rest<false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d,
-                                        nullptr, best, bl);
+                eval_fan_rest<false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d, best,
+                                        bl);
             if (wv < best) {
                 st_g(d + v, kInf, local);
                 changed = 1;
@@ -388,8 +411,9 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const bool leader = me.rank == 0 && threadIdx.x == 0;
     float* dA = a.dist;
     float* dB = a.dist + a.N;
-    int* lA = a.lab;
-    int* lB = a.lab + a.N;
+    // the iteration state: distances, or (distance, label) pairs with labels
+    void* sA = LABELS ? static_cast<void*>(a.dl) : static_cast<void*>(dA);
+    void* sB = LABELS ? static_cast<void*>(a.dl + a.N) : static_cast<void*>(dB);
 
     // A group whose workgroups all run on one XCD exchanges its data through
     // that XCD's L2 with plain stores.  Every workgroup posts its XCD, the
@@ -429,18 +453,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 const float w = a.upper[md.out_off + (v - vo)];
                 d = w >= 0.f ? w : kInf;                 // NaN or negative: no bound
             }
-            st_g(dA + vo + p, d, local);
-            st_g(dB + vo + p, d, local);
-            if (LABELS && p >= m0) {
-                st_g(lA + vo + p, -1, local);
-                st_g(lB + vo + p, -1, local);
+            if (!LABELS || p >= m0) {           // with labels the sources come next
+                st_s<LABELS>(sA, vo + (int)p, d, -1, local);
+                st_s<LABELS>(sB, vo + (int)p, d, -1, local);
             }
         }
         if (LABELS)
             for (long long s = g0; s < md.m; s += gsz) {
                 const int p = a.iperm[vo + a.S[md.s_in + s]];
-                st_g(lA + p, (int)s, local);
-                st_g(lB + p, (int)s, local);
+                st_s<LABELS>(sA, p, 0.f, (int)s, local);
+                st_s<LABELS>(sB, p, 0.f, (int)s, local);
             }
         for (long long r = g0; r < rho; r += gsz) st_g(retire + r, r == 0 ? 0 : -1, local);
         if (!gb.sync(0, &any)) return;
@@ -494,10 +516,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const int j = min(k, rho - 1);                       // Eq. upper_band
             int lo = i;
             if (a.window > 0) lo = max(lo, j - a.window + 1);
-            const float* dold = (k & 1) ? dA : dB;
-            float* dnew = (k & 1) ? dB : dA;
-            const int* lold = (k & 1) ? lA : lB;
-            int* lnew = (k & 1) ? lB : lA;
+            const void* sold = (k & 1) ? sA : sB;
+            void* snew = (k & 1) ? sB : sA;
             const int cb = offs_lds ? s_offs[lo_prev] : offs[lo_prev];   // retired since last iteration: copy
             const int bb = offs_lds ? s_offs[lo] : offs[lo];             // band
             const int be = offs_lds ? s_offs[j + 1] : offs[j + 1];
@@ -509,19 +529,22 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
                 for (long long pp = first; pp < bb; pp += gsz) {
-                    st_g(dnew + vo + (int)pp, ld_c(dold + vo + (int)pp), local);
-                    if (LABELS) st_g(lnew + vo + (int)pp, ld_c(lold + vo + (int)pp), local);
+                    float dc;
+                    int lc = 0;
+                    ld_s<LABELS>(sold, vo + (int)pp, dc, lc);
+                    st_s<LABELS>(snew, vo + (int)pp, dc, lc, local);
                 }
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, dold, dnew,
-                                                                lold, lnew, local);
+                notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    st_g(dnew + v, ld_c(dold + v), local);
-                    if (LABELS) st_g(lnew + v, ld_c(lold + v), local);
+                    float dc;
+                    int lc = 0;
+                    ld_s<LABELS>(sold, v, dc, lc);
+                    st_s<LABELS>(snew, v, dc, lc, local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -532,27 +555,24 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
                 }
-                const float dv = ld_c(dold + v);
+                float dv;
+                int lv = 0;
+                ld_s<LABELS>(sold, v, dv, lv);
                 float best = kInf;
                 int bl = 0x7fffffff;
                 if (cached && cv == v) {
                     int l[kCache];
                     float d[kCache];
                     float4 x[kCache];
-                    gather_fan<LABELS, kCache>(a, ce, dold, lold, d, x, l);
+                    gather_fan<LABELS, kCache>(a, ce, sold, d, x, l);
                     eval_fan_first<LABELS, kCache>(cx0, ce, d, x, l, cL, best, bl);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
-                    best_update<LABELS, kChunk>(a, v, x0, dold, lold, best, bl);
+                    best_update<LABELS, kChunk>(a, v, x0, sold, best, bl);
                 }
-                float dn = dv;
-                if (best < dv) {
-                    dn = best;
-                    if (LABELS) st_g(lnew + v, bl, local);
-                } else if (LABELS) {
-                    st_g(lnew + v, ld_c(lold + v), local);
-                }
-                st_g(dnew + v, dn, local);
+                const bool better = best < dv;
+                const float dn = better ? best : dv;
+                st_s<LABELS>(snew, v, dn, better ? bl : lv, local);
                 if (pp < tb) {
                     const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
                     notconv |= conv ? 0u : 1u;
@@ -573,12 +593,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             }
             lo_prev = lo;
         }
-        const float* dfin = (k & 1) ? dB : dA;
-        const int* lfin = (k & 1) ? lB : lA;
+        const void* sfin = (k & 1) ? sB : sA;
         for (long long p = g0; p < n; p += gsz) {
             const int v = a.perm[vo + p];
-            a.out_d[md.out_off + (v - vo)] = ld_c(dfin + vo + p);
-            if (LABELS) a.out_l[md.out_off + (v - vo)] = ld_c(lfin + vo + p);
+            float df;
+            int lf = 0;
+            ld_s<LABELS>(sfin, vo + (int)p, df, lf);
+            a.out_d[md.out_off + (v - vo)] = df;
+            if (LABELS) a.out_l[md.out_off + (v - vo)] = lf;
         }
         if (leader) {
             a.state[b].iters = k;
@@ -624,7 +646,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.fan = w.fan;
     a.xyz = w.xyz;
     a.dist = w.dist;
-    a.lab = w.lab;
+    a.dl = w.dl;
     a.retire = w.retire;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
