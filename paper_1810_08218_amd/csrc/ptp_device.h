@@ -194,6 +194,21 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
 }
 
 // ---- block-wide scans --------------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from outside the
+// row add 0), then the last lane of row 0 / 2 added to rows 1 / 3 and the
+// last lane of row 1 to rows 2 and 3.  (A shuffle through the LDS crossbar
+// per step costs several times more.)
+__device__ inline int wave_inclusive_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
 // Exclusive prefix of `v` over a workgroup of NT threads; *total receives
 // the sum.  LDS_ONLY: its barriers order LDS only (see lds_barrier).
 template <int NT, typename T, bool LDS_ONLY = false>
@@ -201,12 +216,7 @@ __device__ inline T block_exclusive_scan_n(T v, T* total) {
     __shared__ T warp_sums[NT / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    T x = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        T y = __shfl_up(x, off, kWave);
-        if (lane >= off) x += y;
-    }
+    T x = wave_inclusive_sum(v);
     if (lane == kWave - 1) warp_sums[wid] = x;
     if (LDS_ONLY) lds_barrier();
     else __syncthreads();
