@@ -659,7 +659,8 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
         fn = cache ? reinterpret_cast<const void*>(&k_relax<true, false, true>)
                    : reinterpret_cast<const void*>(&k_relax<true, false, false>);
     else if (p.upper)
-        fn = reinterpret_cast<const void*>(&k_relax<false, true, false>);
+        fn = cache ? reinterpret_cast<const void*>(&k_relax<false, true, true>)
+                   : reinterpret_cast<const void*>(&k_relax<false, true, false>);
     else
         fn = cache ? reinterpret_cast<const void*>(&k_relax<false, false, true>)
                    : reinterpret_cast<const void*>(&k_relax<false, false, false>);
@@ -668,7 +669,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
 
 // Co-resident workgroups of the relaxation kernels a plan may launch: the
 // labelled one, or (without labels) the plain and the warm-start one; with
-// `cache`, the register-caching variants instead of the plain ones.
+// `cache`, the register-caching variants instead of the uncached ones.
 int max_coop_blocks_run(int cus, bool labels, bool cache) {
     int nb = 0, nw = 1 << 20;
     hipError_t e;
@@ -679,7 +680,8 @@ int max_coop_blocks_run(int cus, bool labels, bool cache) {
         e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, true>, kBlock, 0)
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, false>, kBlock, 0);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, false>, kBlock, 0);
+            e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, true>, kBlock, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, false>, kBlock, 0);
     }
     nb = std::min(nb, nw);
     if (e != hipSuccess || nb < 1) nb = 1;
