@@ -20,23 +20,31 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ptp_oracle.c")
 _LIB = os.path.join(_HERE, "libptp_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libptp_oracle_omp.so")
 
 OK, EINVAL, ENOMEM, ENOCONV = 0, -1, -2, -4
 
 
+def _compile(out: str, extra: list, force: bool) -> str:
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                               *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
 def build_oracle(force: bool = False) -> str:
-    """Compile ptp_oracle.c into libptp_oracle.so next to it (gcc -O3)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile ptp_oracle.c into libptp_oracle.so next to it (gcc -O3,
+    sequential) and libptp_oracle_omp.so (the same source with its one
+    OpenMP loop, the Jacobi update of a band, on all host cores)."""
+    _compile(_LIB_OMP, ["-fopenmp"], force)
+    return _compile(_LIB, ["-Wno-unknown-pragmas"], force)
 
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("band_rule", C.c_int),
-                ("window", C.c_int), ("advance_all", C.c_int)]
+                ("window", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -45,6 +53,16 @@ class _Stats(C.Structure):
 
 
 _lib = None
+_lib_omp = None
+
+
+def load_omp() -> C.CDLL:
+    """The OpenMP build (same results, band updates on every host core)."""
+    global _lib_omp
+    if _lib_omp is None:
+        build_oracle()
+        _lib_omp = load_library(_LIB_OMP)
+    return _lib_omp
 
 
 def load_library(path: str) -> C.CDLL:
@@ -91,8 +109,11 @@ def _declare(lib):
     lib.ptpo_local_update.restype = C.c_double
     lib.ptpo_run.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
                              dptr, iptr, C.POINTER(_Stats), iptr, iptr, dptr, C.c_int]
+    lib.ptpo_run_replay.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
+                                    iptr, C.c_int, dptr, iptr, C.POINTER(_Stats), iptr]
     lib.ptpo_run_warm.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.POINTER(_Opts),
-                                  dptr, dptr, C.POINTER(_Stats), iptr, C.POINTER(C.c_int), dptr]
+                                  dptr, C.c_int, dptr, iptr, C.POINTER(_Stats), iptr,
+                                  C.POINTER(C.c_int), dptr]
     lib.ptpo_fixed_point.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.c_int,
                                      dptr, iptr, C.POINTER(C.c_int)]
     lib.ptpo_fast_marching.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, dptr]
@@ -145,10 +166,11 @@ class Result:
     trace_maxrel: np.ndarray
 
 
-def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, advance_all=False,
-        trace_len=None, lib=None) -> Result:
-    """PTP with the paper's band rule (band_rule=0) or the fixed half band
-    (band_rule=1).  Returns distances and labels in the caller's order."""
+def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, trace_len=None, lib=None) -> Result:
+    """PTP with the paper's band rule (band_rule=0: Eq. upper_band and Eq.
+    lower_band, optionally capped at `window` toplesets) or the fixed half band
+    [floor((k+1)/2), k] of the complexity analysis (band_rule=1).  Returns
+    distances and labels in the caller's order."""
     X, F, S = _prep(V, F, S)
     n = X.shape[0]
     dist = np.empty(n, np.float64)
@@ -160,7 +182,7 @@ def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, advance_all=False,
     tlo = np.full(trace_len, -1, np.int32)
     tmr = np.full(trace_len, np.nan, np.float64)
     st = _Stats()
-    opts = _Opts(float(tol), int(max_iters), int(band_rule), int(window), int(bool(advance_all)))
+    opts = _Opts(float(tol), int(max_iters), int(band_rule), int(window))
     rc = _L(lib).ptpo_run(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), dist, label,
                        C.byref(st), retire, tlo, tmr, trace_len)
     if rc not in (OK, ENOCONV):
@@ -170,9 +192,33 @@ def run(V, F, S, tol, max_iters=0, band_rule=0, window=0, advance_all=False,
                   retire[: st.rho].copy(), tlo[: K + 1].copy(), tmr[: K + 1].copy())
 
 
+def replay(V, F, S, tol, retire, K, lib=None) -> Result:
+    """The PTP iteration under a given schedule: retire[rho] = the last
+    iteration that updated each topleset (-1: never retired), K = the number
+    of iterations.  Used to compare arithmetic under another run's band."""
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    dist = np.empty(n, np.float64)
+    label = np.empty(n, np.int32)
+    ret_out = np.empty(n, np.int32)
+    rin = np.full(n, -1, np.int32)
+    r = np.asarray(retire, np.int32)
+    rin[: r.shape[0]] = r
+    st = _Stats()
+    opts = _Opts(float(tol), 0, 0, 0)
+    rc = _L(lib).ptpo_run_replay(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), rin, int(K),
+                                 dist, label, C.byref(st), ret_out)
+    if rc not in (OK, ENOCONV):
+        raise ValueError(f"ptpo_run_replay failed: {rc}")
+    e = np.empty(0)
+    return Result(dist, label, rc, st.iterations, st.rho, st.reachable, int(st.updates),
+                  ret_out[: st.rho].copy(), e, e)
+
+
 @dataclass
 class WarmResult:
     dist: np.ndarray
+    label: np.ndarray
     status: int
     iterations: int
     rho: int
@@ -183,25 +229,28 @@ class WarmResult:
     certified: np.ndarray
 
 
-def run_warm(V, F, S, tol, upper, max_iters=0, window=0, lib=None) -> WarmResult:
-    """PTP started from the upper bound `upper[n]` (caller order) after
-    certifying it; `rejected` counts the bounds the certification withdrew."""
+def run_warm(V, F, S, tol, upper, max_iters=0, window=0, certify=True, lib=None) -> WarmResult:
+    """PTP started from the upper bound `upper[n]` (caller order): certified
+    first (`rejected` counts the bounds withdrawn), or with certify=False taken
+    as a known supersolution (a distance map of a subset of S)."""
     X, F, S = _prep(V, F, S)
     n = X.shape[0]
     w = np.ascontiguousarray(upper, dtype=np.float64)
     if w.shape != (n,):
         raise ValueError("upper must have n entries")
     dist = np.empty(n, np.float64)
+    label = np.empty(n, np.int32)
     cert = np.empty(n, np.float64)
     retire = np.empty(n, np.int32)
     st = _Stats()
     rej = C.c_int(0)
-    opts = _Opts(float(tol), int(max_iters), 0, int(window), 0)
-    rc = _L(lib).ptpo_run_warm(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), w, dist,
-                               C.byref(st), retire, C.byref(rej), cert)
+    opts = _Opts(float(tol), int(max_iters), 0, int(window))
+    rc = _L(lib).ptpo_run_warm(n, F.shape[0], X, F, S.shape[0], S, C.byref(opts), w,
+                               int(bool(certify)), dist, label, C.byref(st), retire,
+                               C.byref(rej), cert)
     if rc not in (OK, ENOCONV):
         raise ValueError(f"ptpo_run_warm failed: {rc}")
-    return WarmResult(dist, rc, st.iterations, st.rho, st.reachable, int(st.updates),
+    return WarmResult(dist, label, rc, st.iterations, st.rho, st.reachable, int(st.updates),
                       retire[: st.rho].copy(), rej.value, cert)
 
 

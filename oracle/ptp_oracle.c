@@ -19,9 +19,13 @@
  *                       B_{i_k}^{j_k} (Sec. 4.2), band ends from Eq. upper_band
  *                       and Eq. lower_band; optionally the fixed half band of
  *                       the complexity analysis (Sec. 6).
+ *   ptpo_run_replay     the same iteration under a given retirement schedule
+ *                       (the arithmetic compared under another run's band).
  *   ptpo_run_warm       the same iteration started from a caller's upper
- *                       bound instead of +inf, after certifying it (an
- *                       extension of the method, not in the paper).
+ *                       bound instead of +inf, certified first or taken as a
+ *                       known supersolution (an extension of the method, not
+ *                       in the paper; farthest point sampling restarts from
+ *                       the previous map this way).
  *   ptpo_fixed_point    plain Jacobi over all vertices until nothing changes:
  *                       the fixed point d* that PTP approximates.
  *   ptpo_fast_marching  sequential Fast Marching (Sec. 3.2) with the same
@@ -295,10 +299,11 @@ typedef struct {
     double tol;       /* epsilon of Eq. lower_band, > 0                     */
     int max_iters;    /* iteration cap K_max; 0 -> 4 rho + 16               */
     int band_rule;    /* 0: relative change (Eq. lower_band)                */
-                      /* 1: fixed band i_k = floor((k + 1) / 2) (Sec. 6)   */
+                      /* 1: fixed half band [floor((k+1)/2), k] of the      */
+                      /*    complexity analysis (Sec. 6), stop after        */
+                      /*    2 rho - 3 iterations                            */
     int window;       /* > 0: band holds at most `window` toplesets; the    */
                       /* ones pushed out below it retire.  0: unbounded     */
-    int advance_all;  /* 1: retire every leading converged topleset         */
 } ptpo_options;
 
 typedef struct {
@@ -308,10 +313,20 @@ typedef struct {
     long long updates;    /* U = sum_k |B_k| (vertex updates)              */
 } ptpo_stats;
 
+/* How the lower end of the band is chosen.  Exactly one mode per run. */
+typedef struct {
+    const double *upper;      /* warm start (caller order), or NULL: start from +inf */
+    int certify;              /* warm start: certify the bound first (1) or take it  */
+                              /* as a known supersolution (0)                       */
+    const int *replay;        /* replay: retire[r] of a given run (the last          */
+                              /* iteration that updated V_r, -1 never) and the      */
+    int replay_K;             /* iteration count K of that run; or NULL             */
+} run_mode;
+
 /*
  * dist[n], label[n] (may be NULL): results in the caller's vertex order.
- * retire_k[n] (may be NULL): iteration at which V_r retired (V_0: 0; not
- *   retired: -1).
+ * retire_k[n] (may be NULL): the last iteration that updated V_r (V_0: 0;
+ *   never retired: -1).
  * trace_lo[max_iters + 1], trace_maxrel[max_iters + 1] (may be NULL): for
  *   each k, the first topleset of the band and the largest relative change
  *   over V_{i_{k-1}} (inf when some value was still infinite).
@@ -319,13 +334,17 @@ typedef struct {
  * error.
  */
 static int run_core(int n, int nf, const double *X, const int *F, int m, const int *S,
-                    const ptpo_options *opt, const double *upper, double *dist, int *label,
+                    const ptpo_options *opt, const run_mode *mode, double *dist, int *label,
                     ptpo_stats *st, int *retire_k, int *trace_lo, double *trace_maxrel,
                     int trace_len, int *rejected_out, double *certified_out)
 {
     int rc = check_mesh(n, nf, F, m, S);
     if (rc) return rc;
-    if (!(opt->tol > 0.0) || opt->window < 0 || opt->max_iters < 0) return PTPO_EINVAL;
+    if (!(opt->tol > 0.0) || opt->window < 0 || opt->max_iters < 0 || opt->band_rule < 0 ||
+        opt->band_rule > 1)
+        return PTPO_EINVAL;
+    const double *upper = mode ? mode->upper : NULL;
+    const int *replay = mode ? mode->replay : NULL;
     incidence inc;
     rc = build_incidence(n, nf, F, &inc);
     if (rc) return rc;
@@ -357,12 +376,13 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
          * caller's bound (negative or NaN: no bound).  Certification: a vertex
          * whose bound is below the best planar update from its neighbours'
          * bounds, w(v) < U(w)(v), loses it (+inf); repeated until nothing
-         * changes.  Withdrawing a bound can only raise U elsewhere, so the set
-         * withdrawn does not depend on the sweep order.  What remains obeys
-         * w >= U(w) with w = 0 on S. */
+         * changes.  What remains obeys w >= U(w) with w = 0 on S.  Without
+         * certification the caller vouches for that property (a distance map
+         * of a subset of S computed by this iteration has it: each value was
+         * set to U of an earlier, pointwise larger map). */
         for (int v = 0; v < n; ++v)
             if (level[v] > 0) dold[v] = upper[v] >= 0.0 ? upper[v] : INFINITY;
-        int rejected = 0, changed = 1;
+        int rejected = 0, changed = mode->certify;
         while (changed) {
             changed = 0;
             for (int q = 0; q < n; ++q) {
@@ -386,6 +406,16 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
         retire_k[0] = 0;
     }
     int kmax = opt->max_iters > 0 ? opt->max_iters : 4 * rho + 16;
+    /* the fixed band finalises V_r by iteration 2r - 1 (Sec. 6 lemma for
+     * regular meshes), so the last topleset is done after 2 rho - 3 */
+    const int kfix = 2 * rho - 3 > 1 ? 2 * rho - 3 : 1;
+    if (replay) {
+        kmax = mode->replay_K;
+        if (kmax < 0 || replay[0] != 0) {
+            rc = PTPO_EINVAL;
+            goto out;
+        }
+    }
     int i = 1, k = 0;
     long long U = 0;
     memcpy(dnew, dold, sizeof(double) * (size_t)n);
@@ -394,57 +424,72 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
         k += 1;
         int j = k < rho ? k : rho - 1;                   /* Eq. upper_band */
         int lo;
-        if (opt->band_rule == 1) {
+        if (replay) {
+            /* the band holds every topleset the given run had not retired
+             * before iteration k */
+            lo = i;
+            while (lo < rho && replay[lo] >= 0 && replay[lo] < k) lo++;
+            if (lo > j) {
+                rc = PTPO_EINVAL;
+                goto out;
+            }
+        } else if (opt->band_rule == 1) {
             lo = (k + 1) / 2;                            /* fixed half band */
             if (lo < 1) lo = 1;
-            if (lo > j) lo = j;
         } else {
             lo = i;
-            if (opt->window > 0 && j - opt->window + 1 > lo) {
-                lo = j - opt->window + 1;
-                /* toplesets pushed below the window are no longer updated */
-                if (retire_k)
-                    for (int r = i; r < lo; ++r) retire_k[r] = k - 1;
-            }
         }
+        if (opt->window > 0 && !replay && j - opt->window + 1 > lo) {
+            lo = j - opt->window + 1;
+            /* toplesets pushed below the window are no longer updated */
+        }
+        if (retire_k)
+            for (int r = i; r < lo; ++r) retire_k[r] = k - 1;
         /* Jacobi update of the band: d_k on B from d_{k-1}; d_k = d_{k-1}
-         * everywhere else */
-        for (int r = lo; r <= j; ++r) {
-            for (int q = offsets[r]; q < offsets[r + 1]; ++q) {
-                int v = order[q];
-                double bu;
-                int bl;
-                best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
-                if (bu < dold[v]) {
-                    dnew[v] = bu;
-                    lnew[v] = bl;
-                } else {
-                    dnew[v] = dold[v];
-                    lnew[v] = lold[v];
-                }
+         * everywhere else.  The vertices are independent (each reads the
+         * previous map only), so the loop may run on several threads. */
+        const int qb = offsets[lo], qe = offsets[j + 1];
+#pragma omp parallel for schedule(static)
+        for (int q = qb; q < qe; ++q) {
+            int v = order[q];
+            double bu;
+            int bl;
+            best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+            if (bu < dold[v]) {
+                dnew[v] = bu;
+                lnew[v] = bl;
+            } else {
+                dnew[v] = dold[v];
+                lnew[v] = lold[v];
             }
-            U += offsets[r + 1] - offsets[r];
         }
+        U += qe - qb;
         if (trace_lo && k < trace_len) trace_lo[k] = lo;
         int inew;
-        if (opt->band_rule == 1) {
-            /* V_r is final after iteration 2r - 1 */
-            inew = (k + 1) / 2 + 1;
-            if (inew < i) inew = i;
+        if (replay) {
+            inew = lo;
+            while (inew < rho && replay[inew] >= 0 && replay[inew] <= k) inew++;
             if (retire_k)
-                for (int r = i; r < inew && r < rho; ++r) retire_k[r] = k;
+                for (int r = lo; r < inew; ++r) retire_k[r] = k;
+        } else if (opt->band_rule == 1) {
+            /* the toplesets below the next iteration's band are final; after
+             * the last iteration every topleset is */
+            inew = k >= kfix ? rho : (k + 2) / 2;
+            if (inew < lo) inew = lo;
+            if (retire_k)
+                for (int r = lo; r < inew && r < rho; ++r) retire_k[r] = k;
         } else {
             /* Eq. lower_band: V_lo retires when every value in it was finite
              * and changed by a relative amount below tol, and not before its
              * second update (k > lo).  From +inf a value is first finite after
              * the iteration that reached its topleset, so the second condition
-             * only binds for a warm start. */
+             * only binds for a warm start.  At most one topleset per
+             * iteration. */
             inew = lo;
-            for (;;) {
-                if (inew >= rho || inew > j || k <= inew) break;
+            if (lo < rho && lo <= j && k > lo) {
                 double worst = 0.0;
                 int ok = 1;
-                for (int q = offsets[inew]; q < offsets[inew + 1]; ++q) {
+                for (int q = offsets[lo]; q < offsets[lo + 1]; ++q) {
                     int v = order[q];
                     if (!isfinite(dold[v])) {
                         ok = 0;
@@ -456,21 +501,22 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
                     if (rel > worst) worst = rel;
                     if (!(rel < opt->tol)) ok = 0;
                 }
-                if (inew == lo && trace_maxrel && k < trace_len) trace_maxrel[k] = worst;
-                if (!ok) break;
-                if (retire_k) retire_k[inew] = k;
-                inew += 1;
-                if (!opt->advance_all) break;
+                if (trace_maxrel && k < trace_len) trace_maxrel[k] = worst;
+                if (ok) {
+                    if (retire_k) retire_k[lo] = k;
+                    inew = lo + 1;
+                }
+            } else if (trace_maxrel && k < trace_len) {
+                trace_maxrel[k] = INFINITY;
             }
         }
         i = inew;
         /* d_{k-1} <- d_k */
-        for (int r = lo; r <= j; ++r)
-            for (int q = offsets[r]; q < offsets[r + 1]; ++q) {
-                int v = order[q];
-                dold[v] = dnew[v];
-                lold[v] = lnew[v];
-            }
+        for (int q = qb; q < qe; ++q) {
+            int v = order[q];
+            dold[v] = dnew[v];
+            lold[v] = lnew[v];
+        }
     }
     if (i < rho) rc = PTPO_ENOCONV;
     int reach = 0;
@@ -500,15 +546,31 @@ int ptpo_run(int n, int nf, const double *X, const int *F, int m, const int *S,
                     trace_maxrel, trace_len, NULL, NULL);
 }
 
-/* upper[n]: the warm start in the caller's vertex order.  rejected_out (may
- * be NULL): number of bounds the certification withdrew; certified[n] (may be
- * NULL): the certified start, caller order. */
+/* Replay: the same iteration, but the band's lower end follows a given
+ * schedule (retire_in[rho], K) instead of the relative-change test, so that
+ * the arithmetic can be compared under another run's schedule.  Returns
+ * PTPO_EINVAL when the schedule is not one the iteration could produce. */
+int ptpo_run_replay(int n, int nf, const double *X, const int *F, int m, const int *S,
+                    const ptpo_options *opt, const int *retire_in, int K, double *dist,
+                    int *label, ptpo_stats *st, int *retire_k)
+{
+    if (!retire_in) return PTPO_EINVAL;
+    run_mode md = {NULL, 0, retire_in, K};
+    return run_core(n, nf, X, F, m, S, opt, &md, dist, label, st, retire_k, NULL, NULL, 0,
+                    NULL, NULL);
+}
+
+/* upper[n]: the warm start in the caller's vertex order.  certify: 1 to
+ * certify it first, 0 to take it as a supersolution.  rejected_out (may be
+ * NULL): number of bounds the certification withdrew; certified[n] (may be
+ * NULL): the start after certification, caller order. */
 int ptpo_run_warm(int n, int nf, const double *X, const int *F, int m, const int *S,
-                  const ptpo_options *opt, const double *upper, double *dist, ptpo_stats *st,
-                  int *retire_k, int *rejected_out, double *certified)
+                  const ptpo_options *opt, const double *upper, int certify, double *dist,
+                  int *label, ptpo_stats *st, int *retire_k, int *rejected_out, double *certified)
 {
     if (!upper) return PTPO_EINVAL;
-    return run_core(n, nf, X, F, m, S, opt, upper, dist, NULL, st, retire_k, NULL, NULL, 0,
+    run_mode md = {upper, certify ? 1 : 0, NULL, 0};
+    return run_core(n, nf, X, F, m, S, opt, &md, dist, label, st, retire_k, NULL, NULL, 0,
                     rejected_out, certified);
 }
 

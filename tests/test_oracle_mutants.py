@@ -26,6 +26,17 @@ MUTANTS = {
     "label tie to larger index": ("else *lab_out = l1 < l2 ? l1 : l2;\n        return p;",
                                   "else *lab_out = l1 > l2 ? l1 : l2;\n        return p;"),
     "retire without the relative test": ("if (!(rel < opt->tol)) ok = 0;", "(void)0;"),
+    "window lower end one below": ("j - opt->window + 1 > lo) {\n            lo = j - opt->window + 1;",
+                                   "j - opt->window > lo) {\n            lo = j - opt->window;"),
+    "window push-out recorded one late": ("for (int r = i; r < lo; ++r) retire_k[r] = k - 1;",
+                                          "for (int r = i; r < lo; ++r) retire_k[r] = k;"),
+    "fixed band lower end floor(k/2)": ("lo = (k + 1) / 2;                            /* fixed half band */",
+                                        "lo = k / 2;"),
+    "fixed band runs 2 rho - 1 iterations": ("const int kfix = 2 * rho - 3 > 1 ? 2 * rho - 3 : 1;",
+                                             "const int kfix = 2 * rho - 1 > 1 ? 2 * rho - 1 : 1;"),
+    "replay drops a topleset in its retiring iteration": (
+        "while (lo < rho && replay[lo] >= 0 && replay[lo] < k) lo++;",
+        "while (lo < rho && replay[lo] >= 0 && replay[lo] <= k) lo++;"),
 }
 
 
@@ -99,7 +110,30 @@ def _battery(lib) -> list:
         close = np.abs(r.dist - fp).max() <= 1e-5 * fp.max()
         return (fp <= dj * (1 + 1e-12)).all() and (r.dist >= fp * (1 - 1e-12)).all() and close
 
+    def ladder():
+        g = golden("ladder_window_and_fixed_band.json")
+        V, F, S = (np.array(g[k], t) for k, t in (("V", np.float32), ("F", np.int32), ("S", np.int32)))
+        for c in g["runs"].values():
+            r = O.run(V, F, S, g["tol"], window=c["window"], band_rule=c["band_rule"], lib=lib)
+            if (r.iterations, r.updates) != (c["K"], c["U"]) or r.retire_k.tolist() != c["retire"]:
+                return False
+            if r.trace_lo[1:].tolist() != c["lo"]:
+                return False
+        return True
+
+    mb = I.bumpy_icosphere(level=4, seed=3, n_sources=6)
+
+    def replay():
+        for kw in ({}, {"window": 3}, {"band_rule": 1}):
+            r = O.run(mb.V, mb.F, mb.S, 1e-4, lib=lib, **kw)
+            p = O.replay(mb.V, mb.F, mb.S, 1e-4, r.retire_k, r.iterations, lib=lib)
+            if not (np.array_equal(p.dist, r.dist) and p.updates == r.updates):
+                return False
+        return True
+
     check("closed forms", closed_forms)
+    check("ladder schedules", ladder)
+    check("replay", replay)
     check("plane wave", plane_wave)
     check("golden squares", squares)
     check("grid rays", grid_rays)
