@@ -53,9 +53,23 @@ typedef enum {
     PTP_EUNSUPPORTED = -5   /* sizes beyond what the library handles          */
 } ptp_status;
 
+/* Band rules (ptp_options.band_rule). */
+#define PTP_BAND_PAPER 0      /* Eq. upper_band / Eq. lower_band: the band grows by one
+                                 topleset per iteration and drops its first one when
+                                 every value there changed by less than tol (Sec. 4.2) */
+#define PTP_BAND_FIXED_HALF 1 /* the fixed band [max(1, floor((k+1)/2)), min(k, rho-1)]
+                                 of the complexity analysis (Sec. 6), run for
+                                 2 rho - 3 iterations (V_r is final after 2r - 1
+                                 iterations on a regular mesh whose toplesets grow);
+                                 tol is not used */
+#define PTP_BAND_JACOBI 2     /* every topleset from 1 on, until an iteration changes
+                                 no value: the fixed point d = min(d, U(d)) the
+                                 iteration approximates; tol is not used */
+
 typedef struct {
     float tol;              /* epsilon of Eq. lower_band, > 0                   */
-    int32_t max_iters;      /* iteration cap; 0 -> 4 * rho + 16                 */
+    int32_t max_iters;      /* iteration cap; 0 -> 4 * rho + 16 (PTP_BAND_JACOBI:
+                               64 * rho + 256)                                  */
     int32_t window;         /* > 0: the band holds at most `window` toplesets
                                and the ones pushed below it stop updating;
                                0: unbounded, the paper's rule                  */
@@ -65,6 +79,7 @@ typedef struct {
                                BFS in one workgroup with LDS bitmaps: 0 -> as
                                large as the device's LDS allows, -1 -> never
                                (tuning only: the toplesets are the same)     */
+    int32_t band_rule;      /* PTP_BAND_*; 0 is the paper's rule              */
 } ptp_options;
 
 typedef struct {
@@ -76,6 +91,13 @@ typedef struct {
                                n_operations without the constant)             */
     int32_t certify_rounds; /* warm start: certification sweeps (0 otherwise)  */
     int32_t certify_rejected; /* warm start: bounds the certification withdrew */
+    float ms_prepare;       /* device time of the last prepare (events on its
+                               stream), -1 when it was not timed               */
+    float ms_run;           /* device time of the last run, -1 when not timed
+                               (a run enqueued under graph capture)            */
+    float ms_mesh_begin;    /* this mesh's iteration began / ended, ms after
+                               the first mesh of the launch began (device     */
+    float ms_mesh_end;      /* clock); -1 when it did not run                   */
 } ptp_stats;
 
 typedef struct ptp_plan ptp_plan;
@@ -118,6 +140,56 @@ ptp_status ptp_solve(ptp_plan *plan, const float *dV, const int32_t *dF, const i
 /* Synchronise the plan's last stream and report the last run: fills *stats
  * and returns its outcome. */
 ptp_status ptp_get_stats(ptp_plan *plan, ptp_stats *stats);
+
+/* The same iteration in float64 (the paper runs single and double precision,
+ * Sec. 5.1): coordinates are the float32 input promoted exactly, distances and
+ * the update in double (correctly rounded square root and division).
+ * dDist: double [n], caller order.  Distances only: PTP_EUNSUPPORTED when the
+ * plan wants labels.  Enqueues work only, like ptp_run; ptp_get_stats
+ * reports it. */
+ptp_status ptp_run_f64(ptp_plan *plan, double *dDist, void *stream);
+
+/* Farthest point sampling (Sec. 5.3; cost analysis in the appendix on the
+ * sampling's complexity): starting from the sources S[0, n_initial), add
+ * n_sources - n_initial vertices one at a time, each the reachable vertex
+ * farthest from the current set by the distance map of that set (largest
+ * float32 distance, smallest vertex id on a tie).
+ *   plan      single-mesh plan created with n_sources = the final count m and
+ *             want_labels = 0 (PTP_EUNSUPPORTED otherwise)
+ *   dS        int32 [m] device: S[0, n_initial) in, S[n_initial, m) out
+ *   warm      0: every map from +inf (the paper's use); 1: every map after the
+ *             first starts from the previous one, which bounds the enlarged
+ *             set's map from above (no certification is needed: each of its
+ *             values was set to the planar update of an earlier, larger map,
+ *             and an added source only lowers updates)
+ *   dDist     float [n] device: the map of the final set S[0, m)
+ *   dRadius   float [m - n_initial] device or NULL: distance of each sample
+ *             when it was chosen
+ *   dSteps    int64 [2 (m - n_initial + 1)] device or NULL: (K, U) of every map
+ * Prepares the plan (validates the mesh and S[0, n_initial)) and enqueues the
+ * whole loop without host round trips, then synchronises.  PTP_EINVAL when
+ * fewer than m vertices are reachable.  Afterwards the plan is prepared for
+ * S[0, m) and ptp_get_stats reports the last map. */
+ptp_status ptp_fps(ptp_plan *plan, const float *dV, const int32_t *dF, int32_t *dS, int32_t n_initial,
+                   void *dWork, size_t work_bytes, int32_t warm, float *dDist, float *dRadius,
+                   int64_t *dSteps, void *stream);
+
+/* One Lloyd step towards a centroidal Voronoi tessellation on the geodesic
+ * Voronoi cells of a labelled run (the paper proposes its method for
+ * centroidal Voronoi tessellations, Sec. 7; cells from multi-source labels,
+ * Sec. 5.3).  Cell s holds the vertices labelled s; vertex v weighs A_v, a
+ * third of the area of its incident triangles; the centroid of s is
+ * sum A_v x_v / sum A_v; the new generator is the vertex of the cell nearest
+ * (Euclidean) to it, smallest id on a tie; an empty cell keeps its generator.
+ * Sums and distances in float64, reduced in a fixed order (deterministic).
+ *   plan      single-mesh plan; the step reads the V, F and S given to its
+ *             last ptp_prepare (validated there; the caller keeps them alive)
+ *   dLabel    int32 [n] labels, caller order (from ptp_run of this plan)
+ *   dSout     int32 [m] the new generators (may not be the prepared S)
+ *   dCentroid double [m][4] device or NULL: (x, y, z, cell area)
+ * Enqueues work only. */
+ptp_status ptp_lloyd_step(ptp_plan *plan, const int32_t *dLabel, int32_t *dSout, double *dCentroid,
+                          void *stream);
 
 /* Copy the topleset order of the last prepare into caller DEVICE buffers:
  * perm[n] = caller vertex id at each position of the order (by topleset, then
@@ -201,6 +273,9 @@ ptp_status ptp_batch_prepare(ptp_batch *batch, const float *dV, const int32_t *d
  * by out_off + local vertex id.  Enqueues work only (capture-safe: kernel
  * launches only). */
 ptp_status ptp_batch_run(ptp_batch *batch, float *dDist, int32_t *dLabel, void *stream);
+
+/* ptp_run_f64 for a batch: dDist double [out_len], indexed like ptp_batch_run. */
+ptp_status ptp_batch_run_f64(ptp_batch *batch, double *dDist, void *stream);
 
 /* Synchronise and report: per-mesh stats and status (host arrays [count],
  * either may be NULL).  Returns PTP_OK, or the first non-OK mesh status. */

@@ -168,7 +168,22 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
     for (int g = 0; g < s.ngroups; ++g) ord[g] = g;
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return gsz[x] > gsz[y]; });
     std::vector<WgInfo> slot;      // by launch index
+    // Every XCD holds at most `cap` workgroups, so launch indices stay below
+    // 8 cap <= gmax.  A rank whose preferred XCD is full goes to the least
+    // used one with room; if none has room, the placement falls back to
+    // consecutive indices.
+    bool full = false;
     auto put = [&](int x, const WgInfo& info) {
+        if (used[x] >= cap) {
+            int alt = -1;
+            for (int y = 0; y < kXcd; ++y)
+                if (used[y] < cap && (alt < 0 || used[y] < used[alt])) alt = y;
+            if (alt < 0) {
+                full = true;
+                return;
+            }
+            x = alt;
+        }
         const int idx = kXcd * used[x] + x;
         used[x] += 1;
         if ((int)slot.size() <= idx) slot.resize(idx + 1, WgInfo{-1, 0, 0, 0});
@@ -187,6 +202,12 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
                 put(x, WgInfo{g, r, gsz[g], firsts[g]});
             }
         }
+    }
+    if (full || (int)slot.size() > gmax) {
+        for (int g = 0; g < s.ngroups; ++g)
+            for (int r = 0; r < gsz[g]; ++r) s.wg.push_back(WgInfo{g, r, gsz[g], firsts[g]});
+        s.G = first;
+        return s;
     }
     s.wg = slot;
     s.G = (int)slot.size();
@@ -221,8 +242,11 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * (N + 1),                 // rowN
         sizeof(int2) * (F3 + 1),               // wedge
         sizeof(float4) * N,                    // xyz
-        sizeof(float) * 2 * N,                 // dist
-        sizeof(unsigned long long) * 2 * N,    // dl
+        // dist / dl: one region, 8 bytes per entry.  A run uses either the
+        // float double buffer (plain and warm runs) or the 8-byte one
+        // (labelled runs: (distance, label) pairs; the float64 run: doubles)
+        sizeof(unsigned long long) * 2 * N,    // dist and dl
+        0,                                     // (dl aliases dist)
         sizeof(unsigned) * 2 * (size_t)z.W,    // bits
         sizeof(int) * 4 * G,                   // cnt
         sizeof(int) * N,                       // retire
@@ -234,6 +258,9 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * (N + 1),                 // fanrow
         sizeof(int) * (2 * F3 + 1),            // fan
         sizeof(int) * kEll * N,                // ellO
+        sizeof(WgInfo) * G,                    // wg_run64
+        sizeof(int) * (G + 1 + B),             // glist_run64
+        sizeof(double) * (size_t)z.S * (kCvtChunks * 6 + 4),   // cvt partial sums, centroids
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -268,7 +295,7 @@ Work carve(void* base, const Layout& L) {
     w.wedge = reinterpret_cast<int2*>(b + L.off[18]);
     w.xyz = reinterpret_cast<float4*>(b + L.off[19]);
     w.dist = reinterpret_cast<float*>(b + L.off[20]);
-    w.dl = reinterpret_cast<unsigned long long*>(b + L.off[21]);
+    w.dl = reinterpret_cast<unsigned long long*>(b + L.off[20]);
     w.bits = reinterpret_cast<unsigned*>(b + L.off[22]);
     w.cnt = reinterpret_cast<int*>(b + L.off[23]);
     w.retire = reinterpret_cast<int*>(b + L.off[24]);
@@ -280,6 +307,9 @@ Work carve(void* base, const Layout& L) {
     w.fanrow = reinterpret_cast<int*>(b + L.off[30]);
     w.fan = reinterpret_cast<int*>(b + L.off[31]);
     w.ellO = reinterpret_cast<int*>(b + L.off[32]);
+    w.wg_run64 = reinterpret_cast<WgInfo*>(b + L.off[33]);
+    w.glist_run64 = reinterpret_cast<int*>(b + L.off[34]);
+    w.cvt = reinterpret_cast<double*>(b + L.off[35]);
     return w;
 }
 
@@ -292,14 +322,20 @@ struct Solver {
     Sizes z{};
     ptp_options opt{};
     bool single = false;
-    int device = 0, cus = 0, max_prep = 0, max_run = 0, lds_max = 0;
+    int device = 0, cus = 0, max_prep = 0, max_run = 0, max_run64 = 0, lds_max = 0;
     std::vector<int> lds_list, grid_list;   // meshes of the one-workgroup / grid BFS
     ptp_schedule sched{};
-    Sched s_prep, s_run;
+    Sched s_prep, s_run, s_run64;
+    bool sched64_ready = false;             // s_run64 uploaded for the current prepare
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // prepare begin/end, run begin/end
+    float ms_prepare = -1.f;
+    bool run_timed = false;
     Layout layout{};
     Work work{};
     hipStream_t stream = nullptr;
-    const int32_t* S = nullptr;
+    const int32_t* S = nullptr;         // the caller's arrays of the last prepare
+    const float* Vp = nullptr;
+    const int32_t* Fp = nullptr;
     std::vector<MeshState> hstate;
     bool prepared = false, ran = false;
     std::string err;
@@ -311,6 +347,11 @@ struct Solver {
     }
     ptp_status hip_fail(hipError_t e, const char* what) {
         return fail(PTP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+
+    ~Solver() {
+        for (hipEvent_t& e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 
     ptp_status init(const ptp_mesh* m, int count, const ptp_options* o, bool one) {
@@ -325,9 +366,10 @@ struct Solver {
             opt.want_labels = 0;
             opt.workgroups = 0;
             opt.lds_bfs_max = 0;
+            opt.band_rule = PTP_BAND_PAPER;
         }
         if (!(opt.tol > 0.f) || opt.max_iters < 0 || opt.window < 0 || opt.workgroups < 0 ||
-            opt.lds_bfs_max < -1)
+            opt.lds_bfs_max < -1 || opt.band_rule < PTP_BAND_PAPER || opt.band_rule > PTP_BAND_JACOBI)
             return PTP_EINVAL;
         long long N = 0, F = 0, Sn = 0, W = 0;
         h_vo.assign(1, 0);
@@ -366,8 +408,12 @@ struct Solver {
         int coop = 0;
         if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
         if (e != hipSuccess || !coop || cus < 1) return PTP_EDEVICE;
+        for (hipEvent_t& x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return PTP_EDEVICE;
         max_prep = max_coop_blocks_bfs(cus);
-        max_run = max_coop_blocks_run(cus, opt.want_labels != 0, single);
+        const bool rules = opt.band_rule != PTP_BAND_PAPER;
+        max_run = max_coop_blocks_run(cus, opt.want_labels != 0, single, rules);
+        max_run64 = max_coop_blocks_run64(cus, rules);
         lds_max = opt.lds_bfs_max < 0 ? 0 : bfs_lds_max_vertices(device);
         if (opt.lds_bfs_max > 0) lds_max = std::min(lds_max, opt.lds_bfs_max);
         long long lds_words = 0;
@@ -385,7 +431,7 @@ struct Solver {
         z.S = Sn;
         z.B = count;
         z.W = W;
-        z.gmax = std::max(max_prep, max_run);
+        z.gmax = std::max(max_prep, std::max(max_run, max_run64));
         sched = default_schedule();
         work_layout(z, &layout);
         return PTP_OK;
@@ -440,6 +486,8 @@ struct Solver {
                        size_t bytes, void* st) {
         prepared = false;
         ran = false;
+        sched64_ready = false;
+        ms_prepare = -1.f;
         if (!dV || !dS || (!dF && z.F > 0) || !dWork) return fail(PTP_EINVAL, "null pointer argument");
         if (reinterpret_cast<uintptr_t>(dWork) & 255)
             return fail(PTP_EINVAL, "workspace must be 256-byte aligned");
@@ -447,6 +495,8 @@ struct Solver {
         stream = static_cast<hipStream_t>(st);
         work = carve(dWork, layout);
         S = dS;
+        Vp = dV;
+        Fp = dF;
         // the grid BFS takes the meshes too large for one workgroup's LDS
         s_prep = Sched{};
         if (!grid_list.empty()) {
@@ -462,8 +512,10 @@ struct Solver {
                 s_prep.glist[x] = grid_list[s_prep.glist[x]];
         }
         hstate.assign(z.B, MeshState{});
-        hipError_t e = hipMemcpyAsync(work.mesh, mesh.data(), sizeof(MeshDesc) * z.B,
-                                      hipMemcpyHostToDevice, stream);
+        const bool timed = !capturing();
+        hipError_t e = timed ? hipEventRecord(ev[0], stream) : hipSuccess;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work.mesh, mesh.data(), sizeof(MeshDesc) * z.B, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(work.vo, h_vo.data(), sizeof(int) * (z.B + 1), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
@@ -480,12 +532,17 @@ struct Solver {
         if (e != hipSuccess) return hip_fail(e, "prepare upload");
         e = launch_prepare(work, z, dV, dF, dS, s_prep.G, (int)lds_list.size(), stream);
         if (e != hipSuccess) return hip_fail(e, "prepare launch");
+        if (timed) {
+            e = hipEventRecord(ev[1], stream);
+            if (e != hipSuccess) return hip_fail(e, "prepare event");
+        }
         e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hstate.data(), work.state, sizeof(MeshState) * z.B, hipMemcpyDeviceToHost,
                                stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "prepare");
+        if (timed && hipEventElapsedTime(&ms_prepare, ev[0], ev[1]) != hipSuccess) ms_prepare = -1.f;
         if (h_ctrl[C_ABORT]) return fail(PTP_EDEVICE, "BFS barrier timed out");
         const int stw = h_ctrl[C_STATUS];
         if (stw) {
@@ -513,27 +570,126 @@ struct Solver {
         return PTP_OK;
     }
 
-    // dUpper non-null: warm start from that caller-order upper bound.
-    ptp_status run(float* dDist, int32_t* dLabel, void* st, const float* dUpper = nullptr) {
+    bool capturing() const {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        return hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    }
+
+    // Double-precision schedule: the same work distribution, limited to the
+    // workgroups the float64 kernel can keep resident.
+    ptp_status ensure_sched64() {
+        if (sched64_ready) return PTP_OK;
+        std::vector<long long> rho(z.B);
+        long long reach = 0;
+        for (int b = 0; b < z.B; ++b) {
+            rho[b] = hstate[b].rho;
+            reach += hstate[b].reach;
+        }
+        s_run64 = make_schedule(mesh, rho, sched, max_run64, single, single_group(max_run64, reach));
+        hipError_t e = upload(s_run64, work.wg_run64, work.glist_run64);
+        if (e != hipSuccess) return hip_fail(e, "schedule upload");
+        sched64_ready = true;
+        return PTP_OK;
+    }
+
+    // dUpper non-null: warm start from that caller-order upper bound
+    // (certified, or with certify = false trusted as a supersolution);
+    // dDist64 non-null: the float64 run.
+    ptp_status run(float* dDist, int32_t* dLabel, void* st, const float* dUpper = nullptr,
+                   double* dDist64 = nullptr, bool certify = true) {
         if (!prepared) return fail(PTP_EINVAL, "run before a successful prepare");
-        if (!dDist) return fail(PTP_EINVAL, "null distance output");
+        const bool f64 = dDist64 != nullptr;
+        if (!dDist && !f64) return fail(PTP_EINVAL, "null distance output");
         const bool labels = opt.want_labels != 0;
         if (labels && dUpper) return fail(PTP_EUNSUPPORTED, "a warm start does not compute labels");
+        if (f64 && (labels || dUpper))
+            return fail(PTP_EUNSUPPORTED, "the float64 run computes distances only, from +inf");
         if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
         stream = static_cast<hipStream_t>(st);
+        if (f64) {
+            ptp_status r = ensure_sched64();
+            if (r != PTP_OK) return r;
+        }
         RunParams rp;
         rp.B = z.B;
         rp.kmax_fixed = opt.max_iters;
         rp.window = opt.window;
+        rp.band_rule = opt.band_rule;
         rp.N = z.N;
         rp.tol = opt.tol;
         rp.S = S;
         rp.upper = dUpper;
+        rp.certify = certify;
         rp.out_d = dDist;
+        rp.out_d64 = dDist64;
         rp.out_l = labels ? dLabel : nullptr;
-        hipError_t e = launch_run(work, rp, labels, single, s_run.G, stream);
+        run_timed = !capturing();
+        hipError_t e = run_timed ? hipEventRecord(ev[2], stream) : hipSuccess;
+        if (e == hipSuccess)
+            e = launch_run(work, rp, labels, single && !f64, f64, f64 ? s_run64.G : s_run.G, stream);
+        if (e == hipSuccess && run_timed) e = hipEventRecord(ev[3], stream);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         ran = true;
+        return PTP_OK;
+    }
+
+    // Farthest point sampling (Sec. 5.3) on a single mesh: S[0, n0) are the
+    // caller's sources; S[n0, m) receive the samples.  Every step is enqueued
+    // without a host round trip: run, farthest vertex, BFS + reorder.
+    ptp_status fps(const float* dV, const int32_t* dF, int32_t* dS, int n0, void* dWork, size_t bytes,
+                   bool warm, float* dDist, float* dRadius, int64_t* dSteps, void* st) {
+        if (!single || z.B != 1) return fail(PTP_EINVAL, "sampling runs on a single-mesh plan");
+        if (opt.want_labels) return fail(PTP_EUNSUPPORTED, "sampling computes distances only");
+        const int mt = mesh[0].m;
+        if (n0 < 1 || n0 > mt) return fail(PTP_EINVAL, "n_initial must be in [1, n_sources]");
+        if (!dDist) return fail(PTP_EINVAL, "null distance output");
+        // validate and prepare with the first n0 sources
+        mesh[0].m = n0;
+        h_so[1] = n0;
+        const long long zs = z.S;
+        z.S = n0;
+        ptp_status r = prepare(dV, dF, dS, dWork, bytes, st);
+        mesh[0].m = mt;
+        h_so[1] = mt;
+        z.S = zs;
+        if (r != PTP_OK) return r;
+        const int n = mesh[0].n;
+        hipError_t e = hipSuccess;
+        for (int slot = n0;; ++slot) {
+            r = run(dDist, nullptr, st, warm && slot > n0 ? dDist : nullptr, nullptr, false);
+            if (r != PTP_OK) return r;
+            int64_t* step = dSteps ? dSteps + 2 * (size_t)(slot - n0) : nullptr;
+            if (slot == mt) {
+                e = launch_fps_pick(work, dDist, n, dS, -1, nullptr, reinterpret_cast<long long*>(step), stream);
+                break;
+            }
+            e = launch_fps_pick(work, dDist, n, dS, slot, dRadius ? dRadius + (slot - n0) : nullptr,
+                                reinterpret_cast<long long*>(step), stream);
+            if (e == hipSuccess)
+                e = launch_prepare_bfs(work, z, dV, dS, s_prep.G, (int)lds_list.size(), stream);
+            if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "sampling");
+        if (h_ctrl[C_STATUS] & ST_FPS_EMPTY)
+            return fail(PTP_EINVAL, "fewer reachable vertices than samples requested");
+        if (h_ctrl[C_STATUS]) return fail(PTP_EINVAL, "invalid input during sampling");
+        return stats(nullptr, nullptr);
+    }
+
+    // One Lloyd step on the labels of the last run (caller order), over the
+    // mesh and sources of the last prepare (validated there).
+    ptp_status lloyd_step(const int32_t* dLabel, int32_t* dSout, double* dCentroid, void* st) {
+        if (!single || z.B != 1) return fail(PTP_EINVAL, "Lloyd steps run on a single-mesh plan");
+        if (!prepared) return fail(PTP_EINVAL, "Lloyd step before a successful prepare");
+        if (!dLabel || !dSout) return fail(PTP_EINVAL, "null pointer argument");
+        if (dSout == S) return fail(PTP_EINVAL, "the new generators may not overwrite the sources");
+        stream = static_cast<hipStream_t>(st);
+        const int m = mesh[0].m;
+        double* cen = dCentroid ? dCentroid : work.cvt + (size_t)z.S * kCvtChunks * 6;
+        hipError_t e = launch_lloyd(work, Vp, Fp, mesh[0].n, mesh[0].f, dLabel, S, m, dSout, cen, stream);
+        if (e != hipSuccess) return hip_fail(e, "Lloyd launch");
         return PTP_OK;
     }
 
@@ -566,6 +722,11 @@ struct Solver {
                                stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "stats");
+        float ms_run = -1.f;
+        if (run_timed && hipEventElapsedTime(&ms_run, ev[2], ev[3]) != hipSuccess) ms_run = -1.f;
+        long long t0 = 0;
+        for (int b = 0; b < z.B; ++b)
+            if (hstate[b].t_begin && (!t0 || hstate[b].t_begin < t0)) t0 = hstate[b].t_begin;
         ptp_status agg = PTP_OK;
         for (int b = 0; b < z.B; ++b) {
             const MeshState& x = hstate[b];
@@ -582,6 +743,11 @@ struct Solver {
                 out[b].vertex_updates = x.updates;
                 out[b].certify_rounds = x.cert_rounds;
                 out[b].certify_rejected = x.cert_rejected;
+                out[b].ms_prepare = ms_prepare;
+                out[b].ms_run = ms_run;
+                // device wall clock at 100 MHz
+                out[b].ms_mesh_begin = x.t_begin ? (float)((x.t_begin - t0) * 1e-5) : -1.f;
+                out[b].ms_mesh_end = x.t_end ? (float)((x.t_end - t0) * 1e-5) : -1.f;
             }
             if (agg == PTP_OK && sb != PTP_OK) agg = sb;
         }
@@ -667,7 +833,7 @@ struct ptp_batch {
 
 extern "C" {
 
-const char* ptp_version(void) { return "ptp-mi355x 0.3 (gfx950)"; }
+const char* ptp_version(void) { return "ptp-mi355x 0.4 (gfx950)"; }
 
 // ---- one mesh ------------------------------------------------------------
 ptp_status ptp_plan_create(ptp_plan** out, int32_t n, int32_t f, int32_t m, const ptp_options* opt) {
@@ -675,7 +841,8 @@ ptp_status ptp_plan_create(ptp_plan** out, int32_t n, int32_t f, int32_t m, cons
     *out = nullptr;
     if (n < 1 || f < 0 || m < 1 || m > n) return PTP_EINVAL;
     if (n > (1 << 29) || (long long)f * 3 >= (1ll << 31)) return PTP_EUNSUPPORTED;
-    if (opt && (!(opt->tol > 0.f) || opt->max_iters < 0 || opt->window < 0 || opt->workgroups < 0))
+    if (opt && (!(opt->tol > 0.f) || opt->max_iters < 0 || opt->window < 0 || opt->workgroups < 0 ||
+                opt->band_rule < PTP_BAND_PAPER || opt->band_rule > PTP_BAND_JACOBI))
         return PTP_EINVAL;
     ptp_plan* p = new (std::nothrow) ptp_plan();
     if (!p) return PTP_ENOMEM;
@@ -724,6 +891,24 @@ ptp_status ptp_solve(ptp_plan* p, const float* dV, const int32_t* dF, const int3
     s = ptp_run(p, dDist, dLabel, stream);
     if (s != PTP_OK) return s;
     return ptp_get_stats(p, stats);
+}
+
+ptp_status ptp_run_f64(ptp_plan* p, double* dDist, void* stream) {
+    if (!p) return PTP_EINVAL;
+    if (!dDist) return p->s.fail(PTP_EINVAL, "null distance output");
+    return p->s.run(nullptr, nullptr, stream, nullptr, dDist);
+}
+
+ptp_status ptp_fps(ptp_plan* p, const float* dV, const int32_t* dF, int32_t* dS, int32_t n_initial,
+                   void* dWork, size_t work_bytes, int32_t warm, float* dDist, float* dRadius, int64_t* dSteps,
+                   void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.fps(dV, dF, dS, n_initial, dWork, work_bytes, warm != 0, dDist, dRadius, dSteps, stream);
+}
+
+ptp_status ptp_lloyd_step(ptp_plan* p, const int32_t* dLabel, int32_t* dSout, double* dCentroid, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.lloyd_step(dLabel, dSout, dCentroid, stream);
 }
 
 ptp_status ptp_get_order(ptp_plan* p, int32_t* dPerm, int32_t* dOffsets, void* stream) {
@@ -815,6 +1000,12 @@ ptp_status ptp_batch_prepare(ptp_batch* p, const float* dV, const int32_t* dF, c
 ptp_status ptp_batch_run(ptp_batch* p, float* dDist, int32_t* dLabel, void* stream) {
     if (!p) return PTP_EINVAL;
     return p->s.run(dDist, dLabel, stream);
+}
+
+ptp_status ptp_batch_run_f64(ptp_batch* p, double* dDist, void* stream) {
+    if (!p) return PTP_EINVAL;
+    if (!dDist) return p->s.fail(PTP_EINVAL, "null distance output");
+    return p->s.run(nullptr, nullptr, stream, nullptr, dDist);
 }
 
 ptp_status ptp_batch_get_stats(ptp_batch* p, ptp_stats* hStats, int32_t* hStatus) {

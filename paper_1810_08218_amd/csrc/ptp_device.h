@@ -22,6 +22,7 @@ enum CtrlWord : int {
     C_UPD_LO = 5,        // vertex updates, low / high 32 bits
     C_UPD_HI = 6,
     C_ABORT = 7,         // a barrier timed out
+    C_FPS_KEY = 8,       // words 8, 9: farthest point sampling argmax key (64 bits)
     C_WORDS = 64
 };
 
@@ -30,6 +31,7 @@ enum StatusBits : int {
     ST_BAD_COORD = 2,
     ST_BAD_SOURCE = 4,
     ST_DUP_SOURCE = 8,
+    ST_FPS_EMPTY = 16,   // farthest point sampling found no vertex to add
 };
 
 // ---- coherent access ---------------------------------------------------

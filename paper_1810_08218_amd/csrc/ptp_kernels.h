@@ -29,6 +29,8 @@ struct MeshState {         // per mesh, written by the kernels
     long long updates;     // U
     int cert_rounds;       // warm start: certification sweeps
     int cert_rejected;     // warm start: bounds withdrawn by the certification
+    long long t_begin;     // device wall clock (100 MHz ticks) when the group
+    long long t_end;       //   started / finished this mesh's iteration
 };
 
 struct WgInfo {            // per workgroup of a persistent launch
@@ -57,8 +59,9 @@ struct Work {
     int* rowN;          // [N + 1] incidence CSR over positions
     int2* wedge;        // [3F]    opposite edge, positions
     float4* xyz;        // [N]     coordinates by position (w unused)
-    float* dist;        // [2N]    Jacobi double buffer
-    unsigned long long* dl;   // [2N] (distance, label) double buffer of the labelled run
+    float* dist;        // [2N]    Jacobi double buffer (plain and warm runs)
+    unsigned long long* dl;   // [2N] the same memory as 8-byte entries: (distance, label)
+                              // pairs of the labelled run, doubles of the float64 run
     unsigned* bits;     // [2 * W] frontier bitmaps, mesh b at 2 * w_off_b
     int* cnt;           // [4 * gmax] per-workgroup chunk counts
     int* retire;        // [N]     last iteration that updated each topleset, mesh b at v_off_b
@@ -70,9 +73,16 @@ struct Work {
     int* fanrow;        // [N + 1] fan CSR over positions
     int* fan;           // [6F]    fans of the incident triangles, positions and flags
     int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
+    WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation
+    int* glist_run64;   // [gmax + 1 + B]
+    double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
 };
 
-constexpr int kLayoutParts = 33;
+constexpr int kLayoutParts = 36;
+
+// Lloyd step: every cell's sums are split over this many chunks of the
+// faces (or vertices), each reduced in a fixed order.
+constexpr int kCvtChunks = 64;
 
 // Neighbour rows of the BFS: the distinct neighbours of a vertex in one
 // 32-byte row, padded with -1; a vertex with more keeps kEllMore in its last
@@ -120,18 +130,29 @@ int bfs_lds_max_vertices(int device);
 // zero the barrier lines (two banks of one per workgroup) of a launch
 void launch_barrier_reset(const Work& w, int lines, hipStream_t st);
 
+// Band rules of the relaxation.
+enum BandRule : int {
+    BAND_PAPER = 0,      // Eq. upper_band / Eq. lower_band (relative change)
+    BAND_FIXED_HALF = 1, // [max(1, floor((k+1)/2)), min(k, rho-1)] for 2 rho - 3 iterations
+    BAND_JACOBI = 2,     // every topleset from 1; stop when no value changed
+};
+
 struct RunParams {
-    int B, kmax_fixed, window;   // kmax_fixed 0: 4 rho + 16 per mesh
+    int B, kmax_fixed, window;   // kmax_fixed 0: the rule's default per mesh
+    int band_rule;
     long long N;
     float tol;
     const int* S;
     const float* upper;          // warm start: caller-order upper bound, or null
+    bool certify;                // warm start: certify the bound (else trusted)
     float* out_d;
+    double* out_d64;             // the double-precision run's output
     int* out_l;
 };
 
-// cache: use the register-caching relaxation (single meshes)
-hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, int g_run,
+// cache: use the register-caching relaxation (single meshes); f64: the
+// double-precision relaxation (no labels, no warm start, no cache)
+hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, bool f64, int g_run,
                       hipStream_t st);
 
 // learned warm start
@@ -148,6 +169,20 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
 size_t mlp_scratch_bytes();
 
 int max_coop_blocks_bfs(int cus);
-int max_coop_blocks_run(int cus, bool labels, bool cache);
+int max_coop_blocks_run(int cus, bool labels, bool cache, bool rules);
+int max_coop_blocks_run64(int cus, bool rules);
+
+// farthest point sampling: argmax of the caller-order map of mesh 0, append
+// to S, grow the mesh's source count; and the BFS + reorder alone (the
+// incidence of the mesh is unchanged between samples)
+hipError_t launch_fps_pick(const Work& w, const float* dist, int n, int* S, int slot, float* radius,
+                           long long* step_stats, hipStream_t st);
+hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, const int* S, int g_prep,
+                              int n_lds, hipStream_t st);
+
+// Lloyd step on Voronoi labels: cell moments over the faces, centroids, the
+// nearest vertex of each cell
+hipError_t launch_lloyd(const Work& w, const float* V, const int* F, int nv, int nf, const int* label,
+                        const int* S_in, int m, int* S_out, double* centroid, hipStream_t st);
 
 }  // namespace ptp

@@ -759,7 +759,16 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     hipLaunchKernelGGL(k_ell, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_prepare_bfs(w, z, V, S, g_prep, n_lds, st);
+}
 
+// Toplesets by BFS from the current sources, then the reorder of coordinates
+// and incidence into topleset order and the fans.  The incidence (rowO,
+// wedgeO, ellO) must already be built; it does not depend on the sources.
+hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, const int* S, int g_prep,
+                              int n_lds, hipStream_t st) {
+    const long long N = z.N;
+    hipError_t e;
     BfsArgs a;
     a.G = g_prep;
     a.mesh = w.mesh;

@@ -6,6 +6,11 @@
 //     relative-change test of the band's first topleset (Eq. lower_band),
 //     band ends advanced on the device (Eq. upper_band / lower_band),
 //   unpermute of distances and labels to the caller's order.
+// Two other controllers share the loop: the fixed half band
+// [floor((k+1)/2), k] of the complexity analysis (Sec. 6) and plain Jacobi
+// over every topleset until no value changes (the fixed point the iteration
+// approximates).  The arithmetic is float32, or float64 (Sec. 5.1 runs both)
+// in the `double` instantiation.
 // One group barrier per iteration; the controller state (i, j, k) is kept in
 // registers, identical in every workgroup of the group, and the only datum
 // exchanged per iteration besides the distances is the "not converged" vote,
@@ -20,16 +25,22 @@ namespace ptp {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
+template <typename R>
+__device__ constexpr R inf_of() { return (R)__builtin_huge_val(); }
 
-__device__ inline float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+template <typename R>
+__device__ inline R dot3(R ax, R ay, R az, R bx, R by, R bz) {
     return ax * bx + ay * by + az * bz;
 }
 
-// Hardware square root and reciprocal (v_sqrt_f32 / v_rcp_f32, about 1 ulp):
-// the update needs relative accuracy near 1e-7, not correct rounding, and
-// the IEEE sequences are several times longer on the critical path.
+// Square root and reciprocal.  float: the hardware instructions (v_sqrt_f32 /
+// v_rcp_f32, about 1 ulp): the update needs relative accuracy near 1e-7, not
+// correct rounding, and the IEEE sequences are several times longer on the
+// critical path.  double: the correctly rounded operations.
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fsqrt(double x) { return __builtin_sqrt(x); }
+__device__ inline double frcp(double x) { return 1.0 / x; }
 
 // Planar update of x0 from (x1, d1), (x2, d2).
 //
@@ -50,26 +61,25 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // after the other.  An infinite input needs no case of its own: its edge
 // update is infinite and the discriminant is -inf or NaN, so the finite edge
 // update is selected (both infinite: +inf).
-template <bool LABELS>
-__device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, float d2, int l1,
-                                     int l2, int& lab) {
-    const float e1x = x1.x - x0.x, e1y = x1.y - x0.y, e1z = x1.z - x0.z;
-    const float e2x = x2.x - x0.x, e2y = x2.y - x0.y, e2z = x2.z - x0.z;
-    const float a = dot3(e1x, e1y, e1z, e1x, e1y, e1z);
-    const float c = dot3(e2x, e2y, e2z, e2x, e2y, e2z);
-    const float p1 = d1 + fsqrt(a), p2 = d2 + fsqrt(c);
-    const float pe = p2 < p1 ? p2 : p1;
-    const float b = dot3(e1x, e1y, e1z, e2x, e2y, e2z);
-    const float cx = e1y * e2z - e1z * e2y;
-    const float cy = e1z * e2x - e1x * e2z;
-    const float cz = e1x * e2y - e1y * e2x;
-    const float det = dot3(cx, cy, cz, cx, cy, cz);
-    const float fx = x1.x - x2.x, fy = x1.y - x2.y, fz = x1.z - x2.z;
-    const float A = dot3(fx, fy, fz, fx, fy, fz);
-    const float delta = d2 - d1;
-    const float disc = det * (A - delta * delta);
-    const float q = (delta * (a - b) + fsqrt(disc)) * frcp(A);
-    const bool planar = det > 1e-12f * a * c && disc >= 0.f && q * (c - b) + b * delta > 0.f &&
+template <typename R, bool LABELS>
+__device__ inline R local_update(float4 x0, float4 x1, float4 x2, R d1, R d2, int l1, int l2, int& lab) {
+    const R e1x = (R)x1.x - (R)x0.x, e1y = (R)x1.y - (R)x0.y, e1z = (R)x1.z - (R)x0.z;
+    const R e2x = (R)x2.x - (R)x0.x, e2y = (R)x2.y - (R)x0.y, e2z = (R)x2.z - (R)x0.z;
+    const R a = dot3(e1x, e1y, e1z, e1x, e1y, e1z);
+    const R c = dot3(e2x, e2y, e2z, e2x, e2y, e2z);
+    const R p1 = d1 + fsqrt(a), p2 = d2 + fsqrt(c);
+    const R pe = p2 < p1 ? p2 : p1;
+    const R b = dot3(e1x, e1y, e1z, e2x, e2y, e2z);
+    const R cx = e1y * e2z - e1z * e2y;
+    const R cy = e1z * e2x - e1x * e2z;
+    const R cz = e1x * e2y - e1y * e2x;
+    const R det = dot3(cx, cy, cz, cx, cy, cz);
+    const R fx = (R)x1.x - (R)x2.x, fy = (R)x1.y - (R)x2.y, fz = (R)x1.z - (R)x2.z;
+    const R A = dot3(fx, fy, fz, fx, fy, fz);
+    const R delta = d2 - d1;
+    const R disc = det * (A - delta * delta);
+    const R q = (delta * (a - b) + fsqrt(disc)) * frcp(A);
+    const bool planar = det > (R)1e-12 * a * c && disc >= (R)0 && q * (c - b) + b * delta > (R)0 &&
                         q * (a - b) > a * delta;
     if (LABELS) {
         const int lmin = min(l1, l2);
@@ -83,6 +93,8 @@ __device__ inline float local_update(float4 x0, float4 x1, float4 x2, float d1, 
 struct RelaxArgs {
     int G;                 // workgroups of the launch
     int kmax_fixed, window;
+    int band_rule;         // BandRule
+    int certify;           // warm start: certify the bound first (else trusted)
     float tol;
     const MeshDesc* mesh;
     MeshState* state;
@@ -98,12 +110,13 @@ struct RelaxArgs {
     const int* fan;
     const float4* xyz;
     float* dist;           // [2N]
-    unsigned long long* dl;   // [2N] (distance, label) pairs, with labels
+    unsigned long long* dl;   // [2N] (distance, label) pairs, with labels; doubles in the f64 run
     int* retire;
     int* ctrl;
     unsigned* bar;
     long long N;
     float* out_d;
+    double* out_d64;
     int* out_l;
 };
 
@@ -112,39 +125,39 @@ struct RelaxArgs {
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
-// The iteration state of a position: its distance (float), or with labels
-// its (distance, label) pair in one 8-byte word, so that a neighbour costs
-// one coherent load and a position one store.
+// The iteration state of a position: its distance, or with labels (float
+// only) its (distance, label) pair in one 8-byte word, so that a neighbour
+// costs one coherent load and a position one store.
 __device__ inline unsigned long long pack_dl(float d, int l) {
     return (unsigned long long)__float_as_uint(d) | ((unsigned long long)(unsigned)l << 32);
 }
 
-template <bool LABELS>
-__device__ inline void ld_s(const void* s, int id, float& d, int& l) {
+template <typename R, bool LABELS>
+__device__ inline void ld_s(const void* s, int id, R& d, int& l) {
     if (LABELS) {
         const unsigned long long x = ld_c(static_cast<const unsigned long long*>(s) + id);
-        d = __uint_as_float((unsigned)x);
+        d = (R)__uint_as_float((unsigned)x);
         l = (int)(unsigned)(x >> 32);
     } else {
-        d = ld_c(static_cast<const float*>(s) + id);
+        d = ld_c(static_cast<const R*>(s) + id);
     }
 }
 
-template <bool LABELS>
-__device__ inline void st_s(void* s, int id, float d, int l, bool local) {
-    if (LABELS) st_g(static_cast<unsigned long long*>(s) + id, pack_dl(d, l), local);
-    else st_g(static_cast<float*>(s) + id, d, local);
+template <typename R, bool LABELS>
+__device__ inline void st_s(void* s, int id, R d, int l, bool local) {
+    if (LABELS) st_g(static_cast<unsigned long long*>(s) + id, pack_dl((float)d, l), local);
+    else st_g(static_cast<R*>(s) + id, d, local);
 }
 
 // Planar update of x0 from one triangle, folded into the (value, label)
 // lexicographic minimum best / bl, which does not depend on the order in
 // which the triangles come.
-template <bool LABELS>
-__device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, float d1, float d2,
-                                   int l1, int l2, float& best, int& bl, bool valid = true) {
+template <typename R, bool LABELS>
+__device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, R d1, R d2, int l1,
+                                   int l2, R& best, int& bl, bool valid = true) {
     int l = 0;
-    const float u = local_update<LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
-    const bool take = valid && (u < best || (LABELS && u == best && l < bl && u < kInf));
+    const R u = local_update<R, LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
+    const bool take = valid && (u < best || (LABELS && u == best && l < bl && u < inf_of<R>()));
     best = take ? u : best;
     if (LABELS) bl = take ? l : bl;
 }
@@ -154,29 +167,28 @@ __device__ inline void fold_update(const float4 x0, const float4 x1, const float
 // coordinates and labels).  Slot q (1 <= q <= C) is the pair (entry q-1,
 // entry q) for q < L unless entry q opens a chain, and the closing pair
 // (entry L-1, entry 0) for q = L on a closed fan.
-template <bool LABELS, int C>
-__device__ inline void eval_fan_first(const float4 x0, const int* e, const float* d, const float4* x,
-                                      const int* l, int L, float& best, int& bl) {
+template <typename R, bool LABELS, int C>
+__device__ inline void eval_fan_first(const float4 x0, const int* e, const R* d, const float4* x, const int* l,
+                                      int L, R& best, int& bl) {
     const bool closed = (e[0] & kFanClosed) != 0;
 #pragma unroll
     for (int q = 1; q <= C; ++q) {
         const int q2 = q < C ? q : 0;
         const bool valid = q < C ? (q < L ? (e[q] & kFanStart) == 0 : (q == L && closed)) : (L == C && closed);
-        fold_update<LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0,
-                            LABELS ? l[q2] : 0, best, bl, valid);
+        fold_update<R, LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0, LABELS ? l[q2] : 0,
+                               best, bl, valid);
     }
 }
 
 // The rest of a fan longer than C entries: chunks of C entries overlapping
 // by one, then the closing pair with entry 0 (d0 / xf / l0) on a closed fan.
-template <bool LABELS, int C>
-__device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0, int f0, int L,
-                                     bool closed, float d0, float4 xf, int l0, const void* sold,
-                                     float& best, int& bl) {
+template <typename R, bool LABELS, int C>
+__device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0, int f0, int L, bool closed,
+                                     R d0, float4 xf, int l0, const void* sold, R& best, int& bl) {
     for (int base = C - 1; base < L - 1; base += C - 1) {
         const int cnt = min(C, L - base);
         int e[C], l[C];
-        float d[C];
+        R d[C];
         float4 x[C];
 #pragma unroll
         for (int q = 0; q < C; ++q) e[q] = q < cnt ? a.fan[f0 + base + q] : v;
@@ -184,62 +196,74 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
         for (int q = 0; q < C; ++q) {
             const int id = e[q] & kFanId;
             l[q] = 0;
-            ld_s<LABELS>(sold, id, d[q], l[q]);
+            ld_s<R, LABELS>(sold, id, d[q], l[q]);
             x[q] = a.xyz[id];
         }
 #pragma unroll
         for (int q = 1; q < C; ++q)
-            fold_update<LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl,
-                                q < cnt && (e[q] & kFanStart) == 0);
+            fold_update<R, LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl,
+                                   q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
-            float dl;
+            R dl;
             int ll = 0;
-            ld_s<LABELS>(sold, id, dl, ll);
+            ld_s<R, LABELS>(sold, id, dl, ll);
             const float4 xl = a.xyz[id];
-            fold_update<LABELS>(x0, xl, xf, dl, d0, ll, l0, best, bl);
+            fold_update<R, LABELS>(x0, xl, xf, dl, d0, ll, l0, best, bl);
         }
     }
 }
 
 // First C entries of the fan at [f0, f0 + L) of position v, padded with
 // entry 0 (with v for an empty fan).
-template <bool LABELS, int C>
+template <int C>
 __device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e) {
     e[0] = L > 0 ? a.fan[f0] : v;
 #pragma unroll
     for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
 }
 
-template <bool LABELS, int C>
-__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const void* sold, float* d, float4* x,
-                                  int* l) {
+template <typename R, bool LABELS, int C>
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const void* sold, R* d, float4* x, int* l) {
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int id = e[q] & kFanId;
         int lq = 0;
-        ld_s<LABELS>(sold, id, d[q], lq);
+        ld_s<R, LABELS>(sold, id, d[q], lq);
         if (LABELS) l[q] = lq;
         x[q] = a.xyz[id];
     }
 }
 
 // Smallest planar update of position v over all its incident triangles.
-template <bool LABELS, int C>
-__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const void* sold, float& best,
+template <typename R, bool LABELS, int C>
+__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const void* sold, R& best,
                                    int& bl) {
-    best = kInf;
+    best = inf_of<R>();
     bl = 0x7fffffff;
     const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
     int e[C], l[C];
-    float d[C];
+    R d[C];
     float4 x[C];
-    load_fan<LABELS, C>(a, v, f0, L, e);
-    gather_fan<LABELS, C>(a, e, sold, d, x, l);
-    eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
+    load_fan<C>(a, v, f0, L, e);
+    gather_fan<R, LABELS, C>(a, e, sold, d, x, l);
+    eval_fan_first<R, LABELS, C>(x0, e, d, x, l, L, best, bl);
     if (L > C)
-        eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], LABELS ? l[0] : 0,
-                                 sold, best, bl);
+        eval_fan_rest<R, LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], LABELS ? l[0] : 0,
+                                    sold, best, bl);
+}
+
+// Convergence of one position between two iterations (Eq. lower_band): a
+// value that was +inf is not converged, an unchanged one is (no 0/0 at
+// coincident vertices), otherwise |dn - dv| / dv < tol.  The Jacobi rule runs
+// it with tol = 0: "finite and unchanged" (once its band holds every
+// topleset, each reachable value is finite, so this is "unchanged").
+__device__ inline float absr(float x) { return fabsf(x); }
+__device__ inline double absr(double x) { return fabs(x); }
+
+template <typename R>
+__device__ inline bool converged(R dv, R dn, float tol) {
+    return dv < inf_of<R>() && (dn == dv || absr(dn - dv) / dv < (R)tol);
 }
 
 // Band positions p, p + gsz, ... (< be) of one thread, software-pipelined:
@@ -248,7 +272,7 @@ __device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, c
 // that owns several band vertices waits for about one memory round per
 // vertex instead of three.  Returns the "not converged" vote of the
 // positions below tb.
-template <bool LABELS, int C>
+template <typename R, bool LABELS, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
                                                 long long tb, long long gsz, const void* sold, void* snew,
                                                 bool local) {
@@ -257,7 +281,7 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     int f0 = a.fanrow[vo + p];
     int L = a.fanrow[vo + p + 1] - f0;
     int e[C];
-    load_fan<LABELS, C>(a, vo + (int)p, f0, L, e);
+    load_fan<C>(a, vo + (int)p, f0, L, e);
     long long pn = p + gsz;
     int fn0 = 0, fn1 = 0;
     if (pn < be) {
@@ -267,36 +291,33 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
-        float dv;
+        R dv;
         int lv = 0;
-        ld_s<LABELS>(sold, v, dv, lv);
+        ld_s<R, LABELS>(sold, v, dv, lv);
         int l[C];
-        float d[C];
+        R d[C];
         float4 x[C];
-        gather_fan<LABELS, C>(a, e, sold, d, x, l);
+        gather_fan<R, LABELS, C>(a, e, sold, d, x, l);
         // the next position's fan entries and the fan row of the one after
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
         int en[C];
         int fnn0 = 0, fnn1 = 0;
-        if (pn < be) load_fan<LABELS, C>(a, vo + (int)pn, fn0, Ln, en);
+        if (pn < be) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
         if (pnn < be) {
             fnn0 = a.fanrow[vo + pnn];
             fnn1 = a.fanrow[vo + pnn + 1];
         }
-        float best = kInf;
+        R best = inf_of<R>();
         int bl = 0x7fffffff;
-        eval_fan_first<LABELS, C>(x0, e, d, x, l, L, best, bl);
+        eval_fan_first<R, LABELS, C>(x0, e, d, x, l, L, best, bl);
         if (L > C)
-            eval_fan_rest<LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0],
-                                     LABELS ? l[0] : 0, sold, best, bl);
+            eval_fan_rest<R, LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0],
+                                        LABELS ? l[0] : 0, sold, best, bl);
         const bool better = best < dv;
-        const float dn = better ? best : dv;
-        st_s<LABELS>(snew, v, dn, better ? bl : lv, local);
-        if (p < tb) {
-            const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
-            notconv |= conv ? 0u : 1u;
-        }
+        const R dn = better ? best : dv;
+        st_s<R, LABELS>(snew, v, dn, better ? bl : lv, local);
+        if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
         if (pn >= be) break;
         p = pn;
         pn = pnn;
@@ -322,7 +343,7 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
     int f0 = a.fanrow[vo + p];
     int L = a.fanrow[vo + p + 1] - f0;
     int e[C];
-    load_fan<false, C>(a, vo + (int)p, f0, L, e);
+    load_fan<C>(a, vo + (int)p, f0, L, e);
     long long pn = p + gsz;
     int fn0 = 0, fn1 = 0;
     if (pn < end) {
@@ -336,12 +357,12 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         int l[C];
         float dd[C];
         float4 x[C];
-        gather_fan<false, C>(a, e, d, dd, x, l);
+        gather_fan<float, false, C>(a, e, d, dd, x, l);
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
         int en[C];
         int fnn0 = 0, fnn1 = 0;
-        if (pn < end) load_fan<false, C>(a, vo + (int)pn, fn0, Ln, en);
+        if (pn < end) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
         if (pnn < end) {
             fnn0 = a.fanrow[vo + pnn];
             fnn1 = a.fanrow[vo + pnn + 1];
@@ -349,10 +370,10 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         if (wv < kInf) {
             float best = kInf;
             int bl = 0;
-            eval_fan_first<false, C>(x0, e, dd, x, l, L, best, bl);
+            eval_fan_first<float, false, C>(x0, e, dd, x, l, L, best, bl);
             if (L > C)
-                eval_fan_rest<false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d, best,
-                                        bl);
+                eval_fan_rest<float, false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d,
+                                               best, bl);
             if (wv < best) {
                 st_g(d + v, kInf, local);
                 changed = 1;
@@ -393,8 +414,13 @@ constexpr int kOffsLds = 4096;
 // wedges, then every neighbour distance and coordinate of those wedges at
 // once (independent loads), then evaluates the planar updates.  Distances and
 // labels are exchanged between workgroups through coherent loads and stores.
-template <bool LABELS, bool WARM, bool CACHE>
+// R = double: the same iteration in float64 (no labels, warm start or cache).
+// RULES: the band rule is read at run time (fixed half band, Jacobi);
+// otherwise it is the paper's, fixed at compile time, which keeps the band
+// loop's registers for the common case.
+template <typename R, bool LABELS, bool WARM, bool CACHE, bool RULES = false>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
+    static_assert(sizeof(R) == 4 || (!LABELS && !WARM && !CACHE), "float64 runs plain only");
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize;
@@ -409,11 +435,15 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const long long gsz = (long long)gs * kBlock;
     const long long g0 = (long long)me.rank * kBlock + threadIdx.x;
     const bool leader = me.rank == 0 && threadIdx.x == 0;
+    const R kInfR = inf_of<R>();
     float* dA = a.dist;
     float* dB = a.dist + a.N;
-    // the iteration state: distances, or (distance, label) pairs with labels
-    void* sA = LABELS ? static_cast<void*>(a.dl) : static_cast<void*>(dA);
-    void* sB = LABELS ? static_cast<void*>(a.dl + a.N) : static_cast<void*>(dB);
+    // the iteration state: distances, or (distance, label) pairs with labels;
+    // the float64 run keeps its doubles in the 8-byte buffer
+    void* sA = (LABELS || sizeof(R) == 8) ? static_cast<void*>(a.dl) : static_cast<void*>(dA);
+    void* sB = (LABELS || sizeof(R) == 8) ? static_cast<void*>(a.dl + a.N) : static_cast<void*>(dB);
+    const int rule = RULES ? a.band_rule : (int)BAND_PAPER;
+    const bool jacobi = rule == BAND_JACOBI;
 
     // A group whose workgroups all run on one XCD exchanges its data through
     // that XCD's L2 with plain stores.  Every workgroup posts its XCD, the
@@ -438,8 +468,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const int rho = a.state[b].rho;
         const int* offs = a.offsets + vo + b;    // topleset starts, local positions
         int* retire = a.retire + vo;
-        const int kmax = a.kmax_fixed > 0 ? a.kmax_fixed : 4 * rho + 16;
+        // iteration cap: the caller's, else the rule's default
+        const int kmax = a.kmax_fixed > 0 ? a.kmax_fixed : (jacobi ? 64 * rho + 256 : 4 * rho + 16);
+        // the fixed half band finalises V_r by iteration 2r - 1 (Sec. 6
+        // lemma), so it stops after 2 rho - 3 iterations
+        const int kfix = max(1, 2 * rho - 3);
         const int m0 = offs[1];                  // |V_0|: the sources occupy [0, m0)
+        if (leader) a.state[b].t_begin = wall_clock64();
         // every read of s_offs of the previous mesh came before its last barrier
         const bool offs_lds = rho < kOffsLds;
         if (offs_lds)
@@ -447,34 +482,34 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
         const int reach = a.state[b].reach;
         for (long long p = g0; p < n; p += gsz) {
-            float d = p < m0 ? 0.f : kInf;
+            R d = p < m0 ? (R)0 : kInfR;
             if (WARM && p >= m0 && p < reach) {      // warm start: the caller's bound
                 const int v = a.perm[vo + p];
                 const float w = a.upper[md.out_off + (v - vo)];
-                d = w >= 0.f ? w : kInf;                 // NaN or negative: no bound
+                d = w >= 0.f ? (R)w : kInfR;             // NaN or negative: no bound
             }
             if (!LABELS || p >= m0) {           // with labels the sources come next
-                st_s<LABELS>(sA, vo + (int)p, d, -1, local);
-                st_s<LABELS>(sB, vo + (int)p, d, -1, local);
+                st_s<R, LABELS>(sA, vo + (int)p, d, -1, local);
+                st_s<R, LABELS>(sB, vo + (int)p, d, -1, local);
             }
         }
         if (LABELS)
             for (long long s = g0; s < md.m; s += gsz) {
                 const int p = a.iperm[vo + a.S[md.s_in + s]];
-                st_s<LABELS>(sA, p, 0.f, (int)s, local);
-                st_s<LABELS>(sB, p, 0.f, (int)s, local);
+                st_s<R, LABELS>(sA, p, (R)0, (int)s, local);
+                st_s<R, LABELS>(sB, p, (R)0, (int)s, local);
             }
         for (long long r = g0; r < rho; r += gsz) st_g(retire + r, r == 0 ? 0 : -1, local);
         if (!gb.sync(0, &any)) return;
 
-        if (WARM) {
+        if (WARM && a.certify) {
             // Certification of the warm start: a vertex whose bound lies below
             // the planar update from its neighbours' bounds (w < U(w)) loses its
             // bound (+inf); repeated until no vertex changes.  The result is a
             // supersolution (w >= U(w), w(S) = 0), hence above the fixed point,
             // so the min-relaxation from it descends to the same fixed point.
-            // Marking only raises U elsewhere, so the closure is unique and the
-            // order of the in-place updates does not matter.
+            // The closure is unique, so the order of the in-place updates does
+            // not matter.
             const long long firstc = first_owned(m0, g032, gsz32);
             int rejected = 0, round = 0;
             for (;; ++round) {
@@ -515,13 +550,15 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             ++k;
             const int j = min(k, rho - 1);                       // Eq. upper_band
             int lo = i;
+            if (rule == BAND_FIXED_HALF) lo = max(1, (k + 1) >> 1);
             if (a.window > 0) lo = max(lo, j - a.window + 1);
             const void* sold = (k & 1) ? sA : sB;
             void* snew = (k & 1) ? sB : sA;
             const int cb = offs_lds ? s_offs[lo_prev] : offs[lo_prev];   // retired since last iteration: copy
             const int bb = offs_lds ? s_offs[lo] : offs[lo];             // band
             const int be = offs_lds ? s_offs[j + 1] : offs[j + 1];
-            const int tb = offs_lds ? s_offs[lo + 1] : offs[lo + 1];     // tested topleset V_lo = [bb, tb)
+            // tested positions: V_lo (relative change), the whole band (Jacobi)
+            const int tb = jacobi ? be : (offs_lds ? s_offs[lo + 1] : offs[lo + 1]);
             unsigned notconv = 0;
             const long long first = first_owned(cb, g032, gsz32);
             // pipelined unless the register cache serves (one position per
@@ -529,22 +566,22 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
                 for (long long pp = first; pp < bb; pp += gsz) {
-                    float dc;
+                    R dc;
                     int lc = 0;
-                    ld_s<LABELS>(sold, vo + (int)pp, dc, lc);
-                    st_s<LABELS>(snew, vo + (int)pp, dc, lc, local);
+                    ld_s<R, LABELS>(sold, vo + (int)pp, dc, lc);
+                    st_s<R, LABELS>(snew, vo + (int)pp, dc, lc, local);
                 }
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_pipelined<LABELS, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
+                notconv |= relax_band_pipelined<R, LABELS, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    float dc;
+                    R dc;
                     int lc = 0;
-                    ld_s<LABELS>(sold, v, dc, lc);
-                    st_s<LABELS>(snew, v, dc, lc, local);
+                    ld_s<R, LABELS>(sold, v, dc, lc);
+                    st_s<R, LABELS>(snew, v, dc, lc, local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -553,39 +590,52 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     const int f0 = a.fanrow[v];
                     cL = a.fanrow[v + 1] - f0;
                     cv = cL <= kCache ? v : -1;
-                    if (cv >= 0) load_fan<LABELS, kCache>(a, v, f0, cL, ce);
+                    if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                float dv;
+                R dv;
                 int lv = 0;
-                ld_s<LABELS>(sold, v, dv, lv);
-                float best = kInf;
+                ld_s<R, LABELS>(sold, v, dv, lv);
+                R best = kInfR;
                 int bl = 0x7fffffff;
                 if (cached && cv == v) {
                     int l[kCache];
-                    float d[kCache];
+                    R d[kCache];
                     float4 x[kCache];
-                    gather_fan<LABELS, kCache>(a, ce, sold, d, x, l);
-                    eval_fan_first<LABELS, kCache>(cx0, ce, d, x, l, cL, best, bl);
+                    gather_fan<R, LABELS, kCache>(a, ce, sold, d, x, l);
+                    eval_fan_first<R, LABELS, kCache>(cx0, ce, d, x, l, cL, best, bl);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
-                    best_update<LABELS, kChunk>(a, v, x0, sold, best, bl);
+                    best_update<R, LABELS, kChunk>(a, v, x0, sold, best, bl);
                 }
                 const bool better = best < dv;
-                const float dn = better ? best : dv;
-                st_s<LABELS>(snew, v, dn, better ? bl : lv, local);
-                if (pp < tb) {
-                    const bool conv = dv < kInf && (dn == dv || fabsf(dn - dv) / dv < a.tol);
-                    notconv |= conv ? 0u : 1u;
-                }
+                const R dn = better ? best : dv;
+                st_s<R, LABELS>(snew, v, dn, better ? bl : lv, local);
+                if (pp < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             }
             upd += be - bb;
             if (!gb.sync(notconv, &any)) return;
             if (leader)
-                for (int r = i; r < lo; ++r) st_g(retire + r, k - 1, local);   // pushed out by the window
-            // Eq. lower_band.  V_lo may retire only after its second update
-            // (k > lo): from +inf that is automatic, and a warm start keeps the
-            // same causality, so the band never runs ahead of the front.
-            if (!any && k > lo) {
+                for (int r = i; r < lo; ++r) st_g(retire + r, k - 1, local);   // pushed out of the band
+            if (rule == BAND_FIXED_HALF) {
+                // the toplesets below the next iteration's band are final;
+                // after the last iteration every topleset is
+                const int inew = k >= kfix ? rho : max(lo, (k + 2) >> 1);
+                if (leader)
+                    for (int r = lo; r < inew; ++r) st_g(retire + r, k, local);
+                i = inew;
+            } else if (jacobi) {
+                // fixed point: no value of the (full) band changed
+                if (!any && j == rho - 1) {
+                    if (leader)
+                        for (int r = lo; r < rho; ++r) st_g(retire + r, k, local);
+                    i = rho;
+                } else {
+                    i = lo;
+                }
+            } else if (!any && k > lo) {
+                // Eq. lower_band.  V_lo may retire only after its second update
+                // (k > lo): from +inf that is automatic, and a warm start keeps
+                // the same causality, so the band never runs ahead of the front.
                 if (leader) st_g(retire + lo, k, local);
                 i = lo + 1;
             } else {
@@ -596,16 +646,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const void* sfin = (k & 1) ? sB : sA;
         for (long long p = g0; p < n; p += gsz) {
             const int v = a.perm[vo + p];
-            float df;
+            R df;
             int lf = 0;
-            ld_s<LABELS>(sfin, vo + (int)p, df, lf);
-            a.out_d[md.out_off + (v - vo)] = df;
+            ld_s<R, LABELS>(sfin, vo + (int)p, df, lf);
+            if (sizeof(R) == 8) a.out_d64[md.out_off + (v - vo)] = (double)df;
+            else a.out_d[md.out_off + (v - vo)] = (float)df;
             if (LABELS) a.out_l[md.out_off + (v - vo)] = lf;
         }
         if (leader) {
             a.state[b].iters = k;
             a.state[b].runstat = runstat;
             a.state[b].updates = upd;
+            a.state[b].t_end = wall_clock64();
         }
     }
 }
@@ -618,12 +670,19 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
         state[b].updates = 0;
         state[b].cert_rounds = 0;
         state[b].cert_rejected = 0;
+        state[b].t_begin = 0;
+        state[b].t_end = 0;
     }
+}
+
+template <typename R, bool LABELS, bool WARM, bool CACHE, bool RULES = false>
+const void* relax_fn() {
+    return reinterpret_cast<const void*>(&k_relax<R, LABELS, WARM, CACHE, RULES>);
 }
 
 }  // namespace
 
-hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, int g_run,
+hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, bool f64, int g_run,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_run_reset, dim3((p.B + 255) / 256), dim3(256), 0, st, w.ctrl, w.state, p.B);
     launch_barrier_reset(w, 2 * g_run, st);
@@ -631,11 +690,13 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.G = g_run;
     a.kmax_fixed = p.kmax_fixed;
     a.window = p.window;
-    a.tol = p.tol;
+    a.band_rule = p.band_rule;
+    a.certify = p.certify ? 1 : 0;
+    a.tol = p.band_rule == BAND_JACOBI ? 0.f : p.tol;
     a.mesh = w.mesh;
     a.state = w.state;
-    a.wg = w.wg_run;
-    a.glist = w.glist_run;
+    a.wg = f64 ? w.wg_run64 : w.wg_run;
+    a.glist = f64 ? w.glist_run64 : w.glist_run;
     a.S = p.S;
     a.upper = p.upper;
     a.xpost = w.cnt;
@@ -652,40 +713,58 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.bar = w.bar;
     a.N = p.N;
     a.out_d = p.out_d;
+    a.out_d64 = p.out_d64;
     a.out_l = p.out_l;
     void* args[] = {&a};
     const void* fn;
-    if (labels)
-        fn = cache ? reinterpret_cast<const void*>(&k_relax<true, false, true>)
-                   : reinterpret_cast<const void*>(&k_relax<true, false, false>);
+    const bool rules = p.band_rule != BAND_PAPER;
+    if (f64)
+        fn = rules ? relax_fn<double, false, false, false, true>() : relax_fn<double, false, false, false>();
+    else if (rules)       // the other band rules: uncached, read at run time
+        fn = labels ? relax_fn<float, true, false, false, true>()
+                    : (p.upper ? relax_fn<float, false, true, false, true>()
+                               : relax_fn<float, false, false, false, true>());
+    else if (labels)
+        fn = cache ? relax_fn<float, true, false, true>() : relax_fn<float, true, false, false>();
     else if (p.upper)
-        fn = cache ? reinterpret_cast<const void*>(&k_relax<false, true, true>)
-                   : reinterpret_cast<const void*>(&k_relax<false, true, false>);
+        fn = cache ? relax_fn<float, false, true, true>() : relax_fn<float, false, true, false>();
     else
-        fn = cache ? reinterpret_cast<const void*>(&k_relax<false, false, true>)
-                   : reinterpret_cast<const void*>(&k_relax<false, false, false>);
+        fn = cache ? relax_fn<float, false, false, true>() : relax_fn<float, false, false, false>();
     return hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
 }
 
+namespace {
+int blocks_per_cu(const void* fn) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess) return 0;
+    return nb;
+}
+}  // namespace
+
 // Co-resident workgroups of the relaxation kernels a plan may launch: the
 // labelled one, or (without labels) the plain and the warm-start one; with
-// `cache`, the register-caching variants instead of the uncached ones.
-int max_coop_blocks_run(int cus, bool labels, bool cache) {
-    int nb = 0, nw = 1 << 20;
-    hipError_t e;
-    if (labels) {
-        e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false, true>, kBlock, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<true, false, false>, kBlock, 0);
+// `cache`, the register-caching variants instead of the uncached ones; with
+// `rules` (a plan with another band rule), the run-time-rule variants.
+int max_coop_blocks_run(int cus, bool labels, bool cache, bool rules) {
+    int nb;
+    if (rules) {
+        nb = labels ? blocks_per_cu(relax_fn<float, true, false, false, true>())
+                    : std::min(blocks_per_cu(relax_fn<float, false, false, false, true>()),
+                               blocks_per_cu(relax_fn<float, false, true, false, true>()));
+    } else if (labels) {
+        nb = blocks_per_cu(cache ? relax_fn<float, true, false, true>() : relax_fn<float, true, false, false>());
     } else {
-        e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, true>, kBlock, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_relax<false, false, false>, kBlock, 0);
-        if (e == hipSuccess)
-            e = cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, true>, kBlock, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, k_relax<false, true, false>, kBlock, 0);
+        nb = std::min(
+            blocks_per_cu(cache ? relax_fn<float, false, false, true>() : relax_fn<float, false, false, false>()),
+            blocks_per_cu(cache ? relax_fn<float, false, true, true>() : relax_fn<float, false, true, false>()));
     }
-    nb = std::min(nb, nw);
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb * cus;
+    return std::max(nb, 1) * cus;
+}
+
+int max_coop_blocks_run64(int cus, bool rules) {
+    return std::max(blocks_per_cu(rules ? relax_fn<double, false, false, false, true>()
+                                        : relax_fn<double, false, false, false>()),
+                    1) * cus;
 }
 
 }  // namespace ptp

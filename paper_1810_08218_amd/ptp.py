@@ -6,8 +6,10 @@ library is missing or fails to load, every call raises; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -34,7 +36,11 @@ EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "
            "ptp_warm_features", "ptp_warm_predict", "ptp_run_warm", "ptp_batch_warm_features",
            "ptp_batch_warm_predict", "ptp_batch_run_warm", "ptp_mlp_params", "ptp_mlp_apply",
            "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step", "ptp_set_window",
-           "ptp_batch_set_window")
+           "ptp_batch_set_window", "ptp_run_f64", "ptp_batch_run_f64", "ptp_fps", "ptp_lloyd_step")
+
+BAND_PAPER = 0          # PTP_BAND_PAPER: Eq. upper_band / Eq. lower_band
+BAND_FIXED_HALF = 1     # PTP_BAND_FIXED_HALF: [floor((k+1)/2), k], 2 rho - 3 iterations
+BAND_JACOBI = 2         # PTP_BAND_JACOBI: every topleset until nothing changes
 
 MLP_PARAMS = 4481       # PTP_MLP_PARAMS
 
@@ -48,17 +54,19 @@ class PTPError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_float), ("max_iters", C.c_int32), ("window", C.c_int32),
                 ("want_labels", C.c_int32), ("workgroups", C.c_int32),
-                ("lds_bfs_max", C.c_int32)]
+                ("lds_bfs_max", C.c_int32), ("band_rule", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("n_toplesets", C.c_int32),
                 ("reachable", C.c_int32), ("workgroups", C.c_int32),
                 ("vertex_updates", C.c_int64), ("certify_rounds", C.c_int32),
-                ("certify_rejected", C.c_int32)]
+                ("certify_rejected", C.c_int32), ("ms_prepare", C.c_float), ("ms_run", C.c_float),
+                ("ms_mesh_begin", C.c_float), ("ms_mesh_end", C.c_float)]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (float(getattr(self, f)) if t is C.c_float else int(getattr(self, f)))
+                for f, t in self._fields_}
 
 
 class MeshDesc(C.Structure):
@@ -80,6 +88,17 @@ class Schedule(C.Structure):
 
 
 _lib = None
+
+# Plans and batches still open when the interpreter exits are destroyed by an
+# exit hook, while the HIP runtime is certainly still up (a destructor run
+# during interpreter teardown could call into a runtime already unloaded).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        obj.close()
 
 
 def load() -> C.CDLL:
@@ -150,6 +169,14 @@ def load() -> C.CDLL:
     for name in ("ptp_set_window", "ptp_batch_set_window"):
         getattr(lib, name).argtypes = [vp, C.c_int32]
         getattr(lib, name).restype = C.c_int
+    lib.ptp_run_f64.argtypes = [vp, vp, vp]
+    lib.ptp_run_f64.restype = C.c_int
+    lib.ptp_batch_run_f64.argtypes = [vp, vp, vp]
+    lib.ptp_batch_run_f64.restype = C.c_int
+    lib.ptp_fps.argtypes = [vp, vp, vp, vp, C.c_int32, vp, C.c_size_t, C.c_int32, vp, vp, vp, vp]
+    lib.ptp_fps.restype = C.c_int
+    lib.ptp_lloyd_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.ptp_lloyd_step.restype = C.c_int
     lib.ptp_mlp_params.argtypes = []
     lib.ptp_mlp_params.restype = C.c_int32
     lib.ptp_mlp_apply.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
@@ -194,25 +221,33 @@ class Plan:
     workspace tensor; all device memory is torch's."""
 
     def __init__(self, n: int, f: int, m: int, tol: float, max_iters: int = 0, window: int = 0,
-                 want_labels: bool = False, workgroups: int = 0, lds_bfs_max: int = 0):
+                 want_labels: bool = False, workgroups: int = 0, lds_bfs_max: int = 0,
+                 band_rule: int = BAND_PAPER):
         lib = load()
         self._lib = lib
         self.n, self.f, self.m = int(n), int(f), int(m)
         self.want_labels = bool(want_labels)
         opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)),
-                      int(workgroups), int(lds_bfs_max))
+                      int(workgroups), int(lds_bfs_max), int(band_rule))
         h = C.c_void_p()
         rc = lib.ptp_plan_create(C.byref(h), self.n, self.f, self.m, C.byref(opt))
         if rc != PTP_OK:
             raise PTPError(rc, "ptp_plan_create")
         self._h = h
         self._work = None
+        _live.add(self)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the host plan and drop the workspace (idempotent)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._lib.ptp_plan_destroy(h)
-            self._h = None
+        self._h = None
+        self._work = None
+        self._keep = None
+
+    def __del__(self):
+        self.close()
 
     def _err(self, rc, what):
         msg = self._lib.ptp_last_error(self._h)
@@ -260,6 +295,66 @@ class Plan:
         rc = self._lib.ptp_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
         if rc != PTP_OK:
             raise self._err(rc, "ptp_run")
+
+    def run_f64(self, dist, stream=None):
+        """The same iteration in float64: dist is a float64 [n] device tensor."""
+        import torch
+        _check_dev(dist, torch.float64, None, "dist")
+        if dist.numel() != self.n:
+            raise ValueError("dist must have n elements")
+        rc = self._lib.ptp_run_f64(self._h, _ptr(dist), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_run_f64")
+
+    def fps(self, V, F, S, n_initial: int, dist, radius=None, steps=None, warm: bool = False,
+            work=None, stream=None):
+        """Farthest point sampling: S (int32 [m] device, m = the plan's source
+        count) holds the first n_initial sources and receives the samples;
+        dist the final map; radius [m - n_initial] and steps int64
+        [2 (m - n_initial + 1)] optional device tensors.  Synchronises."""
+        import torch
+        _check_dev(V, torch.float32, (3,), "V")
+        _check_dev(F, torch.int32, (3,), "F")
+        _check_dev(S, torch.int32, None, "S")
+        _check_dev(dist, torch.float32, None, "dist")
+        if V.shape[0] != self.n or F.shape[0] != self.f or S.numel() != self.m:
+            raise ValueError("mesh sizes differ from the plan")
+        if dist.numel() != self.n:
+            raise ValueError("dist must have n elements")
+        if radius is not None:
+            _check_dev(radius, torch.float32, None, "radius")
+            if radius.numel() < self.m - n_initial:
+                raise ValueError("radius needs m - n_initial entries")
+        if steps is not None:
+            _check_dev(steps, torch.int64, None, "steps")
+            if steps.numel() < 2 * (self.m - n_initial + 1):
+                raise ValueError("steps needs 2 (m - n_initial + 1) entries")
+        if work is None:
+            work = self.workspace(V.device)
+        rc = self._lib.ptp_fps(self._h, _ptr(V), _ptr(F), _ptr(S), int(n_initial), _ptr(work),
+                               work.numel(), int(bool(warm)), _ptr(dist), _ptr(radius), _ptr(steps),
+                               _stream(stream))
+        self._keep = (V, F, S, work)
+        if rc != PTP_OK and rc != PTP_ENOCONV:
+            raise self._err(rc, "ptp_fps")
+        return rc
+
+    def lloyd_step(self, label, S_out, centroid=None, stream=None):
+        """One Lloyd step on the labels of the last run over the prepared mesh
+        and sources: S_out [m] (device int32) receives the new generators,
+        centroid (float64 [m, 4]) the centroids and cell areas."""
+        import torch
+        _check_dev(label, torch.int32, None, "label")
+        _check_dev(S_out, torch.int32, None, "S_out")
+        if label.numel() != self.n or S_out.numel() != self.m:
+            raise ValueError("sizes differ from the plan")
+        if centroid is not None:
+            _check_dev(centroid, torch.float64, (4,), "centroid")
+            if centroid.shape[0] != self.m:
+                raise ValueError("centroid must be [m, 4]")
+        rc = self._lib.ptp_lloyd_step(self._h, _ptr(label), _ptr(S_out), _ptr(centroid), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_lloyd_step")
 
     # -- learned warm start --------------------------------------------------
     def warm_features(self, stream=None):
@@ -343,12 +438,12 @@ class Solution:
 
 
 def solve(V, F, S, tol: float, labels: bool = False, max_iters: int = 0, window: int = 0,
-          workgroups: int = 0, stream=None) -> Solution:
+          workgroups: int = 0, band_rule: int = BAND_PAPER, stream=None) -> Solution:
     """Geodesic distances from the source set S on mesh (V, F): prepare + run
     + stats.  V float32 [n, 3], F int32 [f, 3], S int32 [m], all on the GPU."""
     import torch
     plan = Plan(V.shape[0], F.shape[0], S.numel(), tol, max_iters=max_iters, window=window,
-                want_labels=labels, workgroups=workgroups)
+                want_labels=labels, workgroups=workgroups, band_rule=band_rule)
     plan.prepare(V, F, S, stream=stream)
     dist = torch.empty(V.shape[0], dtype=torch.float32, device=V.device)
     lab = torch.empty(V.shape[0], dtype=torch.int32, device=V.device) if labels else None
@@ -394,7 +489,7 @@ class Batch:
     gets exactly the result a Plan would give it alone."""
 
     def __init__(self, descs, tol: float, max_iters: int = 0, window: int = 0,
-                 want_labels: bool = False, lds_bfs_max: int = 0):
+                 want_labels: bool = False, lds_bfs_max: int = 0, band_rule: int = BAND_PAPER):
         lib = load()
         self._lib = lib
         self.count = len(descs)
@@ -402,19 +497,26 @@ class Batch:
         self.out_len = max(int(d.out_off) + int(d.n_vertices) for d in descs)
         self.want_labels = bool(want_labels)
         opt = Options(float(tol), int(max_iters), int(window), int(bool(want_labels)), 0,
-                      int(lds_bfs_max))
+                      int(lds_bfs_max), int(band_rule))
         h = C.c_void_p()
         rc = lib.ptp_batch_create(C.byref(h), self._descs, self.count, C.byref(opt))
         if rc != PTP_OK:
             raise PTPError(rc, "ptp_batch_create")
         self._h = h
         self._work = None
+        _live.add(self)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the host batch and drop the workspace (idempotent)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._lib.ptp_batch_destroy(h)
-            self._h = None
+        self._h = None
+        self._work = None
+        self._keep = None
+
+    def __del__(self):
+        self.close()
 
     def _err(self, rc, what):
         msg = self._lib.ptp_batch_last_error(self._h)
@@ -458,6 +560,15 @@ class Batch:
         rc = self._lib.ptp_batch_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
         if rc != PTP_OK:
             raise self._err(rc, "ptp_batch_run")
+
+    def run_f64(self, dist, stream=None):
+        import torch
+        _check_dev(dist, torch.float64, None, "dist")
+        if dist.numel() < self.out_len:
+            raise ValueError("dist too short for the batch outputs")
+        rc = self._lib.ptp_batch_run_f64(self._h, _ptr(dist), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_run_f64")
 
     def warm_features(self, stream=None):
         """Network inputs X [out_len, 3] and scale [out_len] as device tensors."""

@@ -6,6 +6,8 @@ changes the schedule, never the result); against the FP64 oracle the same
 parity bar as the single-mesh tests; results do not depend on the work
 distribution (schedules, autotuning); graph replays equal the eager run.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -217,30 +219,52 @@ def test_graph_replay_matches_eager(cuda):
         _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays
 
 
+BATCH_SAMPLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "batch_largest_oracle_samples.npz")
+
+
 def test_full_uneven_batch_512(cuda):
     """The 512-mesh workload (jittered grids of side 32..1024 and tori of
-    2^k x 2^(k-1), k = 5..10, 1-4 sources each; 71M vertices) in one launch:
-    every mesh converges, sources are 0, all vertices reached; the smallest
-    meshes against the oracle and against single-mesh runs."""
+    2^k x 2^(k-1), k = 5..10, 1-4 sources each; 71M vertices) in one launch
+    with the schedule the benchmark times: every mesh converges and equals its
+    own single-mesh plan bit for bit (distances, K, U); the largest grid and
+    the largest torus match stored oracle samples (written by
+    tests/golden/make_oracle_samples.py, which calls only the oracle) with the
+    oracle's schedule; the 12 smallest meshes match the oracle in full."""
     import torch
+    from paper_1810_08218_amd import autotune
     meshes = I.batch_meshes(512)
     V, F, S, descs, out_len = P.concat(meshes)
     say(f"[batch512] n={V.shape[0]} f={F.shape[0]} m={S.shape[0]}")
     dV, dF, dS = (torch.from_numpy(x).cuda() for x in (V, F, S))
     del V, F
     b = P.Batch(descs, 1e-4)
+    b.set_schedule(**autotune.BATCH512_SCHEDULE)
     b.prepare(dV, dF, dS)
     dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
     b.run(dist)
     rc, stats, status = b.stats()
     say(f"  rc {rc} K max {max(s['iterations'] for s in stats)} rho max "
-        f"{max(s['n_toplesets'] for s in stats)} U {sum(s['vertex_updates'] for s in stats)}")
+        f"{max(s['n_toplesets'] for s in stats)} U {sum(s['vertex_updates'] for s in stats)} "
+        f"run {stats[0]['ms_run']:.1f} ms")
     assert rc == P.PTP_OK and all(s == P.PTP_OK for s in status)
     d = dist.cpu().numpy()
     assert np.isfinite(d).all()
     sl = _slices(descs)
     for m, (a, z) in zip(meshes, sl):
         assert (d[a:z][m.S] == 0).all()
+    ref = np.load(BATCH_SAMPLES)
+    for t in (int(x) for x in ref["ts"]):
+        a, z = sl[t]
+        idx = ref[f"t{t}_idx"]
+        mx, mean = rel_errors(d[a:z][idx], ref[f"t{t}_dist"], np.nonzero(np.isin(idx, meshes[t].S))[0])
+        say(f"  {meshes[t].name} (t={t}, n={meshes[t].n}): K {stats[t]['iterations']}/"
+            f"{int(ref[f't{t}_iterations'])} U {stats[t]['vertex_updates']}/{int(ref[f't{t}_updates'])} "
+            f"sampled max rel {mx:.2e} mean {mean:.2e}")
+        assert stats[t]["n_toplesets"] == int(ref[f"t{t}_rho"])
+        assert stats[t]["iterations"] == int(ref[f"t{t}_iterations"])
+        assert stats[t]["vertex_updates"] == int(ref[f"t{t}_updates"])
+        assert mx <= REL_TOL
     order = np.argsort([m.n for m in meshes])[:12]
     for t in order:
         m = meshes[t]
@@ -249,5 +273,19 @@ def test_full_uneven_batch_512(cuda):
         mx, _ = rel_errors(d[a:z], o.dist, m.S)
         assert (stats[t]["iterations"], stats[t]["vertex_updates"]) == (o.iterations, o.updates)
         assert mx <= REL_TOL, m.name
-        g = gpu_run(m, 1e-4, want_order=False)
-        assert np.array_equal(d[a:z], g.dist), m.name
+    # every mesh against its own plan: one plan per mesh, the batch's rows
+    differ = []
+    for t, m in enumerate(meshes):
+        a, z = sl[t]
+        plan = P.Plan(m.n, m.f, m.m, 1e-4)
+        d1 = torch.empty(m.n, dtype=torch.float32, device="cuda")
+        vo, fo, so = int(descs[t].v_off), int(descs[t].f_off), int(descs[t].s_off)
+        plan.prepare(dV[vo:vo + m.n], dF[fo:fo + m.f], dS[so:so + m.m])
+        plan.run(d1)
+        st = plan.stats()
+        same = np.array_equal(d1.cpu().numpy(), d[a:z])
+        same &= (st["iterations"], st["vertex_updates"]) == (stats[t]["iterations"], stats[t]["vertex_updates"])
+        if not same:
+            differ.append(t)
+    say(f"  meshes differing from their single plan: {differ}")
+    assert differ == []
