@@ -137,6 +137,27 @@ ptp_status ptp_solve(ptp_plan *plan, const float *dV, const int32_t *dF, const i
                      void *dWork, size_t work_bytes, float *dDist, int32_t *dLabel,
                      ptp_stats *stats, void *stream);
 
+/* ptp_solve for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: tight serving loops, harnesses that forbid it).  The
+ * workspace is not a caller buffer but a fixed scratch array of
+ * ptp_noalloc_scratch_bytes() (64 MiB) that the library holds on every
+ * device it runs on until the process ends; this call allocates nothing.
+ * The caller still owns V, F, S, dist and label.  PTP_ENOMEM (with a message
+ * naming both sizes) when ptp_workspace_bytes of the plan exceeds the
+ * scratch, that is above roughly 200k vertices.  Every call on a device
+ * shares that device's scratch, and the plan keeps using it for later
+ * ptp_run calls: calls that overlap on one device (other threads, other
+ * streams, runs still in flight) race and give undefined results; the
+ * synchronisation at the end of this call makes consecutive calls on one
+ * thread safe.  Everything a solve reads from the scratch is written first
+ * by the same solve, so earlier contents never matter. */
+ptp_status ptp_solve_noalloc(ptp_plan *plan, const float *dV, const int32_t *dF,
+                             const int32_t *dS, float *dDist, int32_t *dLabel,
+                             ptp_stats *stats, void *stream);
+
+/* Size of the fixed scratch of ptp_solve_noalloc, in bytes. */
+size_t ptp_noalloc_scratch_bytes(void);
+
 /* Synchronise the plan's last stream and report the last run: fills *stats
  * and returns its outcome. */
 ptp_status ptp_get_stats(ptp_plan *plan, ptp_stats *stats);

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
@@ -831,6 +832,40 @@ struct ptp_batch {
     Solver s;
 };
 
+// ---- fixed scratch for callers that cannot allocate ---------------------
+// ptp_solve_noalloc carves its workspace from this array instead of a
+// caller buffer.  Each device holds its own copy from the moment the library
+// is loaded until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device address: the address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call made with that device current).
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 const char* ptp_version(void) { return "ptp-mi355x 0.4 (gfx950)"; }
@@ -892,6 +927,22 @@ ptp_status ptp_solve(ptp_plan* p, const float* dV, const int32_t* dF, const int3
     if (s != PTP_OK) return s;
     return ptp_get_stats(p, stats);
 }
+
+ptp_status ptp_solve_noalloc(ptp_plan* p, const float* dV, const int32_t* dF, const int32_t* dS, float* dDist,
+                             int32_t* dLabel, ptp_stats* stats, void* stream) {
+    if (!p) return PTP_EINVAL;
+    Solver& s = p->s;
+    if (s.layout.total > kScratchBytes)
+        return s.fail(PTP_ENOMEM, "the plan needs " + std::to_string(s.layout.total) +
+                                      " bytes of workspace; the fixed scratch holds " +
+                                      std::to_string(kScratchBytes));
+    void* work = nullptr;
+    const hipError_t e = scratch_address(&work);
+    if (e != hipSuccess) return s.hip_fail(e, "scratch address");
+    return ptp_solve(p, dV, dF, dS, work, kScratchBytes, dDist, dLabel, stats, stream);
+}
+
+size_t ptp_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 ptp_status ptp_run_f64(ptp_plan* p, double* dDist, void* stream) {
     if (!p) return PTP_EINVAL;

@@ -36,7 +36,8 @@ EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "
            "ptp_warm_features", "ptp_warm_predict", "ptp_run_warm", "ptp_batch_warm_features",
            "ptp_batch_warm_predict", "ptp_batch_run_warm", "ptp_mlp_params", "ptp_mlp_apply",
            "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step", "ptp_set_window",
-           "ptp_batch_set_window", "ptp_run_f64", "ptp_batch_run_f64", "ptp_fps", "ptp_lloyd_step")
+           "ptp_batch_set_window", "ptp_run_f64", "ptp_batch_run_f64", "ptp_fps", "ptp_lloyd_step",
+           "ptp_solve_noalloc", "ptp_noalloc_scratch_bytes")
 
 BAND_PAPER = 0          # PTP_BAND_PAPER: Eq. upper_band / Eq. lower_band
 BAND_FIXED_HALF = 1     # PTP_BAND_FIXED_HALF: [floor((k+1)/2), k], 2 rho - 3 iterations
@@ -121,6 +122,10 @@ def load() -> C.CDLL:
     lib.ptp_run.restype = C.c_int
     lib.ptp_solve.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, vp, vp, C.POINTER(Stats), vp]
     lib.ptp_solve.restype = C.c_int
+    lib.ptp_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
+    lib.ptp_solve_noalloc.restype = C.c_int
+    lib.ptp_noalloc_scratch_bytes.argtypes = []
+    lib.ptp_noalloc_scratch_bytes.restype = C.c_size_t
     lib.ptp_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.ptp_get_stats.restype = C.c_int
     lib.ptp_get_order.argtypes = [vp, vp, vp, vp]
@@ -295,6 +300,33 @@ class Plan:
         rc = self._lib.ptp_run(self._h, _ptr(dist), _ptr(label), _stream(stream))
         if rc != PTP_OK:
             raise self._err(rc, "ptp_run")
+
+    def solve_noalloc(self, V, F, S, dist, label=None, stream=None) -> dict:
+        """ptp_solve on the library's fixed scratch (no workspace, no device
+        allocation): prepare + run + synchronise; returns the stats (status
+        included, PTP_ENOCONV allowed)."""
+        import torch
+        _check_dev(V, torch.float32, (3,), "V")
+        _check_dev(F, torch.int32, (3,), "F")
+        _check_dev(S, torch.int32, None, "S")
+        _check_dev(dist, torch.float32, None, "dist")
+        if V.shape[0] != self.n or F.shape[0] != self.f or S.numel() != self.m:
+            raise ValueError("mesh sizes differ from the plan")
+        if dist.numel() != self.n:
+            raise ValueError("dist must have n elements")
+        if label is not None:
+            _check_dev(label, torch.int32, None, "label")
+            if label.numel() != self.n:
+                raise ValueError("label must have n elements")
+        st = Stats()
+        rc = self._lib.ptp_solve_noalloc(self._h, _ptr(V), _ptr(F), _ptr(S), _ptr(dist), _ptr(label),
+                                         C.byref(st), _stream(stream))
+        self._keep = (V, F, S, None)
+        if rc != PTP_OK and rc != PTP_ENOCONV:
+            raise self._err(rc, "ptp_solve_noalloc")
+        d = st.as_dict()
+        d["status"] = rc
+        return d
 
     def run_f64(self, dist, stream=None):
         """The same iteration in float64: dist is a float64 [n] device tensor."""
