@@ -117,6 +117,7 @@ def _declare(lib):
     lib.ptpo_fixed_point.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, C.c_int,
                                      dptr, iptr, C.POINTER(C.c_int)]
     lib.ptpo_fast_marching.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, dptr]
+    lib.ptpo_labels_from_map.argtypes = [C.c_int, C.c_int, dptr, iptr, C.c_int, iptr, dptr, iptr, iptr]
 
 
 def _prep(V, F, S):
@@ -266,6 +267,23 @@ def fixed_point(V, F, S, max_sweeps=100000, lib=None):
     if rc != OK:
         raise ValueError(f"ptpo_fixed_point failed: {rc}")
     return dist, label, sw.value
+
+
+def labels_from_map(V, F, S, dist, lib=None):
+    """Voronoi labels of a distance map (caller order): every vertex takes the
+    index in S of the source at the root of its chain of parents, the parent
+    being the vertex its value comes from under its best triangle (only
+    parents before it in (distance, id) order).  Returns (label, parent);
+    parent is the vertex itself for a source, -1 where there is none."""
+    X, F, S = _prep(V, F, S)
+    n = X.shape[0]
+    d = np.ascontiguousarray(dist, dtype=np.float64)
+    label = np.empty(n, np.int32)
+    parent = np.empty(n, np.int32)
+    rc = _L(lib).ptpo_labels_from_map(n, F.shape[0], X, F, S.shape[0], S, d, label, parent)
+    if rc != OK:
+        raise ValueError(f"ptpo_labels_from_map failed: {rc}")
+    return label, parent
 
 
 def fast_marching(V, F, S, lib=None):

@@ -28,6 +28,9 @@
  *                       the previous map this way).
  *   ptpo_fixed_point    plain Jacobi over all vertices until nothing changes:
  *                       the fixed point d* that PTP approximates.
+ *   ptpo_labels_from_map  Voronoi labels (Sec. 5.3) of a distance map: each
+ *                       vertex takes the source at the root of its chain of
+ *                       parents (the input its value comes from).
  *   ptpo_fast_marching  sequential Fast Marching (Sec. 3.2) with the same
  *                       local update and accepted-only inputs.
  *
@@ -189,8 +192,10 @@ int ptpo_toplesets(int n, int nf, const int *F, int m, const int *S,
  * condition); otherwise, and when either input is missing, the update comes
  * from the edges, min_i (d_i + |x_i - x0|).
  *
- * Labels: an edge update takes the label of its vertex; the planar solution
- * the label of its smaller input (a tie takes the smaller label).        */
+ * *lab_out names where the value comes from: an edge update gives the tag
+ * (l1 or l2) of its vertex, a planar value that of its smaller input; equal
+ * candidates give the smaller tag.  With vertex ids as tags this is the
+ * vertex the value comes from (the parent of the Voronoi labels below). */
 static double local_update(const double *x0, const double *x1, const double *x2,
                            double d1, double d2, int l1, int l2, int *lab_out)
 {
@@ -260,14 +265,12 @@ double ptpo_local_update(const double *x0, const double *x1, const double *x2,
     return p;
 }
 
-/* Best update of vertex v over its incident triangles, reading dist/lab.
- * Lexicographic (value, label) minimum. */
-static void best_update(int v, const incidence *inc, const int *F, const double *X,
-                        const double *dist, const int *lab, double *best, int *blab,
-                        const unsigned char *usable)
+/* Best update of vertex v over its incident triangles, reading dist; with
+ * `usable`, an input not marked usable counts as +inf. */
+static double best_update(int v, const incidence *inc, const int *F, const double *X,
+                          const double *dist, const unsigned char *usable)
 {
     double bu = INFINITY;
-    int bl = -1;
     for (int e = inc->start[v]; e < inc->start[v + 1]; ++e) {
         const int *f = F + 3 * inc->face[e];
         int a, b;
@@ -281,14 +284,101 @@ static void best_update(int v, const incidence *inc, const int *F, const double 
         }
         int l;
         double u = local_update(X + 3 * (size_t)v, X + 3 * (size_t)a, X + 3 * (size_t)b,
-                                da, db, lab[a], lab[b], &l);
-        if (u < bu || (u == bu && isfinite(u) && l < bl)) {
-            bu = u;
-            bl = l;
+                                da, db, a, b, &l);
+        if (u < bu) bu = u;
+    }
+    return bu;
+}
+
+/* ------------------------------------------------------------------ */
+/* Voronoi labels from the final map                                   */
+/* ------------------------------------------------------------------ */
+
+/* The paper splits the mesh into the regions of the sources (Sec. 5.3)
+ * without saying how a vertex is assigned to one; the reading here makes
+ * the label a function of the final distance map.  The parent of a
+ * reachable vertex v that is not a source is the vertex its value comes
+ * from under its best triangle: over the incident triangles the smallest
+ * (update, giver id), where the giver of a planar value is its smaller
+ * input (equal inputs: the smaller id) and that of an edge update the
+ * edge's other end (equal updates: the smaller id).  Only givers that come
+ * before v in (distance, id) order count, so the parents form a forest
+ * whose roots are the sources.  A vertex takes the index in S of its root;
+ * unreachable vertices, and a vertex with no giver before it (possible only
+ * on degenerate input), get -1.  Vertices are labelled in (distance, id)
+ * order, so a parent is labelled before its children. */
+typedef struct {
+    double d;
+    int v;
+} dist_id;
+
+static int cmp_dist_id(const void *pa, const void *pb)
+{
+    const dist_id *a = (const dist_id *)pa, *b = (const dist_id *)pb;
+    if (a->d < b->d) return -1;
+    if (a->d > b->d) return 1;
+    return (a->v > b->v) - (a->v < b->v);
+}
+
+static int label_from_map(int n, const incidence *inc, const int *F, const double *X, int m,
+                          const int *S, const double *dist, int *label, int *parent)
+{
+    dist_id *ord = (dist_id *)malloc(sizeof(dist_id) * ((size_t)n + 1));
+    if (!ord) return PTPO_ENOMEM;
+    int cnt = 0;
+    for (int v = 0; v < n; ++v) {
+        label[v] = -1;
+        if (parent) parent[v] = -1;
+        if (isfinite(dist[v])) {
+            ord[cnt].d = dist[v];
+            ord[cnt].v = v;
+            cnt++;
         }
     }
-    *best = bu;
-    *blab = bl;
+    for (int a = 0; a < m; ++a) {
+        label[S[a]] = a;
+        if (parent) parent[S[a]] = S[a];
+    }
+    qsort(ord, (size_t)cnt, sizeof(dist_id), cmp_dist_id);
+    for (int q = 0; q < cnt; ++q) {
+        const int v = ord[q].v;
+        if (label[v] >= 0) continue;                     /* a source */
+        double bu = INFINITY;
+        int bg = -1;
+        for (int e = inc->start[v]; e < inc->start[v + 1]; ++e) {
+            const int *f = F + 3 * inc->face[e];
+            int a, b;
+            if (f[0] == v) { a = f[1]; b = f[2]; }
+            else if (f[1] == v) { a = f[2]; b = f[0]; }
+            else { a = f[0]; b = f[1]; }
+            int g;
+            double u = local_update(X + 3 * (size_t)v, X + 3 * (size_t)a, X + 3 * (size_t)b,
+                                    dist[a], dist[b], a, b, &g);
+            if (!isfinite(u)) continue;
+            if (!(dist[g] < dist[v] || (dist[g] == dist[v] && g < v))) continue;
+            if (u < bu || (u == bu && g < bg)) {
+                bu = u;
+                bg = g;
+            }
+        }
+        if (parent) parent[v] = bg;
+        label[v] = bg >= 0 ? label[bg] : -1;
+    }
+    free(ord);
+    return PTPO_OK;
+}
+
+int ptpo_labels_from_map(int n, int nf, const double *X, const int *F, int m, const int *S,
+                         const double *dist, int *label, int *parent)
+{
+    int rc = check_mesh(n, nf, F, m, S);
+    if (rc) return rc;
+    incidence inc;
+    rc = build_incidence(n, nf, F, &inc);
+    if (rc) return rc;
+    rc = label_from_map(n, &inc, F, X, m, S, dist, label, parent);
+    free_incidence(&inc);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */
@@ -353,9 +443,7 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
     int *offsets = (int *)malloc(sizeof(int) * ((size_t)n + 2));
     double *dold = (double *)malloc(sizeof(double) * (size_t)n);
     double *dnew = (double *)malloc(sizeof(double) * (size_t)n);
-    int *lold = (int *)malloc(sizeof(int) * (size_t)n);
-    int *lnew = (int *)malloc(sizeof(int) * (size_t)n);
-    if (!level || !order || !offsets || !dold || !dnew || !lold || !lnew) {
+    if (!level || !order || !offsets || !dold || !dnew) {
         rc = PTPO_ENOMEM;
         goto out;
     }
@@ -363,14 +451,8 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
     rc = toplesets_with(&inc, F, m, S, level, order, offsets, &rho);
     if (rc) goto out;
 
-    for (int v = 0; v < n; ++v) {
-        dold[v] = INFINITY;
-        lold[v] = -1;
-    }
-    for (int a = 0; a < m; ++a) {
-        dold[S[a]] = 0.0;
-        lold[S[a]] = a;
-    }
+    for (int v = 0; v < n; ++v) dold[v] = INFINITY;
+    for (int a = 0; a < m; ++a) dold[S[a]] = 0.0;
     if (upper) {
         /* Warm start.  Every reachable non-source vertex starts from the
          * caller's bound (negative or NaN: no bound).  Certification: a vertex
@@ -388,9 +470,7 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
             for (int q = 0; q < n; ++q) {
                 int v = order[q];
                 if (level[v] <= 0 || !isfinite(dold[v])) continue;
-                double bu;
-                int bl;
-                best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+                const double bu = best_update(v, &inc, F, X, dold, NULL);
                 if (dold[v] < bu) {
                     dold[v] = INFINITY;
                     rejected++;
@@ -419,7 +499,6 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
     int i = 1, k = 0;
     long long U = 0;
     memcpy(dnew, dold, sizeof(double) * (size_t)n);
-    memcpy(lnew, lold, sizeof(int) * (size_t)n);
     while (i < rho && k < kmax) {
         k += 1;
         int j = k < rho ? k : rho - 1;                   /* Eq. upper_band */
@@ -452,16 +531,8 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
 #pragma omp parallel for schedule(static)
         for (int q = qb; q < qe; ++q) {
             int v = order[q];
-            double bu;
-            int bl;
-            best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
-            if (bu < dold[v]) {
-                dnew[v] = bu;
-                lnew[v] = bl;
-            } else {
-                dnew[v] = dold[v];
-                lnew[v] = lold[v];
-            }
+            const double bu = best_update(v, &inc, F, X, dold, NULL);
+            dnew[v] = bu < dold[v] ? bu : dold[v];
         }
         U += qe - qb;
         if (trace_lo && k < trace_len) trace_lo[k] = lo;
@@ -515,15 +586,17 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
         for (int q = qb; q < qe; ++q) {
             int v = order[q];
             dold[v] = dnew[v];
-            lold[v] = lnew[v];
         }
     }
     if (i < rho) rc = PTPO_ENOCONV;
     int reach = 0;
     for (int v = 0; v < n; ++v) {
         dist[v] = dold[v];
-        if (label) label[v] = lold[v];
         if (isfinite(dold[v])) reach++;
+    }
+    if (label) {
+        const int lrc = label_from_map(n, &inc, F, X, m, S, dist, label, NULL);
+        if (lrc) rc = lrc;
     }
     if (st) {
         st->iterations = k;
@@ -533,7 +606,7 @@ static int run_core(int n, int nf, const double *X, const int *F, int m, const i
     }
 out:
     free(level); free(order); free(offsets);
-    free(dold); free(dnew); free(lold); free(lnew);
+    free(dold); free(dnew);
     free_incidence(&inc);
     return rc;
 }
@@ -587,20 +660,14 @@ int ptpo_fixed_point(int n, int nf, const double *X, const int *F, int m, const 
     rc = build_incidence(n, nf, F, &inc);
     if (rc) return rc;
     double *dold = (double *)malloc(sizeof(double) * (size_t)n);
-    int *lold = (int *)malloc(sizeof(int) * (size_t)n);
     unsigned char *is_src = (unsigned char *)calloc((size_t)n, 1);
-    int *lab = label ? label : (int *)malloc(sizeof(int) * (size_t)n);
-    if (!dold || !lold || !is_src || !lab) {
+    if (!dold || !is_src) {
         rc = PTPO_ENOMEM;
         goto out;
     }
-    for (int v = 0; v < n; ++v) {
-        dist[v] = INFINITY;
-        lab[v] = -1;
-    }
+    for (int v = 0; v < n; ++v) dist[v] = INFINITY;
     for (int a = 0; a < m; ++a) {
         dist[S[a]] = 0.0;
-        lab[S[a]] = a;
         is_src[S[a]] = 1;
     }
     int sweeps = 0;
@@ -608,16 +675,12 @@ int ptpo_fixed_point(int n, int nf, const double *X, const int *F, int m, const 
     while (sweeps < max_sweeps) {
         sweeps++;
         memcpy(dold, dist, sizeof(double) * (size_t)n);
-        memcpy(lold, lab, sizeof(int) * (size_t)n);
         int changed = 0;
         for (int v = 0; v < n; ++v) {
             if (is_src[v]) continue;
-            double bu;
-            int bl;
-            best_update(v, &inc, F, X, dold, lold, &bu, &bl, NULL);
+            const double bu = best_update(v, &inc, F, X, dold, NULL);
             if (bu < dold[v]) {
                 dist[v] = bu;
-                lab[v] = bl;
                 changed = 1;
             }
         }
@@ -627,9 +690,12 @@ int ptpo_fixed_point(int n, int nf, const double *X, const int *F, int m, const 
         }
     }
     if (sweeps_out) *sweeps_out = sweeps;
+    if (label) {
+        const int lrc = label_from_map(n, &inc, F, X, m, S, dist, label, NULL);
+        if (lrc) rc = lrc;
+    }
 out:
-    free(dold); free(lold); free(is_src);
-    if (!label) free(lab);
+    free(dold); free(is_src);
     free_incidence(&inc);
     return rc;
 }
@@ -682,15 +748,11 @@ int ptpo_fast_marching(int n, int nf, const double *X, const int *F, int m, cons
     size_t cap = (size_t)n + 6 * (size_t)nf + 16;
     heap_item *h = (heap_item *)malloc(sizeof(heap_item) * cap);
     unsigned char *acc = (unsigned char *)calloc((size_t)n, 1);
-    int *lab = (int *)malloc(sizeof(int) * (size_t)n);
-    if (!h || !acc || !lab) {
+    if (!h || !acc) {
         rc = PTPO_ENOMEM;
         goto out;
     }
-    for (int v = 0; v < n; ++v) {
-        dist[v] = INFINITY;
-        lab[v] = 0;
-    }
+    for (int v = 0; v < n; ++v) dist[v] = INFINITY;
     int size = 0;
     for (int a = 0; a < m; ++a) {
         dist[S[a]] = 0.0;
@@ -706,9 +768,7 @@ int ptpo_fast_marching(int n, int nf, const double *X, const int *F, int m, cons
             for (int c = 0; c < 3; ++c) {
                 int u = f[c];
                 if (acc[u]) continue;
-                double bu;
-                int bl;
-                best_update(u, &inc, F, X, dist, lab, &bu, &bl, acc);
+                const double bu = best_update(u, &inc, F, X, dist, acc);
                 if (bu < dist[u]) {
                     dist[u] = bu;
                     if ((size_t)size >= cap) { rc = PTPO_ENOMEM; goto out; }
@@ -718,7 +778,7 @@ int ptpo_fast_marching(int n, int nf, const double *X, const int *F, int m, cons
         }
     }
 out:
-    free(h); free(acc); free(lab);
+    free(h); free(acc);
     free_incidence(&inc);
     return rc;
 }

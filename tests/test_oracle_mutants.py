@@ -34,6 +34,8 @@ MUTANTS = {
                                         "lo = k / 2;"),
     "fixed band runs 2 rho - 1 iterations": ("const int kfix = 2 * rho - 3 > 1 ? 2 * rho - 3 : 1;",
                                              "const int kfix = 2 * rho - 1 > 1 ? 2 * rho - 1 : 1;"),
+    "parent tie to the larger id": ("if (u < bu || (u == bu && g < bg)) {", "if (u < bu || (u == bu && g > bg)) {"),
+    "parent from the first triangle": ("if (u < bu || (u == bu && g < bg)) {", "if (bg < 0) {"),
     "replay drops a topleset in its retiring iteration": (
         "while (lo < rho && replay[lo] >= 0 && replay[lo] < k) lo++;",
         "while (lo < rho && replay[lo] >= 0 && replay[lo] <= k) lo++;"),
@@ -131,7 +133,17 @@ def _battery(lib) -> list:
                 return False
         return True
 
+    mt = I.batch_mesh(263)
+
+    def parents():
+        from test_oracle_ptp import _brute_parents
+        r = O.run(mt.V, mt.F, mt.S, 1e-4, lib=lib)
+        lab, par = O.labels_from_map(mt.V, mt.F, mt.S, r.dist, lib=lib)
+        bp, bl = _brute_parents(mt.V, mt.F, mt.S, r.dist)
+        return np.array_equal(par, bp) and np.array_equal(lab, bl) and np.array_equal(r.label, lab)
+
     check("closed forms", closed_forms)
+    check("parents", parents)
     check("ladder schedules", ladder)
     check("replay", replay)
     check("plane wave", plane_wave)

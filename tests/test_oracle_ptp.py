@@ -201,3 +201,63 @@ def test_unreachable_vertices_stay_infinite():
     r = O.run(V2, F2, np.array([0], np.int32), 1e-6)
     assert np.isinf(r.dist[64:]).all() and (r.label[64:] == -1).all()
     assert np.isfinite(r.dist[:64]).all()
+
+
+def _brute_parents(V, F, S, dist):
+    """Parents by brute force: every incident triangle of every vertex is
+    evaluated under the map, with the vertex its value comes from; the
+    parent is the smallest (update, giver) among givers before the vertex in
+    (distance, id) order.  The giver is found by evaluating the triangle with
+    its two inputs in both orders: if both name the same input it is that
+    one, otherwise the two candidates tie and the smaller id gives.  Labels
+    follow the parents down to the sources."""
+    n = len(V)
+    X = np.asarray(V, np.float64)
+    best = [(np.inf, -1)] * n
+    for f in np.asarray(F):
+        for c in range(3):
+            v, a, b = int(f[c]), int(f[(c + 1) % 3]), int(f[(c + 2) % 3])
+            u, who = O.local_update(X[v], X[a], X[b], dist[a], dist[b])
+            if not np.isfinite(u):
+                continue
+            _, who_sw = O.local_update(X[v], X[b], X[a], dist[b], dist[a])
+            g1 = a if who == 1 else b
+            g2 = b if who_sw == 1 else a
+            g = g1 if g1 == g2 else min(a, b)
+            if not (dist[g] < dist[v] or (dist[g] == dist[v] and g < v)):
+                continue
+            if (u, g) < best[v]:
+                best[v] = (u, g)
+    parent = np.array([g for _, g in best], np.int32)
+    label = np.full(n, -1, np.int32)
+    parent[np.asarray(S)] = np.asarray(S)
+    for i, s in enumerate(S):
+        label[s] = i
+    for v in sorted(range(n), key=lambda x: (dist[x], x)):
+        if label[v] < 0 and np.isfinite(dist[v]) and parent[v] >= 0:
+            label[v] = label[parent[v]]
+    return parent, label
+
+
+@pytest.mark.parametrize("mesh", [I.bumpy_icosphere(level=3, seed=5, n_sources=7), I.batch_mesh(263),
+                                  I.flat_grid(12)], ids=lambda m: m.name)
+def test_labels_from_map_brute_force(mesh):
+    """The parents and labels of the final map equal a brute-force
+    evaluation, form a forest rooted at the sources with every parent a
+    neighbour before its child in (distance, id) order."""
+    S = mesh.S if mesh.m > 1 else np.array([0, mesh.n - 1, mesh.n // 2 + 3], np.int32)
+    r = O.run(mesh.V, mesh.F, S, 1e-4)
+    lab, par = O.labels_from_map(mesh.V, mesh.F, S, r.dist)
+    bp, bl = _brute_parents(mesh.V, mesh.F, S, r.dist)
+    assert np.array_equal(par, bp) and np.array_equal(lab, bl) and np.array_equal(r.label, lab)
+    reach = np.isfinite(r.dist)
+    assert (par[reach] >= 0).all() and (lab[reach] >= 0).all() and (lab[~reach] == -1).all()
+    nb = {(int(a), int(b)) for f in mesh.F for a in f for b in f if a != b}
+    for v in np.nonzero(reach)[0]:
+        p = int(par[v])
+        if v in set(S.tolist()):
+            assert p == v
+            continue
+        assert (int(v), p) in nb
+        assert (r.dist[p], p) < (r.dist[v], v)
+        assert lab[v] == lab[p]
