@@ -29,8 +29,15 @@
  *   F      int32   [f][3]   triangle vertex ids, 0 <= id < n.
  *   S      int32   [m]      source vertex ids, distinct, 0 <= id < n, m >= 1.
  *   dist   float32 [n]      distance to S; +inf where no path exists.
- *   label  int32   [n]      index into S of the source whose front reached
- *                           the vertex (Voronoi label); -1 where unreachable.
+ *   label  int32   [n]      Voronoi label (Sec. 5.3): index into S of the
+ *                           source at the root of the vertex's chain of
+ *                           parents in the final map, the parent being the
+ *                           vertex its value comes from under its best
+ *                           triangle (the smaller input of a planar value,
+ *                           the other end of an edge update; equal candidates:
+ *                           the smaller vertex id; only parents before the
+ *                           vertex in (distance, id) order); -1 where
+ *                           unreachable.
  */
 #ifndef PTP_MI355X_H
 #define PTP_MI355X_H
@@ -212,6 +219,14 @@ ptp_status ptp_fps(ptp_plan *plan, const float *dV, const int32_t *dF, int32_t *
 ptp_status ptp_lloyd_step(ptp_plan *plan, const int32_t *dLabel, int32_t *dSout, double *dCentroid,
                           void *stream);
 
+/* The parents behind the labels of the last run, which must have computed
+ * labels (PTP_EINVAL otherwise): parent[v] = the caller id of the vertex
+ * v's final value comes from (see `label` above), v itself for a source, -1
+ * where unreachable.  Following parents from any vertex descends the final
+ * map to its nearest source along a chain of vertices (a discrete geodesic
+ * path, Sec. 5.3).  dParent int32 [n] device, caller order.  Asynchronous. */
+ptp_status ptp_get_parents(ptp_plan *plan, int32_t *dParent, void *stream);
+
 /* Copy the topleset order of the last prepare into caller DEVICE buffers:
  * perm[n] = caller vertex id at each position of the order (by topleset, then
  * ascending id; unreachable vertices last), offsets[rho + 1] = start of each
@@ -301,6 +316,10 @@ ptp_status ptp_batch_run_f64(ptp_batch *batch, double *dDist, void *stream);
 /* Synchronise and report: per-mesh stats and status (host arrays [count],
  * either may be NULL).  Returns PTP_OK, or the first non-OK mesh status. */
 ptp_status ptp_batch_get_stats(ptp_batch *batch, ptp_stats *hStats, int32_t *hStatus);
+
+/* ptp_get_parents for a batch: dParent [out_len], indexed like ptp_batch_run,
+ * local (per mesh) vertex ids. */
+ptp_status ptp_batch_get_parents(ptp_batch *batch, int32_t *dParent, void *stream);
 
 /* ptp_set_window for a batch (one cap for every mesh). */
 ptp_status ptp_batch_set_window(ptp_batch *batch, int32_t window);

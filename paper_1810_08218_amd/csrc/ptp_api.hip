@@ -240,8 +240,8 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * (N + 1),                 // rowO
         sizeof(int2) * (F3 + 1),               // wedgeO
         sizeof(int) * N,                       // cursor
-        sizeof(int) * (N + 1),                 // rowN
-        sizeof(int2) * (F3 + 1),               // wedge
+        sizeof(int) * (N + 1),                 // fanlen
+        sizeof(int) * (2 * F3 + 2),            // fanO
         sizeof(float4) * N,                    // xyz
         // dist / dl: one region, 8 bytes per entry.  A run uses either the
         // float double buffer (plain and warm runs) or the 8-byte one
@@ -292,8 +292,8 @@ Work carve(void* base, const Layout& L) {
     w.rowO = reinterpret_cast<int*>(b + L.off[14]);
     w.wedgeO = reinterpret_cast<int2*>(b + L.off[15]);
     w.cursor = reinterpret_cast<int*>(b + L.off[16]);
-    w.rowN = reinterpret_cast<int*>(b + L.off[17]);
-    w.wedge = reinterpret_cast<int2*>(b + L.off[18]);
+    w.fanlen = reinterpret_cast<int*>(b + L.off[17]);
+    w.fanO = reinterpret_cast<int*>(b + L.off[18]);
     w.xyz = reinterpret_cast<float4*>(b + L.off[19]);
     w.dist = reinterpret_cast<float*>(b + L.off[20]);
     w.dl = reinterpret_cast<unsigned long long*>(b + L.off[20]);
@@ -339,6 +339,7 @@ struct Solver {
     const int32_t* Fp = nullptr;
     std::vector<MeshState> hstate;
     bool prepared = false, ran = false;
+    bool parents_valid = false;         // the last run computed labels (and parents)
     std::string err;
     int h_ctrl[8];
 
@@ -413,7 +414,7 @@ struct Solver {
             if (hipEventCreate(&x) != hipSuccess) return PTP_EDEVICE;
         max_prep = max_coop_blocks_bfs(cus);
         const bool rules = opt.band_rule != PTP_BAND_PAPER;
-        max_run = max_coop_blocks_run(cus, opt.want_labels != 0, single, rules);
+        max_run = max_coop_blocks_run(cus, single, rules);
         max_run64 = max_coop_blocks_run64(cus, rules);
         lds_max = opt.lds_bfs_max < 0 ? 0 : bfs_lds_max_vertices(device);
         if (opt.lds_bfs_max > 0) lds_max = std::min(lds_max, opt.lds_bfs_max);
@@ -487,6 +488,7 @@ struct Solver {
                        size_t bytes, void* st) {
         prepared = false;
         ran = false;
+        parents_valid = false;
         sched64_ready = false;
         ms_prepare = -1.f;
         if (!dV || !dS || (!dF && z.F > 0) || !dWork) return fail(PTP_EINVAL, "null pointer argument");
@@ -498,7 +500,11 @@ struct Solver {
         S = dS;
         Vp = dV;
         Fp = dF;
-        // the grid BFS takes the meshes too large for one workgroup's LDS
+        // the grid BFS takes the meshes too large for one workgroup's LDS.  A
+        // level costs a group barrier whatever the group's size, and a level
+        // of these meshes holds a few thousand vertices, so the meshes run side
+        // by side, one group each (at most one XCD's worth of workgroups),
+        // rather than one after another on a few large groups.
         s_prep = Sched{};
         if (!grid_list.empty()) {
             std::vector<MeshDesc> gm;
@@ -507,7 +513,13 @@ struct Solver {
                 gm.push_back(mesh[b]);
                 rho_est.push_back((long long)(2.0 * std::sqrt((double)mesh[b].n)) + 1);
             }
-            s_prep = make_schedule(gm, rho_est, sched, max_prep, grid_list.size() == 1,
+            ptp_schedule ps = sched;
+            ps.workgroups = max_prep;
+            ps.small_limit = 1;                  // no single-workgroup class
+            ps.large_limit = 0x7fffffff;         // every mesh in one class
+            ps.medium_group = std::max(1, std::min(32, max_prep / (int)grid_list.size()));
+            ps.xcd_pack = 1;
+            s_prep = make_schedule(gm, rho_est, ps, max_prep, grid_list.size() == 1,
                                    std::min(cus, max_prep));
             for (size_t x = s_prep.ngroups + 1; x < s_prep.glist.size(); ++x)
                 s_prep.glist[x] = grid_list[s_prep.glist[x]];
@@ -602,7 +614,7 @@ struct Solver {
         const bool f64 = dDist64 != nullptr;
         if (!dDist && !f64) return fail(PTP_EINVAL, "null distance output");
         const bool labels = opt.want_labels != 0;
-        if (labels && dUpper) return fail(PTP_EUNSUPPORTED, "a warm start does not compute labels");
+        if (labels && dUpper) return fail(PTP_EUNSUPPORTED, "the warm-start entry points return distances only");
         if (f64 && (labels || dUpper))
             return fail(PTP_EUNSUPPORTED, "the float64 run computes distances only, from +inf");
         if (labels && !dLabel) return fail(PTP_EINVAL, "labels wanted: null label output");
@@ -624,6 +636,11 @@ struct Solver {
         rp.out_d = dDist;
         rp.out_d64 = dDist64;
         rp.out_l = labels ? dLabel : nullptr;
+        rp.Stot = z.S;
+        int nmax = 1;
+        for (const MeshDesc& md : mesh) nmax = std::max(nmax, md.n);
+        rp.jump_rounds = 1;
+        while ((1ll << (rp.jump_rounds - 1)) < nmax) ++rp.jump_rounds;
         run_timed = !capturing();
         hipError_t e = run_timed ? hipEventRecord(ev[2], stream) : hipSuccess;
         if (e == hipSuccess)
@@ -631,6 +648,17 @@ struct Solver {
         if (e == hipSuccess && run_timed) e = hipEventRecord(ev[3], stream);
         if (e != hipSuccess) return hip_fail(e, "run launch");
         ran = true;
+        parents_valid = labels;
+        return PTP_OK;
+    }
+
+    // The parents behind the labels of the last run (caller order).
+    ptp_status get_parents(int32_t* dParent, void* st) {
+        if (!dParent) return fail(PTP_EINVAL, "null parent output");
+        if (!parents_valid) return fail(PTP_EINVAL, "parents come with the labels of a labelled run");
+        stream = static_cast<hipStream_t>(st);
+        const hipError_t e = launch_parents_out(work, z.B, z.N, dParent, stream);
+        if (e != hipSuccess) return hip_fail(e, "parents launch");
         return PTP_OK;
     }
 
@@ -962,6 +990,11 @@ ptp_status ptp_lloyd_step(ptp_plan* p, const int32_t* dLabel, int32_t* dSout, do
     return p->s.lloyd_step(dLabel, dSout, dCentroid, stream);
 }
 
+ptp_status ptp_get_parents(ptp_plan* p, int32_t* dParent, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.get_parents(dParent, stream);
+}
+
 ptp_status ptp_get_order(ptp_plan* p, int32_t* dPerm, int32_t* dOffsets, void* stream) {
     if (!p) return PTP_EINVAL;
     Solver& s = p->s;
@@ -1069,6 +1102,11 @@ ptp_status ptp_batch_get_stats(ptp_batch* p, ptp_stats* hStats, int32_t* hStatus
         return s.fail(PTP_EINVAL, "no run to report");
     }
     return s.stats(hStats, hStatus);
+}
+
+ptp_status ptp_batch_get_parents(ptp_batch* p, int32_t* dParent, void* stream) {
+    if (!p) return PTP_EINVAL;
+    return p->s.get_parents(dParent, stream);
 }
 
 ptp_status ptp_batch_set_window(ptp_batch* p, int32_t window) {

@@ -195,6 +195,33 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
     return lo;
 }
 
+// Element loops over the concatenation take tiles of kTile consecutive
+// elements per workgroup.  The mesh of a tile's first element is found once
+// (binary search over the prefix) and each thread advances it across the
+// few mesh boundaries inside the tile, so an element costs no search of its
+// own.  f(x, b) gets the element and its mesh.
+constexpr int kTileItems = 8;
+constexpr int kTile = kTileItems * kBlock;
+
+template <class Fn>
+__device__ inline void for_tiles(const int* prefix, int B, long long total, Fn f) {
+    __shared__ int tile_mesh;
+    const long long ntiles = (total + kTile - 1) / kTile;
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const long long base = t * kTile;
+        if (threadIdx.x == 0) tile_mesh = mesh_of(prefix, B, base);
+        __syncthreads();
+        int b = tile_mesh;
+        __syncthreads();        // tile_mesh is rewritten for the next tile
+        for (int q = 0; q < kTileItems; ++q) {
+            const long long x = base + (long long)q * kBlock + threadIdx.x;
+            if (x >= total) break;
+            while ((long long)prefix[b + 1] <= x) ++b;
+            f(x, b);
+        }
+    }
+}
+
 // ---- block-wide scans --------------------------------------------------
 // Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by
 // 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from outside the

@@ -55,9 +55,9 @@ struct Work {
     int* offsets;       // [N + B] topleset starts, mesh b at v_off_b + b
     int* rowO;          // [N + 1] incidence CSR over global vertex ids
     int2* wedgeO;       // [3F]    opposite edge of each incident triangle, global ids
-    int* cursor;        // [N]     fill cursors
-    int* rowN;          // [N + 1] incidence CSR over positions
-    int2* wedge;        // [3F]    opposite edge, positions
+    int* cursor;        // [N]     fill cursors; after a labelled run the parents (positions)
+    int* fanlen;        // [N + 1] fan length of each vertex (global ids)
+    int* fanO;          // [6F + 2] fans by global vertex id, vertex v at 2 * rowO[v]
     float4* xyz;        // [N]     coordinates by position (w unused)
     float* dist;        // [2N]    Jacobi double buffer (plain and warm runs)
     unsigned long long* dl;   // [2N] the same memory as 8-byte entries: (distance, label)
@@ -147,13 +147,20 @@ struct RunParams {
     bool certify;                // warm start: certify the bound (else trusted)
     float* out_d;
     double* out_d64;             // the double-precision run's output
-    int* out_l;
+    int* out_l;                  // labels (caller order), or null
+    long long Stot;              // sources over the batch (labels)
+    int jump_rounds;             // pointer-jumping rounds of the labels: ceil(log2(largest n)) + 1
 };
 
 // cache: use the register-caching relaxation (single meshes); f64: the
-// double-precision relaxation (no labels, no warm start, no cache)
+// double-precision relaxation (no labels, no warm start, no cache); labels:
+// Voronoi labels of the final map into p.out_l after the relaxation
 hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache, bool f64, int g_run,
                       hipStream_t st);
+
+// parents of the last labelled run in the caller's order (caller vertex
+// ids; a source its own id, -1 where none)
+hipError_t launch_parents_out(const Work& w, int B, long long N, int* out, hipStream_t st);
 
 // learned warm start
 hipError_t launch_features(const Work& w, const Sizes& z, hipStream_t st);
@@ -169,7 +176,7 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
 size_t mlp_scratch_bytes();
 
 int max_coop_blocks_bfs(int cus);
-int max_coop_blocks_run(int cus, bool labels, bool cache, bool rules);
+int max_coop_blocks_run(int cus, bool cache, bool rules);
 int max_coop_blocks_run64(int cus, bool rules);
 
 // farthest point sampling: argmax of the caller-order map of mesh 0, append

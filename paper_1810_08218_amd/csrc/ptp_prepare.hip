@@ -36,40 +36,35 @@ __global__ __launch_bounds__(kBlock) void k_zero_lines(unsigned* p, long long le
 
 // Face ids must lie in their mesh, coordinates be finite, sources lie in
 // their mesh.  Bad meshes are flagged in their state and in the batch word.
-// Loops run over the internal (concatenated) index spaces; each element finds
-// its mesh by binary search and reads the caller's row.
+// Loops run over the internal (concatenated) index spaces and read the
+// caller's rows.
 __global__ __launch_bounds__(kBlock) void k_validate(const float* V, const int* F, const int* S,
                                                      const MeshDesc* mesh, int B, const int* vo,
                                                      const int* fo3, const int* so, long long N,
                                                      long long F3, long long Stot, MeshState* state,
                                                      int* ctrl) {
-    const long long gsz = (long long)gridDim.x * kBlock;
-    const long long g0 = blockIdx.x * (long long)kBlock + threadIdx.x;
     int bad = 0;
-    for (long long x = g0; x < F3; x += gsz) {
-        const int b = mesh_of(fo3, B, x);
+    for_tiles(fo3, B, F3, [&](long long x, int b) {
         const int v = F[3 * mesh[b].f_in + (x - fo3[b])];
         if (v < 0 || v >= mesh[b].n) {
             atomicOr(&state[b].status, ST_BAD_FACE);
             bad |= ST_BAD_FACE;
         }
-    }
-    for (long long p = g0; p < N; p += gsz) {
-        const int b = mesh_of(vo, B, p);
+    });
+    for_tiles(vo, B, N, [&](long long p, int b) {
         const float* c = V + 3 * (mesh[b].v_in + (p - vo[b]));
         if (!(fabsf(c[0]) <= 3.0e38f) || !(fabsf(c[1]) <= 3.0e38f) || !(fabsf(c[2]) <= 3.0e38f)) {
             atomicOr(&state[b].status, ST_BAD_COORD);
             bad |= ST_BAD_COORD;
         }
-    }
-    for (long long x = g0; x < Stot; x += gsz) {
-        const int b = mesh_of(so, B, x);
+    });
+    for_tiles(so, B, Stot, [&](long long x, int b) {
         const int s = S[mesh[b].s_in + (x - so[b])];
         if (s < 0 || s >= mesh[b].n) {
             atomicOr(&state[b].status, ST_BAD_SOURCE);
             bad |= ST_BAD_SOURCE;
         }
-    }
+    });
     if (bad) atomicOr(ctrl + C_STATUS, bad);
 }
 
@@ -78,11 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_count(const int* F, const MeshDesc* 
                                                   const int* fo3, long long F3, int* row,
                                                   const int* ctrl) {
     if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < F3; x += gsz) {
-        const int b = mesh_of(fo3, B, x);
+    for_tiles(fo3, B, F3, [&](long long x, int b) {
         atomicAdd(row + mesh[b].v_off + F[3 * mesh[b].f_in + (x - fo3[b])] + 1, 1);
-    }
+    });
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const MeshDesc* mesh, int B,
@@ -90,9 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
                                                            const int* row, int* cursor,
                                                            int2* wedgeO, const int* ctrl) {
     if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long x = blockIdx.x * (long long)kBlock + threadIdx.x; x < F3; x += gsz) {
-        const int b = mesh_of(fo3, B, x);
+    for_tiles(fo3, B, F3, [&](long long x, int b) {
         const int vo = mesh[b].v_off;
         const long long lc = x - fo3[b];                 // corner inside the mesh
         const long long t3 = 3 * mesh[b].f_in + (lc - lc % 3);
@@ -100,42 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
         const int v = vo + F[t3 + c];
         const int slot = atomicAdd(cursor + v, 1);
         wedgeO[row[v] + slot] = make_int2(vo + F[t3 + other1(c)], vo + F[t3 + other2(c)]);
-    }
-}
-
-// Distinct neighbours of every vertex from its wedges, into its row of ellO.
-__global__ __launch_bounds__(kBlock) void k_ell(const int* row, const int2* wedgeO, long long N, int* ellO,
-                                                const int* ctrl) {
-    if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long v = blockIdx.x * (long long)kBlock + threadIdx.x; v < N; v += gsz) {
-        int nb[kEll];
-#pragma unroll
-        for (int q = 0; q < kEll; ++q) nb[q] = -1;
-        int cnt = 0;
-        const int e0 = row[v], e1 = row[v + 1];
-        for (int e = e0; e < e1 && cnt <= kEll; ++e) {
-            const int2 t = wedgeO[e];
-            const int xs[2] = {t.x, t.y};
-            for (int z = 0; z < 2; ++z) {
-                bool seen = false;
-#pragma unroll
-                for (int q = 0; q < kEll; ++q) seen |= nb[q] == xs[z];
-                if (!seen) {
-                    if (cnt < kEll) {
-#pragma unroll
-                        for (int q = 0; q < kEll; ++q)
-                            if (q == cnt) nb[q] = xs[z];
-                    }
-                    ++cnt;
-                }
-            }
-        }
-        if (cnt > kEll) nb[kEll - 1] = kEllMore;
-        int4* out = reinterpret_cast<int4*>(ellO + kEll * v);
-        out[0] = make_int4(nb[0], nb[1], nb[2], nb[3]);
-        out[1] = make_int4(nb[4], nb[5], nb[6], nb[7]);
-    }
+    });
 }
 
 // ---- in-place inclusive scan of a[0..len) (three passes) ----------------
@@ -603,50 +559,52 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
     }
 }
 
-// degree of each position, into rowN[p + 1]
-__global__ __launch_bounds__(kBlock) void k_degree_new(const int* perm, const int* rowO,
-                                                       long long N, int* rowN, const int* ctrl) {
+// Fan length of each position, into fanrow[p + 1] (the fans themselves are
+// built once per prepare by vertex id, independent of the sources).
+__global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const int* fanlen, long long N,
+                                                       int* fanrow, const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
     for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int v = perm[p];
-        rowN[p + 1] = rowO[v + 1] - rowO[v];
-        if (p == 0) rowN[0] = 0;
+        fanrow[p + 1] = fanlen[perm[p]];
+        if (p == 0) fanrow[0] = 0;
     }
 }
 
+// Coordinates and fans in topleset order: position p takes the coordinates
+// of its vertex and a copy of the vertex's fan with every neighbour id turned
+// into that neighbour's position (flags kept).
 __global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const MeshDesc* mesh, int B,
                                                     const int* vo, const int* perm, const int* iperm,
-                                                    const int* rowO, const int2* wedgeO,
-                                                    const int* rowN, long long N, float4* xyz,
-                                                    int2* wedge, const int* ctrl) {
+                                                    const int* rowO, const int* fanO, const int* fanlen,
+                                                    const int* fanrow, long long N, float4* xyz, int* fan,
+                                                    const int* ctrl) {
     if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int v = perm[p];
-        const int mb = mesh_of(vo, B, v);
-        const float* c = V + 3 * (mesh[mb].v_in + (v - vo[mb]));
+    for_tiles(vo, B, N, [&](long long p, int b) {
+        const int v = perm[p];                  // a vertex of the same mesh as position p
+        const float* c = V + 3 * (mesh[b].v_in + (v - vo[b]));
         xyz[p] = make_float4(c[0], c[1], c[2], 0.f);
-        const int r0 = rowO[v], r1 = rowO[v + 1];
-        int o = rowN[p];
-        for (int x = r0; x < r1; ++x, ++o) {
-            const int2 t = wedgeO[x];
-            wedge[o] = make_int2(iperm[t.x], iperm[t.y]);
+        const int* src = fanO + 2 * (long long)rowO[v];
+        int* dst = fan + fanrow[p];
+        const int len = fanlen[v];
+        for (int q = 0; q < len; ++q) {
+            const int e = src[q];
+            dst[q] = iperm[e & kFanId] | (e & ~kFanId);
         }
-    }
+    });
 }
 
-// The chains of one position's wedges wd[0..c) (see kFanStart): a chain
-// starts at a wedge that no unused wedge leads into (the lowest unused one
-// if every unused wedge has a predecessor: a closed fan), and follows
-// (a, b) -> (b, c) while an unused wedge continues it.  Entry q goes to
-// emit(q, value); returns the number of entries.  Every wedge is used
-// exactly once, as a consecutive pair of one chain or as the closing pair.
-template <class Emit>
-__device__ inline int build_fan(const int2* wd, int c, Emit emit) {
+// The chains of one vertex's wedges wd(0..c) (see kFanStart): a chain starts
+// at a wedge that no unused wedge leads into (the lowest unused one if every
+// unused wedge has a predecessor: a closed fan), and follows (a, b) -> (b, c)
+// while an unused wedge continues it.  Entry q goes to emit(q, value);
+// returns the number of entries.  Every wedge is used exactly once, as a
+// consecutive pair of one chain or as the closing pair.
+template <class Get, class Emit>
+__device__ inline int build_fan(Get wd, int c, Emit emit) {
     if (c > kFanChainMax) {
         for (int q = 0; q < c; ++q) {
-            const int2 t = wd[q];
+            const int2 t = wd(q);
             emit(2 * q, t.x | kFanStart);
             emit(2 * q + 1, t.y);
         }
@@ -658,11 +616,11 @@ __device__ inline int build_fan(const int2* wd, int c, Emit emit) {
         int s = __ffs(left) - 1;
         for (unsigned m = left; m; m &= m - 1) {
             const int i = __ffs(m) - 1;
-            const int ai = wd[i].x;
+            const int ai = wd(i).x;
             bool pred = false;
             for (unsigned m2 = left; m2 && !pred; m2 &= m2 - 1) {
                 const int j = __ffs(m2) - 1;
-                pred = j != i && wd[j].y == ai;
+                pred = j != i && wd(j).y == ai;
             }
             if (!pred) {
                 s = i;
@@ -670,23 +628,23 @@ __device__ inline int build_fan(const int2* wd, int c, Emit emit) {
             }
         }
         left &= ~(1u << s);
-        const int first = wd[s].x;
+        const int first = wd(s).x;
         const bool whole = len == 0;
         emit(len++, first | kFanStart);
-        int cur = wd[s].y;
+        int cur = wd(s).y;
         emit(len++, cur);
         for (;;) {
             int nx = -1;
             for (unsigned m = left; m; m &= m - 1) {
                 const int j = __ffs(m) - 1;
-                if (wd[j].x == cur) {
+                if (wd(j).x == cur) {
                     nx = j;
                     break;
                 }
             }
             if (nx < 0) break;
             left &= ~(1u << nx);
-            cur = wd[nx].y;
+            cur = wd(nx).y;
             if (whole && !left && cur == first) {     // one closed chain: no repeat
                 emit(0, first | kFanStart | kFanClosed);
                 break;
@@ -697,34 +655,38 @@ __device__ inline int build_fan(const int2* wd, int c, Emit emit) {
     return len;
 }
 
-struct NoEmit {
-    __device__ void operator()(int, int) const {}
-};
-
-struct FanEmit {
-    int* out;
-    __device__ void operator()(int q, int v) const { out[q] = v; }
-};
-
-// fan length of each position, into fanrow[p + 1]
-__global__ __launch_bounds__(kBlock) void k_fan_count(const int* rowN, const int2* wedge, long long N,
-                                                      int* fanrow, const int* ctrl) {
+// Fans by vertex id.  A vertex's wedges (staged in LDS, one column per
+// thread, when there are at most kFanChainMax) are chained into fanO at
+// twice the vertex's incidence offset (a fan has at most two entries per
+// triangle), the length goes to fanlen, and the BFS neighbour row to ellO:
+// the fan's ids (each neighbour named once per chain) padded with -1, or
+// kEllMore in the last entry when the fan has more than kEll entries (the
+// BFS then expands the vertex from its wedges).
+__global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const int2* wedgeO, long long N,
+                                                       int* fanO, int* fanlen, int* ellO, const int* ctrl) {
     if (gated(ctrl)) return;
+    __shared__ int2 wd_s[kFanChainMax * kBlock];
+    const int tid = threadIdx.x;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int r0 = rowN[p];
-        fanrow[p + 1] = build_fan(wedge + r0, rowN[p + 1] - r0, NoEmit{});
-        if (p == 0) fanrow[0] = 0;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_fan_fill(const int* rowN, const int2* wedge, long long N,
-                                                     const int* fanrow, int* fan, const int* ctrl) {
-    if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int r0 = rowN[p];
-        build_fan(wedge + r0, rowN[p + 1] - r0, FanEmit{fan + fanrow[p]});
+    for (long long v = blockIdx.x * (long long)kBlock + tid; v < N; v += gsz) {
+        const int r0 = rowO[v], c = rowO[v + 1] - r0;
+        int* out = fanO + 2 * (long long)r0;
+        auto emit = [&](int q, int x) { out[q] = x; };
+        int len;
+        if (c <= kFanChainMax) {
+            for (int q = 0; q < c; ++q) wd_s[q * kBlock + tid] = wedgeO[r0 + q];
+            len = build_fan([&](int q) { return wd_s[q * kBlock + tid]; }, c, emit);
+        } else {
+            len = build_fan([&](int q) { return wedgeO[r0 + q]; }, c, emit);
+        }
+        fanlen[v] = len;
+        int nb[kEll];
+#pragma unroll
+        for (int q = 0; q < kEll; ++q) nb[q] = q < len ? (out[q] & kFanId) : -1;
+        if (len > kEll) nb[kEll - 1] = kEllMore;
+        int4* er = reinterpret_cast<int4*>(ellO + kEll * v);
+        er[0] = make_int4(nb[0], nb[1], nb[2], nb[3]);
+        er[1] = make_int4(nb[4], nb[5], nb[6], nb[7]);
     }
 }
 
@@ -756,15 +718,17 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
                        w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
-    hipLaunchKernelGGL(k_ell, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
+    hipLaunchKernelGGL(k_fan_global, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.fanO,
+                       w.fanlen, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_prepare_bfs(w, z, V, S, g_prep, n_lds, st);
 }
 
 // Toplesets by BFS from the current sources, then the reorder of coordinates
-// and incidence into topleset order and the fans.  The incidence (rowO,
-// wedgeO, ellO) must already be built; it does not depend on the sources.
+// and fans into topleset order.  The incidence and the fans by vertex id
+// (rowO, wedgeO, ellO, fanO, fanlen) must already be built; they do not
+// depend on the sources.
 hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, const int* S, int g_prep,
                               int n_lds, hipStream_t st) {
     const long long N = z.N;
@@ -812,18 +776,12 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
                                        args, 0, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_degree_new, dim3(grid_for(N)), dim3(kBlock), 0, st, w.perm, w.rowO, N,
-                       w.rowN, w.ctrl);
-    e = scan_inplace(w.rowN + 1, N, w.scan_tmp, w.ctrl, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo,
-                       w.perm, w.iperm, w.rowO, w.wedgeO, w.rowN, N, w.xyz, w.wedge, w.ctrl);
-    hipLaunchKernelGGL(k_fan_count, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowN, w.wedge, N, w.fanrow,
+    hipLaunchKernelGGL(k_fanrow_new, dim3(grid_for(N)), dim3(kBlock), 0, st, w.perm, w.fanlen, N, w.fanrow,
                        w.ctrl);
     e = scan_inplace(w.fanrow + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fan_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowN, w.wedge, N, w.fanrow,
-                       w.fan, w.ctrl);
+    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo, w.perm,
+                       w.iperm, w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.ctrl);
     return hipGetLastError();
 }
 

@@ -117,7 +117,6 @@ struct RelaxArgs {
     long long N;
     float* out_d;
     double* out_d64;
-    int* out_l;
 };
 
 // Fan entries held in registers per band vertex (closed fans of degree <= 6
@@ -125,69 +124,48 @@ struct RelaxArgs {
 constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
-// The iteration state of a position: its distance, or with labels (float
-// only) its (distance, label) pair in one 8-byte word, so that a neighbour
-// costs one coherent load and a position one store.
-__device__ inline unsigned long long pack_dl(float d, int l) {
-    return (unsigned long long)__float_as_uint(d) | ((unsigned long long)(unsigned)l << 32);
+// The iteration state of a position: its distance (float, or double in the
+// float64 run), exchanged between workgroups with coherent loads.
+template <typename R>
+__device__ inline R ld_s(const R* s, int id) {
+    return ld_c(s + id);
 }
 
-template <typename R, bool LABELS>
-__device__ inline void ld_s(const void* s, int id, R& d, int& l) {
-    if (LABELS) {
-        const unsigned long long x = ld_c(static_cast<const unsigned long long*>(s) + id);
-        d = (R)__uint_as_float((unsigned)x);
-        l = (int)(unsigned)(x >> 32);
-    } else {
-        d = ld_c(static_cast<const R*>(s) + id);
-    }
-}
-
-template <typename R, bool LABELS>
-__device__ inline void st_s(void* s, int id, R d, int l, bool local) {
-    if (LABELS) st_g(static_cast<unsigned long long*>(s) + id, pack_dl((float)d, l), local);
-    else st_g(static_cast<R*>(s) + id, d, local);
-}
-
-// Planar update of x0 from one triangle, folded into the (value, label)
-// lexicographic minimum best / bl, which does not depend on the order in
-// which the triangles come.
-template <typename R, bool LABELS>
-__device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, R d1, R d2, int l1,
-                                   int l2, R& best, int& bl, bool valid = true) {
+// Planar update of x0 from one triangle, folded into the minimum `best`
+// (which does not depend on the order in which the triangles come).
+template <typename R>
+__device__ inline void fold_update(const float4 x0, const float4 x1, const float4 x2, R d1, R d2, R& best,
+                                   bool valid = true) {
     int l = 0;
-    const R u = local_update<R, LABELS>(x0, x1, x2, d1, d2, l1, l2, l);
-    const bool take = valid && (u < best || (LABELS && u == best && l < bl && u < inf_of<R>()));
-    best = take ? u : best;
-    if (LABELS) bl = take ? l : bl;
+    const R u = local_update<R, false>(x0, x1, x2, d1, d2, 0, 0, l);
+    best = valid && u < best ? u : best;
 }
 
 // The triangles of the first C entries of a fan of L entries (e: entries
-// with flags, entries past L repeat entry 0; d / x / l: their distances,
-// coordinates and labels).  Slot q (1 <= q <= C) is the pair (entry q-1,
+// with flags, entries past L repeat entry 0; d / x: their distances and
+// coordinates).  Slot q (1 <= q <= C) is the pair (entry q-1,
 // entry q) for q < L unless entry q opens a chain, and the closing pair
 // (entry L-1, entry 0) for q = L on a closed fan.
-template <typename R, bool LABELS, int C>
-__device__ inline void eval_fan_first(const float4 x0, const int* e, const R* d, const float4* x, const int* l,
-                                      int L, R& best, int& bl) {
+template <typename R, int C>
+__device__ inline void eval_fan_first(const float4 x0, const int* e, const R* d, const float4* x, int L,
+                                      R& best) {
     const bool closed = (e[0] & kFanClosed) != 0;
 #pragma unroll
     for (int q = 1; q <= C; ++q) {
         const int q2 = q < C ? q : 0;
         const bool valid = q < C ? (q < L ? (e[q] & kFanStart) == 0 : (q == L && closed)) : (L == C && closed);
-        fold_update<R, LABELS>(x0, x[q - 1], x[q2], d[q - 1], d[q2], LABELS ? l[q - 1] : 0, LABELS ? l[q2] : 0,
-                               best, bl, valid);
+        fold_update<R>(x0, x[q - 1], x[q2], d[q - 1], d[q2], best, valid);
     }
 }
 
 // The rest of a fan longer than C entries: chunks of C entries overlapping
-// by one, then the closing pair with entry 0 (d0 / xf / l0) on a closed fan.
-template <typename R, bool LABELS, int C>
+// by one, then the closing pair with entry 0 (d0 / xf) on a closed fan.
+template <typename R, int C>
 __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0, int f0, int L, bool closed,
-                                     R d0, float4 xf, int l0, const void* sold, R& best, int& bl) {
+                                     R d0, float4 xf, const R* sold, R& best) {
     for (int base = C - 1; base < L - 1; base += C - 1) {
         const int cnt = min(C, L - base);
-        int e[C], l[C];
+        int e[C];
         R d[C];
         float4 x[C];
 #pragma unroll
@@ -195,21 +173,17 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             const int id = e[q] & kFanId;
-            l[q] = 0;
-            ld_s<R, LABELS>(sold, id, d[q], l[q]);
+            d[q] = ld_s(sold, id);
             x[q] = a.xyz[id];
         }
 #pragma unroll
         for (int q = 1; q < C; ++q)
-            fold_update<R, LABELS>(x0, x[q - 1], x[q], d[q - 1], d[q], l[q - 1], l[q], best, bl,
-                                   q < cnt && (e[q] & kFanStart) == 0);
+            fold_update<R>(x0, x[q - 1], x[q], d[q - 1], d[q], best, q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
-            R dl;
-            int ll = 0;
-            ld_s<R, LABELS>(sold, id, dl, ll);
+            const R dl = ld_s(sold, id);
             const float4 xl = a.xyz[id];
-            fold_update<R, LABELS>(x0, xl, xf, dl, d0, ll, l0, best, bl);
+            fold_update<R>(x0, xl, xf, dl, d0, best);
         }
     }
 }
@@ -223,34 +197,28 @@ __device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e
     for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
 }
 
-template <typename R, bool LABELS, int C>
-__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const void* sold, R* d, float4* x, int* l) {
+template <typename R, int C>
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int id = e[q] & kFanId;
-        int lq = 0;
-        ld_s<R, LABELS>(sold, id, d[q], lq);
-        if (LABELS) l[q] = lq;
+        d[q] = ld_s(sold, id);
         x[q] = a.xyz[id];
     }
 }
 
 // Smallest planar update of position v over all its incident triangles.
-template <typename R, bool LABELS, int C>
-__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const void* sold, R& best,
-                                   int& bl) {
+template <typename R, int C>
+__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const R* sold, R& best) {
     best = inf_of<R>();
-    bl = 0x7fffffff;
     const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
-    int e[C], l[C];
+    int e[C];
     R d[C];
     float4 x[C];
     load_fan<C>(a, v, f0, L, e);
-    gather_fan<R, LABELS, C>(a, e, sold, d, x, l);
-    eval_fan_first<R, LABELS, C>(x0, e, d, x, l, L, best, bl);
-    if (L > C)
-        eval_fan_rest<R, LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], LABELS ? l[0] : 0,
-                                    sold, best, bl);
+    gather_fan<R, C>(a, e, sold, d, x);
+    eval_fan_first<R, C>(x0, e, d, x, L, best);
+    if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
 }
 
 // Convergence of one position between two iterations (Eq. lower_band): a
@@ -272,9 +240,9 @@ __device__ inline bool converged(R dv, R dn, float tol) {
 // that owns several band vertices waits for about one memory round per
 // vertex instead of three.  Returns the "not converged" vote of the
 // positions below tb.
-template <typename R, bool LABELS, int C>
+template <typename R, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
-                                                long long tb, long long gsz, const void* sold, void* snew,
+                                                long long tb, long long gsz, const R* sold, R* snew,
                                                 bool local) {
     unsigned notconv = 0;
     if (p >= be) return 0;
@@ -291,13 +259,10 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
-        R dv;
-        int lv = 0;
-        ld_s<R, LABELS>(sold, v, dv, lv);
-        int l[C];
+        const R dv = ld_s(sold, v);
         R d[C];
         float4 x[C];
-        gather_fan<R, LABELS, C>(a, e, sold, d, x, l);
+        gather_fan<R, C>(a, e, sold, d, x);
         // the next position's fan entries and the fan row of the one after
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
@@ -309,14 +274,10 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
             fnn1 = a.fanrow[vo + pnn + 1];
         }
         R best = inf_of<R>();
-        int bl = 0x7fffffff;
-        eval_fan_first<R, LABELS, C>(x0, e, d, x, l, L, best, bl);
-        if (L > C)
-            eval_fan_rest<R, LABELS, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0],
-                                        LABELS ? l[0] : 0, sold, best, bl);
-        const bool better = best < dv;
-        const R dn = better ? best : dv;
-        st_s<R, LABELS>(snew, v, dn, better ? bl : lv, local);
+        eval_fan_first<R, C>(x0, e, d, x, L, best);
+        if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
+        const R dn = best < dv ? best : dv;
+        st_g(snew + v, dn, local);
         if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
         if (pn >= be) break;
         p = pn;
@@ -354,10 +315,9 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
         const float wv = ld_c(d + v);
-        int l[C];
         float dd[C];
         float4 x[C];
-        gather_fan<float, false, C>(a, e, d, dd, x, l);
+        gather_fan<float, C>(a, e, d, dd, x);
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
         int en[C];
@@ -369,11 +329,8 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         }
         if (wv < kInf) {
             float best = kInf;
-            int bl = 0;
-            eval_fan_first<float, false, C>(x0, e, dd, x, l, L, best, bl);
-            if (L > C)
-                eval_fan_rest<float, false, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], 0, d,
-                                               best, bl);
+            eval_fan_first<float, C>(x0, e, dd, x, L, best);
+            if (L > C) eval_fan_rest<float, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], d, best);
             if (wv < best) {
                 st_g(d + v, kInf, local);
                 changed = 1;
@@ -413,14 +370,14 @@ constexpr int kOffsLds = 4096;
 // stay in that CU's caches.  For each vertex it first gathers up to kChunk
 // wedges, then every neighbour distance and coordinate of those wedges at
 // once (independent loads), then evaluates the planar updates.  Distances and
-// labels are exchanged between workgroups through coherent loads and stores.
-// R = double: the same iteration in float64 (no labels, warm start or cache).
+// are exchanged between workgroups through coherent loads and stores.
+// R = double: the same iteration in float64 (no warm start or cache).
 // RULES: the band rule is read at run time (fixed half band, Jacobi);
 // otherwise it is the paper's, fixed at compile time, which keeps the band
 // loop's registers for the common case.
-template <typename R, bool LABELS, bool WARM, bool CACHE, bool RULES = false>
+template <typename R, bool WARM, bool CACHE, bool RULES = false>
 __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
-    static_assert(sizeof(R) == 4 || (!LABELS && !WARM && !CACHE), "float64 runs plain only");
+    static_assert(sizeof(R) == 4 || (!WARM && !CACHE), "float64 runs plain only");
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
     const int gs = me.gsize;
@@ -438,10 +395,17 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     const R kInfR = inf_of<R>();
     float* dA = a.dist;
     float* dB = a.dist + a.N;
-    // the iteration state: distances, or (distance, label) pairs with labels;
-    // the float64 run keeps its doubles in the 8-byte buffer
-    void* sA = (LABELS || sizeof(R) == 8) ? static_cast<void*>(a.dl) : static_cast<void*>(dA);
-    void* sB = (LABELS || sizeof(R) == 8) ? static_cast<void*>(a.dl + a.N) : static_cast<void*>(dB);
+    // the iteration state: the float double buffer, or the float64 run's
+    // doubles in the 8-byte view of the same memory
+    R* sA;
+    R* sB;
+    if constexpr (sizeof(R) == 8) {
+        sA = reinterpret_cast<R*>(a.dl);
+        sB = reinterpret_cast<R*>(a.dl + a.N);
+    } else {
+        sA = dA;
+        sB = dB;
+    }
     const int rule = RULES ? a.band_rule : (int)BAND_PAPER;
     const bool jacobi = rule == BAND_JACOBI;
 
@@ -488,17 +452,9 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 const float w = a.upper[md.out_off + (v - vo)];
                 d = w >= 0.f ? (R)w : kInfR;             // NaN or negative: no bound
             }
-            if (!LABELS || p >= m0) {           // with labels the sources come next
-                st_s<R, LABELS>(sA, vo + (int)p, d, -1, local);
-                st_s<R, LABELS>(sB, vo + (int)p, d, -1, local);
-            }
+            st_g(sA + vo + p, d, local);
+            st_g(sB + vo + p, d, local);
         }
-        if (LABELS)
-            for (long long s = g0; s < md.m; s += gsz) {
-                const int p = a.iperm[vo + a.S[md.s_in + s]];
-                st_s<R, LABELS>(sA, p, (R)0, (int)s, local);
-                st_s<R, LABELS>(sB, p, (R)0, (int)s, local);
-            }
         for (long long r = g0; r < rho; r += gsz) st_g(retire + r, r == 0 ? 0 : -1, local);
         if (!gb.sync(0, &any)) return;
 
@@ -552,8 +508,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             int lo = i;
             if (rule == BAND_FIXED_HALF) lo = max(1, (k + 1) >> 1);
             if (a.window > 0) lo = max(lo, j - a.window + 1);
-            const void* sold = (k & 1) ? sA : sB;
-            void* snew = (k & 1) ? sB : sA;
+            const R* sold = (k & 1) ? sA : sB;
+            R* snew = (k & 1) ? sB : sA;
             const int cb = offs_lds ? s_offs[lo_prev] : offs[lo_prev];   // retired since last iteration: copy
             const int bb = offs_lds ? s_offs[lo] : offs[lo];             // band
             const int be = offs_lds ? s_offs[j + 1] : offs[j + 1];
@@ -565,23 +521,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             // thread)
             const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
-                for (long long pp = first; pp < bb; pp += gsz) {
-                    R dc;
-                    int lc = 0;
-                    ld_s<R, LABELS>(sold, vo + (int)pp, dc, lc);
-                    st_s<R, LABELS>(snew, vo + (int)pp, dc, lc, local);
-                }
+                for (long long pp = first; pp < bb; pp += gsz)
+                    st_g(snew + vo + pp, ld_s(sold, vo + (int)pp), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_pipelined<R, LABELS, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
+                notconv |= relax_band_pipelined<R, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    R dc;
-                    int lc = 0;
-                    ld_s<R, LABELS>(sold, v, dc, lc);
-                    st_s<R, LABELS>(snew, v, dc, lc, local);
+                    st_g(snew + v, ld_s(sold, v), local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -592,24 +541,19 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                R dv;
-                int lv = 0;
-                ld_s<R, LABELS>(sold, v, dv, lv);
+                const R dv = ld_s(sold, v);
                 R best = kInfR;
-                int bl = 0x7fffffff;
                 if (cached && cv == v) {
-                    int l[kCache];
                     R d[kCache];
                     float4 x[kCache];
-                    gather_fan<R, LABELS, kCache>(a, ce, sold, d, x, l);
-                    eval_fan_first<R, LABELS, kCache>(cx0, ce, d, x, l, cL, best, bl);
+                    gather_fan<R, kCache>(a, ce, sold, d, x);
+                    eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
-                    best_update<R, LABELS, kChunk>(a, v, x0, sold, best, bl);
+                    best_update<R, kChunk>(a, v, x0, sold, best);
                 }
-                const bool better = best < dv;
-                const R dn = better ? best : dv;
-                st_s<R, LABELS>(snew, v, dn, better ? bl : lv, local);
+                const R dn = best < dv ? best : dv;
+                st_g(snew + v, dn, local);
                 if (pp < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             }
             upd += be - bb;
@@ -643,15 +587,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             }
             lo_prev = lo;
         }
-        const void* sfin = (k & 1) ? sB : sA;
+        const R* sfin = (k & 1) ? sB : sA;
         for (long long p = g0; p < n; p += gsz) {
             const int v = a.perm[vo + p];
-            R df;
-            int lf = 0;
-            ld_s<R, LABELS>(sfin, vo + (int)p, df, lf);
+            const R df = ld_s(sfin, vo + (int)p);
             if (sizeof(R) == 8) a.out_d64[md.out_off + (v - vo)] = (double)df;
             else a.out_d[md.out_off + (v - vo)] = (float)df;
-            if (LABELS) a.out_l[md.out_off + (v - vo)] = lf;
         }
         if (leader) {
             a.state[b].iters = k;
@@ -675,9 +616,119 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
     }
 }
 
-template <typename R, bool LABELS, bool WARM, bool CACHE, bool RULES = false>
+// ---- Voronoi labels of the final map ---------------------------------------
+// The label of a vertex is the index in S of the source at the root of its
+// chain of parents.  The parent is the vertex its final value comes from
+// under its best triangle: over the fan's triangles the smallest (update,
+// giver id), the giver of a planar value being its smaller input and that of
+// an edge update the edge's other end (equal candidates: the smaller id),
+// among givers that come before the vertex in (distance, id) order, so that
+// the parents form a forest rooted at the sources.  Ids are the caller's
+// vertex ids, so the result does not depend on the internal order.  `parent`
+// and `root` receive parent positions (a source its own, -1 for an
+// unreachable vertex or one without a giver); pointer jumping then turns
+// `root` into roots.
+__global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const MeshState* state, int B,
+                                                    const int* vo_prefix, long long N, const int* perm,
+                                                    const int* level, const int* fanrow, const int* fan,
+                                                    const float4* xyz, const float* dist, int* parent,
+                                                    int* root) {
+    for_tiles(vo_prefix, B, N, [&](long long p, int b) {
+        const int vo = mesh[b].v_off;
+        // the mesh's final distances: the buffer its last iteration wrote
+        const float* d = dist + ((state[b].iters & 1) ? N : 0);
+        const int vid = perm[p] - vo;
+        if (level[vo + vid] == 0) {
+            parent[p] = (int)p;
+            root[p] = (int)p;
+            return;
+        }
+        const float dv = d[p];
+        int bq = -1;
+        if (dv < kInf) {
+            const float4 x0 = xyz[p];
+            float bu = kInf;
+            int bg = 0x7fffffff;
+            auto tri = [&](int q1, int q2) {
+                const float d1 = d[q1], d2 = d[q2];
+                const int i1 = perm[q1] - vo, i2 = perm[q2] - vo;
+                int g = 0;
+                const float u = local_update<float, true>(x0, xyz[q1], xyz[q2], d1, d2, i1, i2, g);
+                if (!(u < kInf)) return;
+                const float dg = g == i1 ? d1 : d2;
+                if (!(dg < dv || (dg == dv && g < vid))) return;
+                if (u < bu || (u == bu && g < bg)) {
+                    bu = u;
+                    bg = g;
+                    bq = g == i1 ? q1 : q2;
+                }
+            };
+            const int f0 = fanrow[p], L = fanrow[p + 1] - f0;
+            int first = -1, prev = -1;
+            for (int q = 0; q < L; ++q) {
+                const int e = fan[f0 + q];
+                const int id = e & kFanId;
+                if (q == 0) first = id;
+                else if (!(e & kFanStart)) tri(prev, id);
+                prev = id;
+            }
+            if (L > 1 && (fan[f0] & kFanClosed)) tri(prev, first);
+        }
+        parent[p] = bq;
+        root[p] = bq;
+    });
+}
+
+// One round of pointer jumping: every vertex moves its pointer to its
+// pointer's pointer.  Pointers only ever move towards the roots, so reading a
+// neighbour's pointer before or after its update this round is equally
+// right; a chain of length c is resolved after ceil(log2 c) rounds.
+__global__ __launch_bounds__(kBlock) void k_jump(long long N, int* root) {
+    const long long gsz = (long long)gridDim.x * kBlock;
+    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
+        const int r = root[p];
+        if (r < 0) continue;
+        const int rr = root[r];
+        if (rr != r) root[p] = rr;
+    }
+}
+
+// Index in S of the source at each source position.
+__global__ __launch_bounds__(kBlock) void k_source_index(const MeshDesc* mesh, int B, const int* so,
+                                                         long long Stot, const int* S, const int* iperm,
+                                                         int* srcidx) {
+    for_tiles(so, B, Stot, [&](long long x, int b) {
+        const int s = (int)(x - so[b]);
+        srcidx[iperm[mesh[b].v_off + S[mesh[b].s_in + s]]] = s;
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_out(const MeshDesc* mesh, int B, const int* vo_prefix,
+                                                      long long N, const int* perm, const int* root,
+                                                      const int* srcidx, int* out_l) {
+    for_tiles(vo_prefix, B, N, [&](long long p, int b) {
+        const int r = root[p];
+        out_l[mesh[b].out_off + (perm[p] - mesh[b].v_off)] = r >= 0 ? srcidx[r] : -1;
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_parent_out(const MeshDesc* mesh, int B, const int* vo_prefix,
+                                                       long long N, const int* perm, const int* parent,
+                                                       int* out) {
+    for_tiles(vo_prefix, B, N, [&](long long p, int b) {
+        const int vo = mesh[b].v_off, q = parent[p];
+        out[mesh[b].out_off + (perm[p] - vo)] = q >= 0 ? perm[q] - vo : -1;
+    });
+}
+
+template <typename R, bool WARM, bool CACHE, bool RULES = false>
 const void* relax_fn() {
-    return reinterpret_cast<const void*>(&k_relax<R, LABELS, WARM, CACHE, RULES>);
+    return reinterpret_cast<const void*>(&k_relax<R, WARM, CACHE, RULES>);
+}
+
+int tile_grid(long long total) {
+    const long long t = (total + kTile - 1) / kTile;
+    return (int)std::max<long long>(1, std::min<long long>(8192, t));
 }
 
 }  // namespace
@@ -714,23 +765,41 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.N = p.N;
     a.out_d = p.out_d;
     a.out_d64 = p.out_d64;
-    a.out_l = p.out_l;
     void* args[] = {&a};
     const void* fn;
     const bool rules = p.band_rule != BAND_PAPER;
     if (f64)
-        fn = rules ? relax_fn<double, false, false, false, true>() : relax_fn<double, false, false, false>();
+        fn = rules ? relax_fn<double, false, false, true>() : relax_fn<double, false, false>();
     else if (rules)       // the other band rules: uncached, read at run time
-        fn = labels ? relax_fn<float, true, false, false, true>()
-                    : (p.upper ? relax_fn<float, false, true, false, true>()
-                               : relax_fn<float, false, false, false, true>());
-    else if (labels)
-        fn = cache ? relax_fn<float, true, false, true>() : relax_fn<float, true, false, false>();
+        fn = p.upper ? relax_fn<float, true, false, true>() : relax_fn<float, false, false, true>();
     else if (p.upper)
-        fn = cache ? relax_fn<float, false, true, true>() : relax_fn<float, false, true, false>();
+        fn = cache ? relax_fn<float, true, true>() : relax_fn<float, true, false>();
     else
-        fn = cache ? relax_fn<float, false, false, true>() : relax_fn<float, false, false, false>();
-    return hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
+        fn = cache ? relax_fn<float, false, true>() : relax_fn<float, false, false>();
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(g_run), dim3(kBlock), args, 0, st);
+    if (e != hipSuccess || !labels) return e;
+    // labels of the final map: parents (kept in the fill cursors of the
+    // prepare, free by now), pointer jumping, then the caller's order; root
+    // and source index live in the upper half of the distance region (the
+    // float run uses its lower half)
+    int* root = reinterpret_cast<int*>(w.dist + 2 * p.N);
+    int* srcidx = reinterpret_cast<int*>(w.dist + 3 * p.N);
+    const int gN = tile_grid(p.N);
+    hipLaunchKernelGGL(k_source_index, dim3(tile_grid(p.Stot)), dim3(kBlock), 0, st, w.mesh, p.B, w.so, p.Stot,
+                       p.S, w.iperm, srcidx);
+    hipLaunchKernelGGL(k_parents, dim3(gN), dim3(kBlock), 0, st, w.mesh, w.state, p.B, w.vo, p.N, w.perm,
+                       w.level, w.fanrow, w.fan, w.xyz, w.dist, w.cursor, root);
+    for (int r = 0; r < p.jump_rounds; ++r)
+        hipLaunchKernelGGL(k_jump, dim3(gN), dim3(kBlock), 0, st, p.N, root);
+    hipLaunchKernelGGL(k_label_out, dim3(gN), dim3(kBlock), 0, st, w.mesh, p.B, w.vo, p.N, w.perm, root, srcidx,
+                       p.out_l);
+    return hipGetLastError();
+}
+
+hipError_t launch_parents_out(const Work& w, int B, long long N, int* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_parent_out, dim3(tile_grid(N)), dim3(kBlock), 0, st, w.mesh, B, w.vo, N, w.perm,
+                       w.cursor, out);
+    return hipGetLastError();
 }
 
 namespace {
@@ -741,29 +810,23 @@ int blocks_per_cu(const void* fn) {
 }
 }  // namespace
 
-// Co-resident workgroups of the relaxation kernels a plan may launch: the
-// labelled one, or (without labels) the plain and the warm-start one; with
-// `cache`, the register-caching variants instead of the uncached ones; with
-// `rules` (a plan with another band rule), the run-time-rule variants.
-int max_coop_blocks_run(int cus, bool labels, bool cache, bool rules) {
+// Co-resident workgroups of the relaxation kernels a plan may launch (the
+// plain and the warm-start one; with `cache`, the register-caching variants;
+// with `rules`, the run-time-rule variants).
+int max_coop_blocks_run(int cus, bool cache, bool rules) {
     int nb;
-    if (rules) {
-        nb = labels ? blocks_per_cu(relax_fn<float, true, false, false, true>())
-                    : std::min(blocks_per_cu(relax_fn<float, false, false, false, true>()),
-                               blocks_per_cu(relax_fn<float, false, true, false, true>()));
-    } else if (labels) {
-        nb = blocks_per_cu(cache ? relax_fn<float, true, false, true>() : relax_fn<float, true, false, false>());
-    } else {
-        nb = std::min(
-            blocks_per_cu(cache ? relax_fn<float, false, false, true>() : relax_fn<float, false, false, false>()),
-            blocks_per_cu(cache ? relax_fn<float, false, true, true>() : relax_fn<float, false, true, false>()));
-    }
+    if (rules)
+        nb = std::min(blocks_per_cu(relax_fn<float, false, false, true>()),
+                      blocks_per_cu(relax_fn<float, true, false, true>()));
+    else
+        nb = std::min(blocks_per_cu(cache ? relax_fn<float, false, true>() : relax_fn<float, false, false>()),
+                      blocks_per_cu(cache ? relax_fn<float, true, true>() : relax_fn<float, true, false>()));
     return std::max(nb, 1) * cus;
 }
 
 int max_coop_blocks_run64(int cus, bool rules) {
-    return std::max(blocks_per_cu(rules ? relax_fn<double, false, false, false, true>()
-                                        : relax_fn<double, false, false, false>()),
+    return std::max(blocks_per_cu(rules ? relax_fn<double, false, false, true>()
+                                        : relax_fn<double, false, false>()),
                     1) * cus;
 }
 

@@ -42,7 +42,8 @@ __device__ inline bool wave_uniform(int b) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_edge_max(const float4* xyz, const int* row, const int2* wedge,
-                                                     const int* vo, int B, long long N,
+                                                     const int* perm, const int* iperm, const int* vo, int B,
+                                                     long long N,
                                                      unsigned long long* emax) {
     const long long gsz = (long long)gridDim.x * kBlock;
     const long long span = (N + gsz - 1) / gsz * gsz;          // every lane runs the same trips
@@ -52,8 +53,9 @@ __global__ __launch_bounds__(kBlock) void k_edge_max(const float4* xyz, const in
         float mx = 0.f;
         if (in) {
             const float4 x = xyz[p];
-            for (int e = row[p]; e < row[p + 1]; ++e) {
-                const float4 a = xyz[wedge[e].x];
+            const int v = perm[p];
+            for (int e = row[v]; e < row[v + 1]; ++e) {
+                const float4 a = xyz[iperm[wedge[e].x]];
                 mx = fmaxf(mx, len3(a.x - x.x, a.y - x.y, a.z - x.z));
             }
         }
@@ -68,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_max(const float4* xyz, const in
 }
 
 __global__ __launch_bounds__(kBlock) void k_edge_sum(const float4* xyz, const int* row, const int2* wedge,
-                                                     const int* vo, int B, long long N,
+                                                     const int* perm, const int* iperm, const int* vo, int B,
+                                                     long long N,
                                                      const unsigned long long* emax,
                                                      unsigned long long* acc) {
     const long long gsz = (long long)gridDim.x * kBlock;
@@ -82,8 +85,9 @@ __global__ __launch_bounds__(kBlock) void k_edge_sum(const float4* xyz, const in
             if (mx > 0.f) {
                 const double scale = 2147483648.0 / (double)mx;
                 const float4 x = xyz[p];
-                for (int e = row[p]; e < row[p + 1]; ++e) {
-                    const float4 a = xyz[wedge[e].x];
+                const int v = perm[p];
+                for (int e = row[v]; e < row[v + 1]; ++e) {
+                    const float4 a = xyz[iperm[wedge[e].x]];
                     s += (unsigned long long)llrint((double)len3(a.x - x.x, a.y - x.y, a.z - x.z) * scale);
                 }
             }
@@ -137,7 +141,8 @@ __device__ inline WedgeGeo wedge_geo(const float4 x, const float4 a, const float
 // Network inputs (x0, x1, x2) and the scale l per internal position; w = -1
 // marks positions with no feature (unreachable vertices).
 __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const int* row, const int2* wedge,
-                                                     const int* perm, const int* level, const int* vo,
+                                                     const int* perm, const int* iperm, const int* level,
+                                                     const int* vo,
                                                      const MeshDesc* mesh, const MeshState* state, int B,
                                                      long long N, float4* feat) {
     const long long gsz = (long long)gridDim.x * kBlock;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const in
         const int b = mesh_of(vo, B, p);
         const int v0 = mesh[b].v_off;
         const float l = state[b].mean_edge;
-        const int hop = level[perm[p]];
+        const int hop = level[perm[p]];   // by global vertex id
         if (hop < 0) {
             feat[p] = make_float4(0.f, 0.f, 0.f, -1.f);
             continue;
@@ -159,10 +164,11 @@ __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const in
         // The incidence order of a vertex's triangles is not fixed (it comes
         // from atomics), so the sums are taken in fixed point: a first pass
         // finds the largest magnitude, the second adds integers scaled to it.
-        const int e0 = row[p], e1 = row[p + 1];
+        const int v = perm[p];
+        const int e0 = row[v], e1 = row[v + 1];
         float mk = 0.f, mq = 0.f;
         for (int e = e0; e < e1; ++e) {
-            const WedgeGeo g = wedge_geo(x, xyz[wedge[e].x], xyz[wedge[e].y]);
+            const WedgeGeo g = wedge_geo(x, xyz[iperm[wedge[e].x]], xyz[iperm[wedge[e].y]]);
             mk = fmaxf(mk, fmaxf(fabsf(g.k.x), fmaxf(fabsf(g.k.y), fabsf(g.k.z))));
             mq = fmaxf(mq, fmaxf(g.dbl, fmaxf(fabsf(g.q.x), fmaxf(fabsf(g.q.y), fabsf(g.q.z)))));
         }
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_features(const float4* xyz, const in
         const double sq = mq > 0.f ? 4611686018427387904.0 / ((double)mq * deg) : 0.0;
         long long Kx = 0, Ky = 0, Kz = 0, Nx = 0, Ny = 0, Nz = 0, A = 0;
         for (int e = e0; e < e1; ++e) {
-            const WedgeGeo g = wedge_geo(x, xyz[wedge[e].x], xyz[wedge[e].y]);
+            const WedgeGeo g = wedge_geo(x, xyz[iperm[wedge[e].x]], xyz[iperm[wedge[e].y]]);
             Kx += llrint((double)g.k.x * sk);
             Ky += llrint((double)g.k.y * sk);
             Kz += llrint((double)g.k.z * sk);
@@ -470,14 +476,14 @@ hipError_t launch_features(const Work& w, const Sizes& z, hipStream_t st) {
     unsigned long long* acc = w.edge_acc;           // [B] sums, then [B] maxima
     unsigned long long* emax = w.edge_acc + z.B;
     hipLaunchKernelGGL(k_zero_u64, dim3((2 * z.B + 255) / 256), dim3(256), 0, st, acc, 2 * z.B);
-    hipLaunchKernelGGL(k_edge_max, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowN, w.wedge, w.vo, z.B, z.N,
-                       emax);
-    hipLaunchKernelGGL(k_edge_sum, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowN, w.wedge, w.vo, z.B, z.N,
-                       emax, acc);
-    hipLaunchKernelGGL(k_edge_mean, dim3((z.B + 255) / 256), dim3(256), 0, st, acc, emax, w.rowN, w.mesh,
+    hipLaunchKernelGGL(k_edge_max, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowO, w.wedgeO, w.perm, w.iperm,
+                       w.vo, z.B, z.N, emax);
+    hipLaunchKernelGGL(k_edge_sum, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowO, w.wedgeO, w.perm, w.iperm,
+                       w.vo, z.B, z.N, emax, acc);
+    hipLaunchKernelGGL(k_edge_mean, dim3((z.B + 255) / 256), dim3(256), 0, st, acc, emax, w.rowO, w.mesh,
                        z.B, w.state);
-    hipLaunchKernelGGL(k_features, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowN, w.wedge, w.perm, w.level,
-                       w.vo, w.mesh, w.state, z.B, z.N, w.feat);
+    hipLaunchKernelGGL(k_features, dim3(grid), dim3(kBlock), 0, st, w.xyz, w.rowO, w.wedgeO, w.perm, w.iperm,
+                       w.level, w.vo, w.mesh, w.state, z.B, z.N, w.feat);
     return hipGetLastError();
 }
 

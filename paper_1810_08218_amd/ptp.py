@@ -37,7 +37,7 @@ EXPORTS = ("ptp_plan_create", "ptp_workspace_bytes", "ptp_prepare", "ptp_run", "
            "ptp_batch_warm_predict", "ptp_batch_run_warm", "ptp_mlp_params", "ptp_mlp_apply",
            "ptp_mlp_scratch_bytes", "ptp_mlp_grad", "ptp_adam_step", "ptp_set_window",
            "ptp_batch_set_window", "ptp_run_f64", "ptp_batch_run_f64", "ptp_fps", "ptp_lloyd_step",
-           "ptp_solve_noalloc", "ptp_noalloc_scratch_bytes")
+           "ptp_solve_noalloc", "ptp_noalloc_scratch_bytes", "ptp_get_parents", "ptp_batch_get_parents")
 
 BAND_PAPER = 0          # PTP_BAND_PAPER: Eq. upper_band / Eq. lower_band
 BAND_FIXED_HALF = 1     # PTP_BAND_FIXED_HALF: [floor((k+1)/2), k], 2 rho - 3 iterations
@@ -128,6 +128,10 @@ def load() -> C.CDLL:
     lib.ptp_noalloc_scratch_bytes.restype = C.c_size_t
     lib.ptp_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.ptp_get_stats.restype = C.c_int
+    lib.ptp_get_parents.argtypes = [vp, vp, vp]
+    lib.ptp_get_parents.restype = C.c_int
+    lib.ptp_batch_get_parents.argtypes = [vp, vp, vp]
+    lib.ptp_batch_get_parents.restype = C.c_int
     lib.ptp_get_order.argtypes = [vp, vp, vp, vp]
     lib.ptp_get_order.restype = C.c_int
     lib.ptp_get_schedule.argtypes = [vp, vp]
@@ -440,6 +444,17 @@ class Plan:
     def n_toplesets(self) -> int:
         return int(self._lib.ptp_n_toplesets(self._h))
 
+    def parents(self, stream=None):
+        """Parents behind the labels of the last (labelled) run: int32 [n]
+        device tensor of caller vertex ids (a source its own id, -1 where
+        unreachable)."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        rc = self._lib.ptp_get_parents(self._h, _ptr(out), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_get_parents")
+        return out
+
     def order(self, stream=None):
         """(perm[n], offsets[rho + 1]) as int32 device tensors."""
         import torch
@@ -639,6 +654,17 @@ class Batch:
         status = (C.c_int32 * self.count)()
         rc = self._lib.ptp_batch_get_stats(self._h, st, status)
         return rc, [s.as_dict() for s in st], [int(x) for x in status]
+
+    def parents(self, stream=None):
+        """Parents behind the labels of the last (labelled) run: int32
+        [out_len] device tensor of local vertex ids, indexed like the
+        outputs."""
+        import torch
+        out = torch.empty(self.out_len, dtype=torch.int32, device="cuda")
+        rc = self._lib.ptp_batch_get_parents(self._h, _ptr(out), _stream(stream))
+        if rc != PTP_OK:
+            raise self._err(rc, "ptp_batch_get_parents")
+        return out
 
     def set_window(self, window: int):
         """Band cap for the following runs of every mesh (changes results)."""

@@ -8,8 +8,8 @@ results are bit-identical to the sequential one.
 
 Files (tests/golden/):
   bumpy_icosphere9_oracle_samples.npz   level-9 bumpy icosphere, 32 sources,
-      labels, tol 1e-4: 20,000 sampled vertices with their one-ring (distances
-      and labels), K, rho, U and the retirement schedule
+      tol 1e-4: distances at 20,000 sampled vertices, K, rho, U and the
+      retirement schedule
   bumpy_icosphere9_warm_dijkstra.npz    the same mesh without labels, started
       from float32(1.05 x Dijkstra distance): sampled distances, K, U, schedule
   batch_largest_oracle_samples.npz      the largest jittered grid (t = 95) and
@@ -38,26 +38,15 @@ def _sample(n, seed=12345, k=N_SAMPLES):
     return np.sort(rng.choice(n, min(k, n), replace=False)).astype(np.int64)
 
 
-def ring_of(F, idx):
-    """One-ring (the vertices sharing a triangle) of every sampled vertex, as
-    a flat sorted id list."""
-    want = np.zeros(int(F.max()) + 1, bool)
-    want[idx] = True
-    hit = want[F].any(axis=1)
-    return np.unique(F[hit].ravel()).astype(np.int64)
-
-
 def bumpy9():
     lib = O.load_omp()
     m = I.bumpy_icosphere(level=9, seed=3, n_sources=32)
     tol = 1e-4
     r = O.run(m.V, m.F, m.S, tol, lib=lib)
     idx = _sample(m.n)
-    ring = ring_of(m.F, idx)
     out = os.path.join(HERE, "bumpy_icosphere9_oracle_samples.npz")
     np.savez_compressed(
-        out, idx=idx, dist=r.dist[idx], label=r.label[idx], ring=ring, ring_dist=r.dist[ring],
-        ring_label=r.label[ring], iterations=np.int64(r.iterations), rho=np.int64(r.rho),
+        out, idx=idx, dist=r.dist[idx], iterations=np.int64(r.iterations), rho=np.int64(r.rho),
         updates=np.int64(r.updates), status=np.int64(r.status), retire_k=r.retire_k,
         trace_maxrel=r.trace_maxrel, tol=np.float64(tol),
         dist_max=np.float64(np.max(r.dist[np.isfinite(r.dist)])), dist_sum=np.float64(np.sum(r.dist)))

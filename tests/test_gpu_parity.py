@@ -8,8 +8,11 @@ Bars:
     (float32 arithmetic against the float64 oracle at the same iteration
     rule); sources exactly 0, unreachable vertices +inf on both sides;
   * distances are compared with the oracle replaying the GPU's schedule;
-  * labels: equal, except where two fronts offer the vertex distances within
-    1e-4 (relative) of each other; the rate of such cases is reported.
+  * labels (from the final map: each vertex takes the label of its parent,
+    the vertex its value comes from): the GPU's labels follow its parents
+    exactly, and a parent differs from the oracle's only where the two offer
+    the vertex updates within 1e-4 (relative) of each other; the rates are
+    reported.
 """
 import os
 
@@ -66,10 +69,10 @@ def check_parity(cuda, mesh, tol, labels=False, workgroups=0, max_iters=0, windo
     assert g.status == rp.status
     assert mx <= REL_TOL
     if labels:
-        n_bad = check_labels(mesh, g.label, rp.label, rp.dist)
+        n_lab, n_par = check_labels(mesh, g.label, g.parent, rp.dist)
         reach = np.isfinite(rp.dist).sum()
-        say(f"  label mismatches {n_bad} of {reach} (rate {n_bad / reach:.2e})")
-        assert (g.label[np.isinf(rp.dist)] == -1).all()
+        say(f"  label mismatches {n_lab}, parent mismatches (ties within 1e-4) {n_par} of {reach} "
+            f"(rates {n_lab / reach:.2e}, {n_par / reach:.2e})")
     return g, rp
 
 
@@ -284,36 +287,31 @@ SAMPLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                        "bumpy_icosphere9_oracle_samples.npz")
 
 
-def test_parity_bumpy_icosphere_9_sampled(cuda):
+def test_parity_bumpy_icosphere_9(cuda):
     """Full-size 32-source mesh in the benchmark's launch configuration,
-    against stored oracle values at 20,000 sampled vertices (written by
-    tests/golden/make_oracle_samples.py, which calls only the oracle), plus
-    the complete schedule, K, rho and U.  A sampled label that differs must be
-    offered within 1e-4 by the vertex's triangles under the oracle's map (the
-    file keeps the one-ring of every sample)."""
+    against the oracle's run of the whole mesh (its OpenMP build, bit-identical
+    to the sequential one): every distance, the schedule, K, rho and U, and
+    the labels through their parents.  The oracle's run is also held to the
+    values stored by tests/golden/make_oracle_samples.py (20,000 sampled
+    distances, K, rho, U and the schedule), so a change of the oracle shows."""
     ref = np.load(SAMPLES)
     m = I.bumpy_icosphere(level=9, seed=3, n_sources=32)
-    g = gpu_run(m, float(ref["tol"]), labels=True, want_order=False)
-    same = np.array_equal(g.retire, ref["retire_k"])
+    tol = float(ref["tol"])
+    o = O.run(m.V, m.F, m.S, tol, lib=O.load_omp())
     idx = ref["idx"]
-    mx, mean = rel_errors(g.dist[idx], ref["dist"], np.nonzero(np.isin(idx, m.S))[0])
-    say(f"  K {g.iterations}/{int(ref['iterations'])} rho {g.rho}/{int(ref['rho'])} "
-        f"U {g.updates}/{int(ref['updates'])} same schedule {same} max rel {mx:.3e} mean {mean:.3e}")
-    assert g.rho == int(ref["rho"])
-    assert same and g.iterations == int(ref["iterations"]) and g.updates == int(ref["updates"])
+    assert np.array_equal(o.dist[idx], ref["dist"]) and np.array_equal(o.retire_k, ref["retire_k"])
+    assert (o.iterations, o.rho, o.updates) == (int(ref["iterations"]), int(ref["rho"]), int(ref["updates"]))
+    g = gpu_run(m, tol, labels=True, want_order=False)
+    same = np.array_equal(g.retire, o.retire_k)
+    mx, mean = rel_errors(g.dist, o.dist, m.S)
+    say(f"  K {g.iterations}/{o.iterations} rho {g.rho}/{o.rho} U {g.updates}/{o.updates} "
+        f"same schedule {same} max rel {mx:.3e} mean {mean:.3e}")
+    assert g.rho == o.rho
+    assert same and g.iterations == o.iterations and g.updates == o.updates
     assert mx <= REL_TOL
     assert (g.dist[m.S] == 0).all() and np.isfinite(g.dist).all()
-    od = np.full(m.n, np.inf)
-    ol = np.full(m.n, -1, np.int32)
-    od[ref["ring"]] = ref["ring_dist"]
-    ol[ref["ring"]] = ref["ring_label"]
-    gl = np.full(m.n, -1, np.int32)
-    gl[idx] = g.label[idx]
-    ol_s = np.full(m.n, -1, np.int32)
-    ol_s[idx] = ref["label"]
-    sub = I.Mesh(m.V, m.F[np.isin(m.F, idx).any(axis=1)], m.S, name="ring")
-    n_bad = check_labels(sub, gl, ol_s, od)
-    say(f"  sampled label mismatches {n_bad} of {idx.size}")
+    n_lab, n_par = check_labels(m, g.label, g.parent, o.dist)
+    say(f"  label mismatches {n_lab}, parent mismatches (ties within 1e-4) {n_par} of {m.n}")
 
 
 WARM_SAMPLES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
