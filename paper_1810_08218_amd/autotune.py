@@ -21,15 +21,19 @@ CACHE = os.environ.get("PTP_SCHEDULE_CACHE",
 # The schedule the tuner picked for the 512-mesh workload (jittered grids of
 # side 32..1024 and tori 2^k x 2^(k-1), 1-4 sources, 71M vertices) on MI355X;
 # the benchmark times the batch with it and the tests check results with it.
-BATCH512_SCHEDULE = dict(workgroups=1024, small_limit=65536, large_limit=524288, medium_group=16,
-                         large_group=96)
+BATCH512_SCHEDULE = dict(workgroups=1024, small_limit=32768, large_limit=524288, medium_group=16,
+                         large_group=32)
 
 
 def candidates() -> list:
+    """Work distributions to try: size classes and group sizes.  Groups of up
+    to 32 workgroups run on one XCD; the mesh queues let a group that runs out
+    of its class's meshes take smaller ones, so larger classes may get more
+    groups than their share."""
     out = []
-    for G in (512, 1024):
-        for sl, ll in ((8192, 131072), (32768, 262144), (65536, 524288)):
-            for mg, lg in ((4, 16), (8, 32), (16, 64), (16, 96), (32, 128)):
+    for G in (768, 1024):
+        for sl, ll in ((16384, 262144), (32768, 524288), (65536, 524288)):
+            for mg, lg in ((8, 32), (16, 32), (16, 48), (16, 64), (32, 96)):
                 out.append(dict(workgroups=G, small_limit=sl, large_limit=ll, medium_group=mg,
                                 large_group=lg))
     return out

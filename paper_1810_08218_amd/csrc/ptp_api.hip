@@ -32,27 +32,46 @@ struct Sched {
     int ngroups = 0;
     std::vector<WgInfo> wg;      // [G]
     std::vector<int> glist;      // starts [ngroups + 1] (absolute), then mesh ids
-    std::vector<int> gsize_of;   // [B] group size that handles each mesh
+    std::vector<int> gsize_of;   // [B] group size of each mesh's class
+    // the same assignment as queues the groups take meshes from at run time:
+    // [4] starts of the class lists (small, medium, large) and their end,
+    // [ngroups] class of each group, then the class lists, each ordered by
+    // decreasing estimated time
+    std::vector<int> queue;
 };
 
-// Seconds for one mesh on a group of s workgroups: rho dependent iterations of
-// a few microseconds each, plus the band work spread over the group (about
-// 4 n vertex updates at ~8 ns per update per workgroup).  Only the relative
-// size matters: it drives the assignment, the results never depend on it.
+// Seconds of the BFS of a mesh of n vertices and rho toplesets on a group of
+// s workgroups: a level costs a group barrier and a few round trips.  Only
+// the relative size matters: it drives the assignment, the results never
+// depend on it.
 double est_time(long long n, long long rho, int s) {
     return (double)rho * 5e-6 + 4.0 * (double)n * 8e-9 / (double)s;
 }
 
-Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long long>& rho,
-                    const ptp_schedule& p, int gmax, bool single, int single_g) {
+// Relaxation time of a mesh with K iterations and U vertex updates on a
+// group of s workgroups, from measured runs on the 512-mesh batch: a group
+// iteration costs ~1.6 us on one workgroup and ~6.5 us on several (barrier,
+// controller), and a thread takes ~3 us per band vertex it owns.  Without a
+// measured run, K ~ 1.2 rho and U ~ 0.2 n rho stand in.
+double est_run(double K, double U, int s) {
+    return K * (s == 1 ? 1.6e-6 : 6.5e-6) + 3e-6 * U / (256.0 * s);
+}
+
+using CostFn = std::function<double(int, int)>;   // (mesh, group size) -> seconds
+
+Sched make_schedule(const std::vector<MeshDesc>& mesh, const CostFn& est, const ptp_schedule& p, int gmax,
+                    bool single, int single_g) {
     Sched s;
     const int B = (int)mesh.size();
     s.gsize_of.assign(B, 1);
     std::vector<std::vector<int>> groups;
-    std::vector<int> gsz;
+    std::vector<int> gsz, gclass;
+    std::vector<int> qlists[3];
     if (single) {
         groups.push_back({0});
         gsz.push_back(std::max(1, std::min(single_g, gmax)));
+        gclass.push_back(0);
+        qlists[0] = {0};
         s.gsize_of[0] = gsz[0];
     } else {
         const int G = std::max(1, std::min(p.workgroups, gmax));
@@ -83,7 +102,7 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
         }
         double C[3] = {0, 0, 0};
         for (int c = 0; c < 3; ++c)
-            for (int b : members[c]) C[c] += est_time(mesh[b].n, rho[b], size_c[c]);
+            for (int b : members[c]) C[c] += est(b, size_c[c]);
         // hand out the remaining workgroups to the class with the largest load per group
         for (;;) {
             int best = -1;
@@ -106,13 +125,13 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
             if (members[c].empty()) continue;
             std::vector<int> ord = members[c];
             const int sc = size_c[c];
-            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-                return est_time(mesh[x].n, rho[x], sc) > est_time(mesh[y].n, rho[y], sc);
-            });
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return est(x, sc) > est(y, sc); });
+            qlists[c] = ord;
             const int first = (int)groups.size();
             for (int g = 0; g < ng[c]; ++g) {
                 groups.emplace_back();
                 gsz.push_back(sc);
+                gclass.push_back(c);
             }
             using Item = std::pair<double, int>;
             std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
@@ -121,7 +140,7 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
                 Item it = heap.top();
                 heap.pop();
                 groups[it.second].push_back(b);
-                it.first += est_time(mesh[b].n, rho[b], sc);
+                it.first += est(b, sc);
                 heap.push(it);
                 s.gsize_of[b] = sc;
             }
@@ -137,6 +156,10 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const std::vector<long lo
     s.glist[s.ngroups] = pos;
     for (int g = 0; g < s.ngroups; ++g)
         for (int b : groups[g]) s.glist.push_back(b);
+    s.queue.assign(4, 0);
+    for (int c = 0; c < 3; ++c) s.queue[c + 1] = s.queue[c] + (int)qlists[c].size();
+    for (int g = 0; g < s.ngroups; ++g) s.queue.push_back(gclass[g]);
+    for (int c = 0; c < 3; ++c) s.queue.insert(s.queue.end(), qlists[c].begin(), qlists[c].end());
     // Workgroup slots.  Consecutive launch indices go to the 8 XCDs in turn
     // (index i runs on XCD i mod 8), and each XCD has its own L2, so a group
     // placed on one XCD exchanges its data and barrier lines through one L2.
@@ -227,9 +250,9 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(MeshDesc) * B,                  // mesh
         sizeof(MeshState) * B,                 // state
         sizeof(WgInfo) * G,                    // wg_prep
-        sizeof(int) * (G + 1 + B),             // glist_prep
+        sizeof(int) * (G + 8 + B),             // glist_prep
         sizeof(WgInfo) * G,                    // wg_run
-        sizeof(int) * (G + 1 + B),             // glist_run
+        sizeof(int) * (G + 8 + B),             // glist_run
         sizeof(int) * (B + 1),                 // vo
         sizeof(int) * (B + 1),                 // fo3
         sizeof(int) * (B + 1),                 // so
@@ -260,7 +283,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * (2 * F3 + 1),            // fan
         sizeof(int) * kEll * N,                // ellO
         sizeof(WgInfo) * G,                    // wg_run64
-        sizeof(int) * (G + 1 + B),             // glist_run64
+        sizeof(int) * (G + 8 + B),             // glist_run64
         sizeof(double) * (size_t)z.S * (kCvtChunks * 6 + 4),   // cvt partial sums, centroids
     };
     size_t off = 0;
@@ -323,8 +346,11 @@ struct Solver {
     Sizes z{};
     ptp_options opt{};
     bool single = false;
-    int device = 0, cus = 0, max_prep = 0, max_run = 0, max_run64 = 0, lds_max = 0;
-    std::vector<int> lds_list, grid_list;   // meshes of the one-workgroup / grid BFS
+    int device = 0, cus = 0, max_prep = 0, max_run = 0, max_run64 = 0, lds_max = 0, big_max = 0;
+    // meshes of the one-workgroup BFS (the larger ones, n_big of them, first;
+    // each part by decreasing size) and of the grid BFS
+    std::vector<int> lds_list, grid_list;
+    int n_big = 0;
     ptp_schedule sched{};
     Sched s_prep, s_run, s_run64;
     bool sched64_ready = false;             // s_run64 uploaded for the current prepare
@@ -338,6 +364,7 @@ struct Solver {
     const float* Vp = nullptr;
     const int32_t* Fp = nullptr;
     std::vector<MeshState> hstate;
+    std::vector<long long> meas_K, meas_U, meas_rho;   // the last run's K, U and rho per mesh
     bool prepared = false, ran = false;
     bool parents_valid = false;         // the last run computed labels (and parents)
     std::string err;
@@ -416,18 +443,33 @@ struct Solver {
         const bool rules = opt.band_rule != PTP_BAND_PAPER;
         max_run = max_coop_blocks_run(cus, single, rules);
         max_run64 = max_coop_blocks_run64(cus, rules);
-        lds_max = opt.lds_bfs_max < 0 ? 0 : bfs_lds_max_vertices(device);
-        if (opt.lds_bfs_max > 0) lds_max = std::min(lds_max, opt.lds_bfs_max);
-        long long lds_words = 0;
+        if (opt.lds_bfs_max >= 0) bfs_one_limits(device, &lds_max, &big_max);
+        if (opt.lds_bfs_max > 0) {
+            lds_max = std::min(lds_max, opt.lds_bfs_max);
+            big_max = std::min(big_max, opt.lds_bfs_max);
+        }
+        long long lds_words = 0, big_words = 0;
+        std::vector<int> small_one;
         for (int b = 0; b < count; ++b) {
+            const long long words = (mesh[b].n + 31) / 32;
             if (mesh[b].n <= lds_max) {
+                small_one.push_back(b);
+                lds_words = std::max(lds_words, words);
+            } else if (mesh[b].n <= big_max) {
                 lds_list.push_back(b);
-                lds_words = std::max<long long>(lds_words, (mesh[b].n + 31) / 32);
+                big_words = std::max(big_words, words);
             } else {
                 grid_list.push_back(b);
             }
         }
+        // largest first: the workgroups of a launch start in index order
+        auto by_size = [&](int x, int y) { return mesh[x].n > mesh[y].n; };
+        std::stable_sort(lds_list.begin(), lds_list.end(), by_size);
+        std::stable_sort(small_one.begin(), small_one.end(), by_size);
+        n_big = (int)lds_list.size();
+        lds_list.insert(lds_list.end(), small_one.begin(), small_one.end());
         z.lds_words = lds_words;
+        z.big_words = big_words;
         z.N = N;
         z.F = F;
         z.S = Sn;
@@ -443,9 +485,9 @@ struct Solver {
         ptp_schedule p;
         p.workgroups = std::min(max_run, 4 * cus);
         p.small_limit = 32768;
-        p.large_limit = 262144;
-        p.medium_group = 4;
-        p.large_group = 16;
+        p.large_limit = 524288;
+        p.medium_group = 16;
+        p.large_group = 32;
         p.xcd_pack = 1;
         return p;
     }
@@ -473,6 +515,28 @@ struct Solver {
         long long g = reach / 1536;
         g = g <= 48 ? 32 : std::min(512ll, g);
         return (int)std::min<long long>(g, gmax);
+    }
+
+    // Relaxation time estimate of each mesh for the scheduler: from the K and
+    // U of the last run of the same batch when that run saw the same number
+    // of toplesets (the same mesh and sources, most likely), else from rho
+    // and n.  The schedule only orders and places the work; results never
+    // depend on it.
+    CostFn run_cost(const std::vector<long long>& rho) const {
+        return [this, &rho](int b, int sz) {
+            if (b < (int)meas_rho.size() && meas_rho[b] == rho[b] && meas_K[b] > 0)
+                return est_run((double)meas_K[b], (double)meas_U[b], sz);
+            return est_run(1.2 * (double)rho[b], 0.2 * (double)mesh[b].n * (double)rho[b], sz);
+        };
+    }
+
+    // The run launches take their meshes from the queues (Sched::queue).
+    hipError_t upload_run(const Sched& s, WgInfo* dwg, int* dq) {
+        hipError_t e = hipMemcpyAsync(dwg, s.wg.data(), sizeof(WgInfo) * s.wg.size(), hipMemcpyHostToDevice,
+                                      stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dq, s.queue.data(), sizeof(int) * s.queue.size(), hipMemcpyHostToDevice, stream);
+        return e;
     }
 
     hipError_t upload(const Sched& s, WgInfo* dwg, int* dgl) {
@@ -519,8 +583,8 @@ struct Solver {
             ps.large_limit = 0x7fffffff;         // every mesh in one class
             ps.medium_group = std::max(1, std::min(32, max_prep / (int)grid_list.size()));
             ps.xcd_pack = 1;
-            s_prep = make_schedule(gm, rho_est, ps, max_prep, grid_list.size() == 1,
-                                   std::min(cus, max_prep));
+            s_prep = make_schedule(gm, [&](int b, int sz) { return est_time(gm[b].n, rho_est[b], sz); }, ps,
+                                   max_prep, grid_list.size() == 1, std::min(cus, max_prep));
             for (size_t x = s_prep.ngroups + 1; x < s_prep.glist.size(); ++x)
                 s_prep.glist[x] = grid_list[s_prep.glist[x]];
         }
@@ -543,7 +607,7 @@ struct Solver {
             e = hipMemcpyAsync(work.lds_mesh, lds_list.data(), sizeof(int) * lds_list.size(),
                                hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return hip_fail(e, "prepare upload");
-        e = launch_prepare(work, z, dV, dF, dS, s_prep.G, (int)lds_list.size(), stream);
+        e = launch_prepare(work, z, dV, dF, dS, s_prep.G, (int)lds_list.size(), n_big, stream);
         if (e != hipSuccess) return hip_fail(e, "prepare launch");
         if (timed) {
             e = hipEventRecord(ev[1], stream);
@@ -575,8 +639,8 @@ struct Solver {
             rho[b] = x.rho;
             reach += x.reach;
         }
-        s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
-        e = upload(s_run, work.wg_run, work.glist_run);
+        s_run = make_schedule(mesh, run_cost(rho), sched, max_run, single, single_group(max_run, reach));
+        e = upload_run(s_run, work.wg_run, work.glist_run);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "schedule upload");
         prepared = true;
@@ -598,8 +662,8 @@ struct Solver {
             rho[b] = hstate[b].rho;
             reach += hstate[b].reach;
         }
-        s_run64 = make_schedule(mesh, rho, sched, max_run64, single, single_group(max_run64, reach));
-        hipError_t e = upload(s_run64, work.wg_run64, work.glist_run64);
+        s_run64 = make_schedule(mesh, run_cost(rho), sched, max_run64, single, single_group(max_run64, reach));
+        hipError_t e = upload_run(s_run64, work.wg_run64, work.glist_run64);
         if (e != hipSuccess) return hip_fail(e, "schedule upload");
         sched64_ready = true;
         return PTP_OK;
@@ -637,6 +701,7 @@ struct Solver {
         rp.out_d64 = dDist64;
         rp.out_l = labels ? dLabel : nullptr;
         rp.Stot = z.S;
+        rp.ngroups = f64 ? s_run64.ngroups : s_run.ngroups;
         int nmax = 1;
         for (const MeshDesc& md : mesh) nmax = std::max(nmax, md.n);
         rp.jump_rounds = 1;
@@ -695,7 +760,7 @@ struct Solver {
             e = launch_fps_pick(work, dDist, n, dS, slot, dRadius ? dRadius + (slot - n0) : nullptr,
                                 reinterpret_cast<long long*>(step), stream);
             if (e == hipSuccess)
-                e = launch_prepare_bfs(work, z, dV, dS, s_prep.G, (int)lds_list.size(), stream);
+                e = launch_prepare_bfs(work, z, dV, dS, s_prep.G, (int)lds_list.size(), n_big, stream);
             if (e != hipSuccess) break;
         }
         if (e == hipSuccess) e = hipMemcpyAsync(h_ctrl, work.ctrl, sizeof(int) * 8, hipMemcpyDeviceToHost, stream);
@@ -753,6 +818,15 @@ struct Solver {
         if (e != hipSuccess) return hip_fail(e, "stats");
         float ms_run = -1.f;
         if (run_timed && hipEventElapsedTime(&ms_run, ev[2], ev[3]) != hipSuccess) ms_run = -1.f;
+        meas_K.assign(z.B, 0);
+        meas_U.assign(z.B, 0);
+        meas_rho.assign(z.B, -1);
+        for (int b = 0; b < z.B; ++b)
+            if (!h_ctrl[C_ABORT] && !hstate[b].status && !hstate[b].runstat) {
+                meas_K[b] = hstate[b].iters;
+                meas_U[b] = hstate[b].updates;
+                meas_rho[b] = hstate[b].rho;
+            }
         long long t0 = 0;
         for (int b = 0; b < z.B; ++b)
             if (hstate[b].t_begin && (!t0 || hstate[b].t_begin < t0)) t0 = hstate[b].t_begin;
@@ -768,7 +842,7 @@ struct Solver {
                 out[b].iterations = x.iters;
                 out[b].n_toplesets = x.rho;
                 out[b].reachable = x.reach;
-                out[b].workgroups = s_run.gsize_of[b];
+                out[b].workgroups = x.wgs > 0 ? x.wgs : s_run.gsize_of[b];
                 out[b].vertex_updates = x.updates;
                 out[b].certify_rounds = x.cert_rounds;
                 out[b].certify_rejected = x.cert_rejected;
@@ -808,8 +882,8 @@ struct Solver {
         ptp_status rc = PTP_OK;
         for (int c = 0; c < n && rc == PTP_OK; ++c) {
             set_schedule(&cand[c]);
-            s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
-            hipError_t e = upload(s_run, work.wg_run, work.glist_run);
+            s_run = make_schedule(mesh, run_cost(rho), sched, max_run, single, single_group(max_run, reach));
+            hipError_t e = upload_run(s_run, work.wg_run, work.glist_run);
             if (e != hipSuccess) {
                 rc = hip_fail(e, "schedule upload");
                 break;
@@ -844,8 +918,8 @@ struct Solver {
             return rc;
         }
         set_schedule(&cand[bi]);
-        s_run = make_schedule(mesh, rho, sched, max_run, single, single_group(max_run, reach));
-        hipError_t e = upload(s_run, work.wg_run, work.glist_run);
+        s_run = make_schedule(mesh, run_cost(rho), sched, max_run, single, single_group(max_run, reach));
+        hipError_t e = upload_run(s_run, work.wg_run, work.glist_run);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "schedule upload");
         if (best) *best = bi;

@@ -23,6 +23,7 @@ enum CtrlWord : int {
     C_UPD_HI = 6,
     C_ABORT = 7,         // a barrier timed out
     C_FPS_KEY = 8,       // words 8, 9: farthest point sampling argmax key (64 bits)
+    C_QHEAD = 12,        // words 12..14: next entry of each mesh queue of the relaxation
     C_WORDS = 64
 };
 

@@ -31,6 +31,8 @@ struct MeshState {         // per mesh, written by the kernels
     int cert_rejected;     // warm start: bounds withdrawn by the certification
     long long t_begin;     // device wall clock (100 MHz ticks) when the group
     long long t_end;       //   started / finished this mesh's iteration
+    int wgs;               // workgroups of the group that ran it
+    int pad2;
 };
 
 struct WgInfo {            // per workgroup of a persistent launch
@@ -43,9 +45,9 @@ struct Work {
     MeshDesc* mesh;     // [B]
     MeshState* state;   // [B]
     WgInfo* wg_prep;    // [gmax]  group layout of the BFS launch
-    int* glist_prep;    // [gmax + 1 + B] per-group mesh lists (CSR: starts then ids)
+    int* glist_prep;    // [gmax + 8 + B] per-group mesh lists (CSR: starts then ids)
     WgInfo* wg_run;     // [gmax]  group layout of the relaxation launch
-    int* glist_run;     // [gmax + 1 + B]
+    int* glist_run;     // [gmax + 8 + B] mesh queues of the relaxation launch (Sched::queue)
     int* vo;            // [B + 1] internal vertex prefix (mesh of a position / vertex)
     int* fo3;           // [B + 1] 3 * internal face prefix (mesh of a face corner)
     int* so;            // [B + 1] internal source prefix (mesh of a source)
@@ -74,7 +76,7 @@ struct Work {
     int* fan;           // [6F]    fans of the incident triangles, positions and flags
     int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
     WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation
-    int* glist_run64;   // [gmax + 1 + B]
+    int* glist_run64;   // [gmax + 8 + B]
     double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
 };
 
@@ -107,7 +109,8 @@ struct Sizes {
     long long N, F, S;      // internal totals over the batch
     int B;                  // meshes
     long long W;            // bitmap words (sum over meshes)
-    long long lds_words;    // largest bitmap (words) among the one-workgroup BFS meshes
+    long long lds_words;    // largest bitmap (words) among the meshes of the one-workgroup LDS BFS
+    long long big_words;    // the same among the larger one-workgroup BFS meshes (frontier in memory)
     int gmax;               // largest persistent grid
 };
 
@@ -120,12 +123,13 @@ size_t work_layout(const Sizes& z, Layout* L);
 Work carve(void* base, const Layout& L);
 
 // prepare: every kernel after validation is gated on the batch status word
-// n_lds meshes (ids in w.lds_mesh) take the one-workgroup LDS BFS, the
-// others the persistent grid BFS on g_prep workgroups (0: none).
+// n_one meshes (ids in w.lds_mesh, the n_big larger ones first) take the
+// one-workgroup BFS, the others the persistent grid BFS on g_prep
+// workgroups (0: none).
 hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
-                          const int* S, int g_prep, int n_lds, hipStream_t st);
-size_t bfs_lds_bytes(long long words);
-int bfs_lds_max_vertices(int device);
+                          const int* S, int g_prep, int n_one, int n_big, hipStream_t st);
+size_t bfs_one_bytes(long long lds_words, long long big_words);
+void bfs_one_limits(int device, int* lds_max, int* big_max);
 
 // zero the barrier lines (two banks of one per workgroup) of a launch
 void launch_barrier_reset(const Work& w, int lines, hipStream_t st);
@@ -150,6 +154,7 @@ struct RunParams {
     int* out_l;                  // labels (caller order), or null
     long long Stot;              // sources over the batch (labels)
     int jump_rounds;             // pointer-jumping rounds of the labels: ceil(log2(largest n)) + 1
+    int ngroups;                 // groups of the launch (their classes head the queue array)
 };
 
 // cache: use the register-caching relaxation (single meshes); f64: the
@@ -185,7 +190,7 @@ int max_coop_blocks_run64(int cus, bool rules);
 hipError_t launch_fps_pick(const Work& w, const float* dist, int n, int* S, int slot, float* radius,
                            long long* step_stats, hipStream_t st);
 hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, const int* S, int g_prep,
-                              int n_lds, hipStream_t st);
+                              int n_one, int n_big, hipStream_t st);
 
 // Lloyd step on Voronoi labels: cell moments over the faces, centroids, the
 // nearest vertex of each cell

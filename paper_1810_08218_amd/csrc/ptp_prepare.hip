@@ -397,7 +397,9 @@ constexpr int kLdsList = 4096;
 constexpr int kExpand = 8;     // wedges loaded together per expanded vertex
 
 struct BfsLdsArgs {
-    const int* lmesh;      // mesh ids, one per workgroup
+    const int* lmesh;      // mesh ids, one per workgroup: the n_big large ones first
+    int n_big;
+    unsigned* bits;        // frontier bitmaps in global memory (large meshes)
     const MeshDesc* mesh;
     MeshState* state;
     const int* S;
@@ -411,8 +413,7 @@ struct BfsLdsArgs {
     int* ctrl;
 };
 
-__global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
-    if (gated(a.ctrl)) return;
+__device__ void bfs_lds(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
     const int b = a.lmesh[blockIdx.x];
@@ -559,6 +560,226 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_lds(BfsLdsArgs a) {
     }
 }
 
+// ---- BFS of one larger mesh in one workgroup -----------------------------
+// For a mesh whose visited bitmap fits in LDS but whose next-topleset bitmap
+// and rank table do not: the next topleset is a bitmap in global memory
+// (this workgroup's share of the frontier bitmaps, served from L2), and a
+// summary bitmap in LDS marks its non-empty words, so a level visits only the
+// words that hold vertices instead of scanning the whole bitmap.  Per level:
+// the non-empty words are staged in ascending order in rounds of kBigWl (word,
+// its bits, the rank of its first vertex), each vertex is found by a binary
+// search over the ranks (one vertex per thread), emitted in canonical order,
+// then the level is cleared and expanded as in bfs_lds, the new vertices'
+// bits set with global atomics (their summary bits with LDS atomics).
+constexpr int kBigWl = 2048;
+
+__device__ inline int kth_bit(unsigned w, int k) {
+    int bit = 0;
+    for (int step = 16; step >= 1; step >>= 1) {
+        const unsigned low = w & ((1u << step) - 1u);
+        const int c = __popc(low);
+        if (k >= c) {
+            k -= c;
+            w >>= step;
+            bit += step;
+        } else {
+            w = low;
+        }
+    }
+    return bit;
+}
+
+__device__ void bfs_big(const BfsLdsArgs& a) {
+    extern __shared__ unsigned lds[];
+    const int tid = threadIdx.x;
+    const int b = a.lmesh[blockIdx.x];
+    const MeshDesc d = a.mesh[b];
+    const int n = d.n, vo = d.v_off;
+    const int W = (n + 31) / 32, SW = (W + 31) / 32;
+    unsigned* vis = lds;                                         // [W]
+    unsigned* summ = lds + W;                                    // [SW]
+    int* wl = reinterpret_cast<int*>(summ + SW);                 // [kBigWl]
+    int* wpre = wl + kBigWl;                                     // [kBigWl + 1]
+    unsigned* wv = reinterpret_cast<unsigned*>(wpre + kBigWl + 1);   // [kBigWl]
+    unsigned* nxt = a.bits + 2ll * d.w_off;                      // [W], global
+    int* offs = a.offsets + vo + b;
+    for (int x = tid; x < W; x += kLdsBlock) {
+        vis[x] = 0u;
+        nxt[x] = 0u;
+    }
+    for (int x = tid; x < SW; x += kLdsBlock) summ[x] = 0u;
+    wait_memory();                                               // cleared before the atomics
+    __syncthreads();
+    unsigned dup = 0;
+    for (int s = tid; s < d.m; s += kLdsBlock) {
+        const int v = a.S[d.s_in + s];
+        const unsigned bit = 1u << (v & 31);
+        if (atomicOr(vis + (v >> 5), bit) & bit) {
+            dup = 1;
+        } else {
+            atomicOr(nxt + (v >> 5), bit);
+            atomicOr(summ + (v >> 10), 1u << ((v >> 5) & 31));
+        }
+    }
+    wait_memory();
+    if (__syncthreads_or(dup)) {
+        if (tid == 0) {
+            atomicOr(&a.state[b].status, ST_DUP_SOURCE);
+            atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
+        }
+        return;
+    }
+    const int sq = (SW + kLdsBlock - 1) / kLdsBlock;
+    const int s0 = min(tid * sq, SW), s1 = min(s0 + sq, SW);
+    int base = 0, r = 0;
+    for (;; ++r) {
+        int nw = 0;
+        for (int x = s0; x < s1; ++x) nw += __popc(summ[x]);
+        int totw;
+        const int wbase = block_exclusive_scan_n<kLdsBlock, int, true>(nw, &totw);
+        if (totw == 0) break;
+        if (tid == 0) offs[r] = base;
+        int total = 0;
+        for (int w0 = 0; w0 < totw; w0 += kBigWl) {
+            const int cnt = min(kBigWl, totw - w0);
+            int k = wbase;
+            for (int x = s0; x < s1 && k < w0 + kBigWl; ++x) {
+                unsigned sm = summ[x];
+                while (sm) {
+                    const int w = x * 32 + __ffs(sm) - 1;
+                    sm &= sm - 1;
+                    if (k >= w0 && k < w0 + kBigWl) wl[k - w0] = w;
+                    ++k;
+                }
+            }
+            lds_barrier();
+            // the staged words' bits: coherent loads (the expansion's atomics
+            // completed in L2 before the last barrier)
+            const unsigned v0 = tid < cnt ? ld_c(nxt + wl[tid]) : 0u;
+            const unsigned v1 = tid + kLdsBlock < cnt ? ld_c(nxt + wl[tid + kLdsBlock]) : 0u;
+            int t0, t1;
+            const int p0 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v0), &t0);
+            const int p1 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v1), &t1);
+            if (tid < cnt) {
+                wpre[tid] = p0;
+                wv[tid] = v0;
+            }
+            if (tid + kLdsBlock < cnt) {
+                wpre[tid + kLdsBlock] = t0 + p1;
+                wv[tid + kLdsBlock] = v1;
+            }
+            const int tv = t0 + t1;
+            if (tid == 0) wpre[cnt] = tv;
+            lds_barrier();
+            for (int t = tid; t < tv; t += kLdsBlock) {
+                int lo = 0, hi = cnt;               // wpre[lo] <= t < wpre[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (wpre[mid] <= t) lo = mid;
+                    else hi = mid;
+                }
+                const int u = wl[lo] * 32 + kth_bit(wv[lo], t - wpre[lo]);
+                const int pos = base + total + t;
+                a.perm[vo + pos] = vo + u;
+                a.iperm[vo + u] = vo + pos;
+                a.level[vo + u] = r;
+            }
+            total += tv;
+            lds_barrier();                          // the stage is rewritten by the next round
+        }
+        // clear the level's words (global) and its summary
+        for (int x = s0; x < s1; ++x) {
+            unsigned sm = summ[x];
+            while (sm) {
+                nxt[x * 32 + __ffs(sm) - 1] = 0u;
+                sm &= sm - 1;
+            }
+            summ[x] = 0u;
+        }
+        wait_memory();                              // perm stores and cleared words landed
+        __syncthreads();
+        for (int t = tid; t < total; t += kLdsBlock) {
+            const int u = ld_c(a.perm + vo + base + t) - vo;
+            const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + u));
+            const int4 r0 = er[0], r1 = er[1];
+            const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+            if (ev[kEll - 1] != kEllMore) {
+#pragma unroll
+                for (int q = 0; q < kEll; ++q) {
+                    if (ev[q] < 0) continue;
+                    const int x = ev[q] - vo;
+                    const unsigned bit = 1u << (x & 31);
+                    if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
+                        atomicOr(nxt + (x >> 5), bit);
+                        atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
+                    }
+                }
+                continue;
+            }
+            const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
+            for (int eb = e0; eb < e1; eb += kExpand) {
+                const int cnt = min(kExpand, e1 - eb);
+                int2 nb[kExpand];
+#pragma unroll
+                for (int q = 0; q < kExpand; ++q) nb[q] = q < cnt ? a.wedgeO[eb + q] : make_int2(vo + u, vo + u);
+#pragma unroll
+                for (int q = 0; q < kExpand; ++q) {
+                    const int xs[2] = {nb[q].x - vo, nb[q].y - vo};
+                    for (int z = 0; z < 2; ++z) {
+                        const int x = xs[z];
+                        const unsigned bit = 1u << (x & 31);
+                        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
+                            atomicOr(nxt + (x >> 5), bit);
+                            atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
+                        }
+                    }
+                }
+            }
+        }
+        wait_memory();                              // the frontier's atomics completed
+        __syncthreads();
+        base += total;
+    }
+    const int rho = r, reach = base;
+    // unreachable vertices follow in ascending id order, level -1
+    const int q = (W + kLdsBlock - 1) / kLdsBlock;
+    const int my0 = min(tid * q, W), my1 = min(my0 + q, W);
+    int pc = 0;
+    for (int x = my0; x < my1; ++x) {
+        unsigned word = ~vis[x];
+        if (x == W - 1 && (n & 31)) word &= (1u << (n & 31)) - 1u;
+        pc += __popc(word);
+    }
+    int total;
+    int rank = block_exclusive_scan_n<kLdsBlock, int, true>(pc, &total);
+    for (int x = my0; x < my1; ++x) {
+        unsigned word = ~vis[x];
+        if (x == W - 1 && (n & 31)) word &= (1u << (n & 31)) - 1u;
+        while (word) {
+            const int u = x * 32 + __ffs(word) - 1;
+            word &= word - 1;
+            const int pos = reach + rank;
+            a.perm[vo + pos] = vo + u;
+            a.iperm[vo + u] = vo + pos;
+            a.level[vo + u] = -1;
+            ++rank;
+        }
+    }
+    if (tid == 0) {
+        offs[rho] = reach;
+        a.state[b].rho = rho;
+        a.state[b].reach = reach;
+    }
+}
+
+// One workgroup per mesh: the larger meshes (first n_big blocks) with the
+// frontier in global memory, the others with every bitmap in LDS.
+__global__ __launch_bounds__(kLdsBlock) void k_bfs_one(BfsLdsArgs a) {
+    if (gated(a.ctrl)) return;
+    if ((int)blockIdx.x < a.n_big) bfs_big(a);
+    else bfs_lds(a);
+}
+
 // Fan length of each position, into fanrow[p + 1] (the fans themselves are
 // built once per prepare by vertex id, independent of the sources).
 __global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const int* fanlen, long long N,
@@ -571,17 +792,19 @@ __global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const in
     }
 }
 
-// Coordinates and fans in topleset order: position p takes the coordinates
-// of its vertex and a copy of the vertex's fan with every neighbour id turned
-// into that neighbour's position (flags kept).
+// Coordinates and fans in topleset order: the position of each vertex takes
+// its coordinates and a copy of its fan with every neighbour id turned into
+// that neighbour's position (flags kept).  The loop runs over vertex ids, so
+// the fans are read in storage order and the neighbours' positions are
+// looked up around the vertex's own id (meshes number neighbours closely);
+// only the writes scatter, one row per vertex.
 __global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const MeshDesc* mesh, int B,
-                                                    const int* vo, const int* perm, const int* iperm,
-                                                    const int* rowO, const int* fanO, const int* fanlen,
-                                                    const int* fanrow, long long N, float4* xyz, int* fan,
-                                                    const int* ctrl) {
+                                                    const int* vo, const int* iperm, const int* rowO,
+                                                    const int* fanO, const int* fanlen, const int* fanrow,
+                                                    long long N, float4* xyz, int* fan, const int* ctrl) {
     if (gated(ctrl)) return;
-    for_tiles(vo, B, N, [&](long long p, int b) {
-        const int v = perm[p];                  // a vertex of the same mesh as position p
+    for_tiles(vo, B, N, [&](long long v, int b) {
+        const int p = iperm[v];                 // a position of the same mesh
         const float* c = V + 3 * (mesh[b].v_in + (v - vo[b]));
         xyz[p] = make_float4(c[0], c[1], c[2], 0.f);
         const int* src = fanO + 2 * (long long)rowO[v];
@@ -705,7 +928,7 @@ void launch_barrier_reset(const Work& w, int lines, hipStream_t st) {
 }
 
 hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const int* F,
-                          const int* S, int g_prep, int n_lds, hipStream_t st) {
+                          const int* S, int g_prep, int n_one, int n_big, hipStream_t st) {
     const long long N = z.N, F3 = 3 * z.F;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, st, w.ctrl, (long long)C_WORDS, 0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(N + 1)), dim3(kBlock), 0, st, w.rowO, N + 1, 0);
@@ -722,7 +945,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
                        w.fanlen, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_prepare_bfs(w, z, V, S, g_prep, n_lds, st);
+    return launch_prepare_bfs(w, z, V, S, g_prep, n_one, n_big, st);
 }
 
 // Toplesets by BFS from the current sources, then the reorder of coordinates
@@ -730,7 +953,7 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
 // (rowO, wedgeO, ellO, fanO, fanlen) must already be built; they do not
 // depend on the sources.
 hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, const int* S, int g_prep,
-                              int n_lds, hipStream_t st) {
+                              int n_one, int n_big, hipStream_t st) {
     const long long N = z.N;
     hipError_t e;
     BfsArgs a;
@@ -751,9 +974,11 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
     a.cnt = w.cnt;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
-    if (n_lds > 0) {
+    if (n_one > 0) {
         BfsLdsArgs l;
         l.lmesh = w.lds_mesh;
+        l.n_big = n_big;
+        l.bits = w.bits;
         l.mesh = w.mesh;
         l.state = w.state;
         l.S = S;
@@ -765,7 +990,8 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
         l.iperm = w.iperm;
         l.offsets = w.offsets;
         l.ctrl = w.ctrl;
-        hipLaunchKernelGGL(k_bfs_lds, dim3(n_lds), dim3(kLdsBlock), bfs_lds_bytes(z.lds_words), st, l);
+        hipLaunchKernelGGL(k_bfs_one, dim3(n_one), dim3(kLdsBlock), bfs_one_bytes(z.lds_words, z.big_words), st,
+                           l);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -780,28 +1006,39 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
                        w.ctrl);
     e = scan_inplace(w.fanrow + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo, w.perm,
-                       w.iperm, w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.ctrl);
+    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo, w.iperm,
+                       w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.ctrl);
     return hipGetLastError();
 }
 
-size_t bfs_lds_bytes(long long words) {
-    return sizeof(unsigned) * (size_t)(3 * words + 1) + sizeof(int) * kLdsList;
+// Dynamic LDS of the one-workgroup BFS launch: three words per 32 vertices
+// and the emission list for the largest mesh with every bitmap in LDS; one
+// word per 32 vertices, one per 1,024 and the round stage for the largest
+// mesh with its frontier in global memory.
+size_t bfs_one_bytes(long long lds_words, long long big_words) {
+    const size_t lds = lds_words > 0 ? sizeof(unsigned) * (size_t)(3 * lds_words + 1) + sizeof(int) * kLdsList : 0;
+    const size_t big =
+        big_words > 0 ? sizeof(unsigned) * (size_t)(big_words + (big_words + 31) / 32 + 3 * kBigWl + 1) : 0;
+    return lds > big ? lds : big;
 }
 
-// Largest mesh (vertices) the one-workgroup BFS takes on this device, 0 if
-// none; raises the kernel's dynamic LDS limit to what the device allows.
-int bfs_lds_max_vertices(int device) {
+// Largest meshes (vertices) the two one-workgroup BFS paths take on this
+// device (0 if none); raises the kernel's dynamic LDS limit to what the
+// device allows.
+void bfs_one_limits(int device, int* lds_max, int* big_max) {
+    *lds_max = *big_max = 0;
     int smem = 0;
-    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
-        return 0;
-    const long long avail = (long long)smem - (long long)sizeof(int) * kLdsList - 1024;   // static
-    if (avail <= 0) return 0;
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_lds),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(avail + sizeof(int) * kLdsList)) != hipSuccess)
-        return 0;
-    return (int)((avail - 4) / 12) * 32;     // three words per 32 vertices
+    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return;
+    const long long avail = (long long)smem - 1024;                 // static LDS of the kernel
+    if (avail <= (long long)sizeof(int) * (3 * kBigWl + 64)) return;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bfs_one), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)avail) != hipSuccess)
+        return;
+    const long long a_lds = avail - (long long)sizeof(int) * kLdsList - 4;
+    *lds_max = a_lds > 0 ? (int)(a_lds / 12) * 32 : 0;                   // three words per 32 vertices
+    const long long a_big = avail - (long long)sizeof(unsigned) * (3 * kBigWl + 2);
+    // W + ceil(W / 32) words with W = n / 32 vertices' words: about 33 words per 1,024 vertices
+    *big_max = (int)std::min<long long>(a_big / 4 * 32 / 33 * 32, 1ll << 29);
 }
 
 int max_coop_blocks_bfs(int cus) {

@@ -99,7 +99,8 @@ struct RelaxArgs {
     const MeshDesc* mesh;
     MeshState* state;
     const WgInfo* wg;
-    const int* glist;      // per group: starts [ngroups + 1], then mesh ids
+    const int* queue;      // mesh queues: class starts [4], class of each group [ngroups], lists
+    int ngroups;
     const int* S;
     const float* upper;    // warm start: caller-order upper bound, or null
     int* xpost;            // [G] XCD of each workgroup (scratch)
@@ -423,10 +424,27 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
     }
     gb.local = local;
 
-    const int* lst = a.glist + a.glist[me.group];
-    const int nlst = a.glist[me.group + 1] - a.glist[me.group];
-    for (int li = 0; li < nlst; ++li) {
-        const int b = lst[li];
+    // Meshes are taken from queues at run time: the group's leader takes the
+    // next mesh of its class's queue (ordered by decreasing estimated time),
+    // or of a smaller class once that is empty, and posts it in the group's
+    // slot; a group's last read of the slot precedes its next barrier, which
+    // the leader passes before it posts again.
+    const int* qs = a.queue;
+    const int cls = qs[4 + me.group];
+    const int* qlist = qs + 4 + a.ngroups;
+    int* slot = a.xpost + a.G + me.group;
+    for (;;) {
+        if (leader) {
+            int bn = -1;
+            for (int c = cls; c >= 0 && bn < 0; --c) {
+                const int i = atomicAdd(a.ctrl + C_QHEAD + c, 1);
+                if (i < qs[c + 1] - qs[c]) bn = qlist[qs[c] + i];
+            }
+            st_c(slot, bn);
+        }
+        if (!gb.sync(0, &any)) return;
+        const int b = ld_c(slot);
+        if (b < 0) break;
         const MeshDesc md = a.mesh[b];
         const int n = md.n, vo = md.v_off;
         const int rho = a.state[b].rho;
@@ -438,7 +456,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         // lemma), so it stops after 2 rho - 3 iterations
         const int kfix = max(1, 2 * rho - 3);
         const int m0 = offs[1];                  // |V_0|: the sources occupy [0, m0)
-        if (leader) a.state[b].t_begin = wall_clock64();
+        if (leader) {
+            a.state[b].t_begin = wall_clock64();
+            a.state[b].wgs = gs;
+        }
         // every read of s_offs of the previous mesh came before its last barrier
         const bool offs_lds = rho < kOffsLds;
         if (offs_lds)
@@ -604,7 +625,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 }
 
 __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[C_ABORT] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl[C_ABORT] = 0;
+        for (int c = 0; c < 3; ++c) ctrl[C_QHEAD + c] = 0;
+    }
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
         state[b].iters = 0;
         state[b].runstat = 0;
@@ -613,6 +637,7 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
         state[b].cert_rejected = 0;
         state[b].t_begin = 0;
         state[b].t_end = 0;
+        state[b].wgs = 0;
     }
 }
 
@@ -747,7 +772,8 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.mesh = w.mesh;
     a.state = w.state;
     a.wg = f64 ? w.wg_run64 : w.wg_run;
-    a.glist = f64 ? w.glist_run64 : w.glist_run;
+    a.queue = f64 ? w.glist_run64 : w.glist_run;
+    a.ngroups = p.ngroups;
     a.S = p.S;
     a.upper = p.upper;
     a.xpost = w.cnt;

@@ -130,6 +130,30 @@ def test_bfs_paths_agree(cuda, mesh):
     assert np.array_equal(a.perm, order) and np.array_equal(a.offsets, offsets)
 
 
+def _large_one_workgroup_cases():
+    """Meshes beyond the LDS bitmaps of one workgroup but whose visited bitmap
+    still fits there (about 0.4M to 1.07M vertices): the one-workgroup BFS
+    keeps the next topleset in global memory.  The grid with 3,000 sources
+    has levels of more non-empty words than one staging round holds."""
+    g = I.flat_grid(700)
+    S = np.sort(np.random.default_rng(5).choice(g.n, 3000, replace=False)).astype(np.int32)
+    return [g, I.Mesh(g.V, g.F, S, name="grid700_3000_sources"), I.batch_mesh(262), I.batch_mesh(95)]
+
+
+@pytest.mark.parametrize("mesh", _large_one_workgroup_cases(), ids=lambda m: m.name)
+def test_large_meshes_one_workgroup_bfs(cuda, mesh):
+    """The one-workgroup BFS of larger meshes and the persistent grid BFS give
+    the same toplesets and order, equal to the oracle's, and the same run."""
+    a = gpu_run(mesh, 1e-4, lds_bfs_max=0)
+    b = gpu_run(mesh, 1e-4, lds_bfs_max=-1)
+    level, order, offsets, rho = O.toplesets(mesh.V, mesh.F, mesh.S)
+    say(f"  rho {rho} prepare one-workgroup {a.stats['ms_prepare']:.2f} ms, grid {b.stats['ms_prepare']:.2f} ms")
+    assert a.rho == b.rho == rho
+    assert np.array_equal(a.perm, order) and np.array_equal(a.offsets, offsets)
+    assert np.array_equal(b.perm, order) and np.array_equal(b.offsets, offsets)
+    assert np.array_equal(a.dist, b.dist) and (a.iterations, a.updates) == (b.iterations, b.updates)
+
+
 def test_parity_flat_grid_64(cuda):
     check_parity(cuda, I.flat_grid(64), 1e-6)
 
