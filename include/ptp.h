@@ -105,6 +105,13 @@ typedef struct {
     float ms_mesh_begin;    /* this mesh's iteration began / ended, ms after
                                the first mesh of the launch began (device     */
     float ms_mesh_end;      /* clock); -1 when it did not run                   */
+    int64_t evaluated_updates; /* the vertex updates whose triangles were
+                               evaluated: an update of a vertex that was
+                               updated in the previous iteration and none of
+                               whose neighbours changed there keeps its value
+                               without evaluation (the result would be the
+                               same); vertex_updates counts every update of
+                               the band                                      */
 } ptp_stats;
 
 typedef struct ptp_plan ptp_plan;

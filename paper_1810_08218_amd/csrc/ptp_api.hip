@@ -851,6 +851,7 @@ struct Solver {
                 // device wall clock at 100 MHz
                 out[b].ms_mesh_begin = x.t_begin ? (float)((x.t_begin - t0) * 1e-5) : -1.f;
                 out[b].ms_mesh_end = x.t_end ? (float)((x.t_end - t0) * 1e-5) : -1.f;
+                out[b].evaluated_updates = (int64_t)x.evaluated;
             }
             if (agg == PTP_OK && sb != PTP_OK) agg = sb;
         }

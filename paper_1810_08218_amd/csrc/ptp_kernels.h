@@ -33,6 +33,7 @@ struct MeshState {         // per mesh, written by the kernels
     long long t_end;       //   started / finished this mesh's iteration
     int wgs;               // workgroups of the group that ran it
     int pad2;
+    unsigned long long evaluated;   // band positions whose triangles were evaluated
 };
 
 struct WgInfo {            // per workgroup of a persistent launch

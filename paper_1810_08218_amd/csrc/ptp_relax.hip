@@ -126,11 +126,24 @@ constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
 // The iteration state of a position: its distance (float, or double in the
-// float64 run), exchanged between workgroups with coherent loads.
+// float64 run), exchanged between workgroups with coherent loads.  The sign
+// bit of a stored distance (distances are never negative) records whether
+// the update that wrote it changed the value.  A band vertex that was
+// updated in the previous iteration and none of whose neighbours changed
+// there keeps its value without evaluating its triangles: the update is a
+// function of the neighbours' values alone, so it would give the result the
+// previous iteration already folded in (d_k = min(d_{k-1}, U(d_{k-1})) with
+// U(d_{k-1}) = U(d_{k-2}) >= d_{k-1}).  The results are bit-identical.
 template <typename R>
 __device__ inline R ld_s(const R* s, int id) {
     return ld_c(s + id);
 }
+__device__ inline float mag(float x) { return fabsf(x); }
+__device__ inline double mag(double x) { return fabs(x); }
+__device__ inline bool flagged(float x) { return (__float_as_uint(x) >> 31) != 0u; }
+__device__ inline bool flagged(double x) { return __double_as_longlong(x) < 0; }
+template <typename R>
+__device__ inline R tagged(R d, bool changed) { return changed ? -d : d; }
 
 // Planar update of x0 from one triangle, folded into the minimum `best`
 // (which does not depend on the order in which the triangles come).
@@ -174,7 +187,7 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             const int id = e[q] & kFanId;
-            d[q] = ld_s(sold, id);
+            d[q] = mag(ld_s(sold, id));
             x[q] = a.xyz[id];
         }
 #pragma unroll
@@ -182,7 +195,7 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
             fold_update<R>(x0, x[q - 1], x[q], d[q - 1], d[q], best, q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
-            const R dl = ld_s(sold, id);
+            const R dl = mag(ld_s(sold, id));
             const float4 xl = a.xyz[id];
             fold_update<R>(x0, xl, xf, dl, d0, best);
         }
@@ -198,14 +211,23 @@ __device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e
     for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
 }
 
+// Distances (magnitudes) and coordinates of the first C fan entries;
+// returns whether any of them changed in the iteration that wrote it.
 template <typename R, int C>
-__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
+__device__ inline bool gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int id = e[q] & kFanId;
         d[q] = ld_s(sold, id);
         x[q] = a.xyz[id];
     }
+    bool chg = false;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        chg |= flagged(d[q]);
+        d[q] = mag(d[q]);
+    }
+    return chg;
 }
 
 // Smallest planar update of position v over all its incident triangles.
@@ -241,10 +263,13 @@ __device__ inline bool converged(R dv, R dn, float tol) {
 // that owns several band vertices waits for about one memory round per
 // vertex instead of three.  Returns the "not converged" vote of the
 // positions below tb.
+// Positions below bprev were updated in the previous iteration, so they may
+// keep their value when no neighbour changed (see ld_s); *evals counts the
+// positions whose triangles were evaluated.
 template <typename R, int C>
 __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
-                                                long long tb, long long gsz, const R* sold, R* snew,
-                                                bool local) {
+                                                long long tb, long long gsz, long long bprev, const R* sold,
+                                                R* snew, bool local, int* evals) {
     unsigned notconv = 0;
     if (p >= be) return 0;
     int f0 = a.fanrow[vo + p];
@@ -260,10 +285,10 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
-        const R dv = ld_s(sold, v);
+        const R dv = mag(ld_s(sold, v));
         R d[C];
         float4 x[C];
-        gather_fan<R, C>(a, e, sold, d, x);
+        const bool chg = gather_fan<R, C>(a, e, sold, d, x);
         // the next position's fan entries and the fan row of the one after
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
@@ -275,10 +300,13 @@ __device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long
             fnn1 = a.fanrow[vo + pnn + 1];
         }
         R best = inf_of<R>();
-        eval_fan_first<R, C>(x0, e, d, x, L, best);
-        if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
+        if (chg || p >= bprev || L > C) {
+            eval_fan_first<R, C>(x0, e, d, x, L, best);
+            if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
+            ++*evals;
+        }
         const R dn = best < dv ? best : dv;
-        st_g(snew + v, dn, local);
+        st_g(snew + v, tagged(dn, dn != dv), local);
         if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
         if (pn >= be) break;
         p = pn;
@@ -318,7 +346,7 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         const float wv = ld_c(d + v);
         float dd[C];
         float4 x[C];
-        gather_fan<float, C>(a, e, d, dd, x);
+        (void)gather_fan<float, C>(a, e, d, dd, x);
         const long long pnn = pn + gsz;
         const int Ln = fn1 - fn0;
         int en[C];
@@ -510,6 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
         int i = 1, lo_prev = 1, k = 0, runstat = 0;
         long long upd = 0;
+        int bprev = 0;        // end of the previous iteration's band (none before the first)
+        int evals = 0;        // this thread's evaluated positions
         // CACHE: the fan of the vertex this thread handled last.  While the
         // band is no wider than the group's threads, a band vertex keeps its
         // thread for every iteration it spends in the band, so after its first
@@ -543,15 +573,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
             const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
                 for (long long pp = first; pp < bb; pp += gsz)
-                    st_g(snew + vo + pp, ld_s(sold, vo + (int)pp), local);
+                    st_g(snew + vo + pp, mag(ld_s(sold, vo + (int)pp)), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_pipelined<R, kChunk>(a, vo, firstb, be, tb, gsz, sold, snew, local);
+                notconv |= relax_band_pipelined<R, kChunk>(a, vo, firstb, be, tb, gsz, bprev, sold, snew, local,
+                                                           &evals);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    st_g(snew + v, ld_s(sold, v), local);
+                    st_g(snew + v, mag(ld_s(sold, v)), local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -562,22 +593,27 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                const R dv = ld_s(sold, v);
+                const R dv = mag(ld_s(sold, v));
                 R best = kInfR;
                 if (cached && cv == v) {
                     R d[kCache];
                     float4 x[kCache];
-                    gather_fan<R, kCache>(a, ce, sold, d, x);
-                    eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
+                    const bool chg = gather_fan<R, kCache>(a, ce, sold, d, x);
+                    if (chg || pp >= bprev) {
+                        eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
+                        ++evals;
+                    }
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
                     best_update<R, kChunk>(a, v, x0, sold, best);
+                    ++evals;
                 }
                 const R dn = best < dv ? best : dv;
-                st_g(snew + v, dn, local);
+                st_g(snew + v, tagged(dn, dn != dv), local);
                 if (pp < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             }
             upd += be - bb;
+            bprev = be;
             if (!gb.sync(notconv, &any)) return;
             if (leader)
                 for (int r = i; r < lo; ++r) st_g(retire + r, k - 1, local);   // pushed out of the band
@@ -611,10 +647,14 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
         const R* sfin = (k & 1) ? sB : sA;
         for (long long p = g0; p < n; p += gsz) {
             const int v = a.perm[vo + p];
-            const R df = ld_s(sfin, vo + (int)p);
+            const R df = mag(ld_s(sfin, vo + (int)p));
             if (sizeof(R) == 8) a.out_d64[md.out_off + (v - vo)] = (double)df;
             else a.out_d[md.out_off + (v - vo)] = (float)df;
         }
+        // evaluated positions: a wave sum, one atomic per wave
+        long long ev = evals;
+        for (int o = kWave / 2; o > 0; o >>= 1) ev += __shfl_xor(ev, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0 && ev) atomicAdd(&a.state[b].evaluated, (unsigned long long)ev);
         if (leader) {
             a.state[b].iters = k;
             a.state[b].runstat = runstat;
@@ -638,6 +678,7 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
         state[b].t_begin = 0;
         state[b].t_end = 0;
         state[b].wgs = 0;
+        state[b].evaluated = 0;
     }
 }
 
@@ -668,14 +709,14 @@ __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const 
             root[p] = (int)p;
             return;
         }
-        const float dv = d[p];
+        const float dv = fabsf(d[p]);
         int bq = -1;
         if (dv < kInf) {
             const float4 x0 = xyz[p];
             float bu = kInf;
             int bg = 0x7fffffff;
             auto tri = [&](int q1, int q2) {
-                const float d1 = d[q1], d2 = d[q2];
+                const float d1 = fabsf(d[q1]), d2 = fabsf(d[q2]);
                 const int i1 = perm[q1] - vo, i2 = perm[q2] - vo;
                 int g = 0;
                 const float u = local_update<float, true>(x0, xyz[q1], xyz[q2], d1, d2, i1, i2, g);

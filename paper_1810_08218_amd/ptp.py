@@ -63,7 +63,8 @@ class Stats(C.Structure):
                 ("reachable", C.c_int32), ("workgroups", C.c_int32),
                 ("vertex_updates", C.c_int64), ("certify_rounds", C.c_int32),
                 ("certify_rejected", C.c_int32), ("ms_prepare", C.c_float), ("ms_run", C.c_float),
-                ("ms_mesh_begin", C.c_float), ("ms_mesh_end", C.c_float)]
+                ("ms_mesh_begin", C.c_float), ("ms_mesh_end", C.c_float),
+                ("evaluated_updates", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: (float(getattr(self, f)) if t is C.c_float else int(getattr(self, f)))
