@@ -79,9 +79,10 @@ struct Work {
     WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation
     int* glist_run64;   // [gmax + 8 + B]
     double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
+    int* mark;          // [N]     per position: the last iteration + 1 in which a neighbour changed
 };
 
-constexpr int kLayoutParts = 36;
+constexpr int kLayoutParts = 37;
 
 // Lloyd step: every cell's sums are split over this many chunks of the
 // faces (or vertices), each reduced in a fixed order.

@@ -68,14 +68,92 @@ __global__ __launch_bounds__(kBlock) void k_validate(const float* V, const int* 
     if (bad) atomicOr(ctrl + C_STATUS, bad);
 }
 
+// Corner loops of the incidence build: a tile of kTile corners (consecutive
+// faces) usually touches a narrow range of vertex ids, so their counts are
+// gathered in LDS first and each distinct vertex costs one global atomic
+// instead of one per corner (a vertex appears in about six corners, mostly of
+// nearby faces).  Tiles whose id range exceeds kAgg fall back to per-corner
+// global atomics.
+constexpr int kAgg = 8192;
+
+struct TileCorners {
+    int vid[kTileItems];   // global vertex id of each of this thread's corners, -1 past the end
+    long long t3[kTileItems];   // caller row of the corner's face
+    int c[kTileItems];     // corner inside the face
+    int vo[kTileItems];    // vertex offset of the corner's mesh
+};
+
+// Loads this thread's corners of tile t and returns the tile's id range
+// [*lo, *hi] (block-wide; lo > hi when the tile is empty).
+__device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int B, const int* fo3, long long F3,
+                                         long long t, TileCorners& tc, int* lo, int* hi, int* red) {
+    __shared__ int tile_mesh;
+    const long long base = t * kTile;
+    if (threadIdx.x == 0) tile_mesh = mesh_of(fo3, B, base);
+    __syncthreads();
+    int b = tile_mesh;
+    int mn = 0x7fffffff, mx = -1;
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const long long x = base + (long long)q * kBlock + threadIdx.x;
+        tc.vid[q] = -1;
+        if (x < F3) {
+            while ((long long)fo3[b + 1] <= x) ++b;
+            const long long lc = x - fo3[b];
+            tc.t3[q] = 3 * mesh[b].f_in + (lc - lc % 3);
+            tc.c[q] = (int)(lc % 3);
+            tc.vo[q] = mesh[b].v_off;
+            tc.vid[q] = tc.vo[q] + F[tc.t3[q] + tc.c[q]];
+            mn = min(mn, tc.vid[q]);
+            mx = max(mx, tc.vid[q]);
+        }
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, kWave));
+        mx = max(mx, __shfl_xor(mx, o, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[w] = mn;
+        red[4 + w] = mx;
+    }
+    __syncthreads();
+    mn = min(min(red[0], red[1]), min(red[2], red[3]));
+    mx = max(max(red[4], red[5]), max(red[6], red[7]));
+    *lo = mn;
+    *hi = mx;
+    __syncthreads();        // red and tile_mesh are rewritten by the next tile
+}
+
 // degree of each internal vertex, counted into row[v + 1]
 __global__ __launch_bounds__(kBlock) void k_count(const int* F, const MeshDesc* mesh, int B,
                                                   const int* fo3, long long F3, int* row,
                                                   const int* ctrl) {
     if (gated(ctrl)) return;
-    for_tiles(fo3, B, F3, [&](long long x, int b) {
-        atomicAdd(row + mesh[b].v_off + F[3 * mesh[b].f_in + (x - fo3[b])] + 1, 1);
-    });
+    __shared__ int cnt[kAgg];
+    __shared__ int red[8];
+    const long long ntiles = (F3 + kTile - 1) / kTile;
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        TileCorners tc;
+        int lo, hi;
+        load_tile_corners(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
+        if (hi - lo >= kAgg) {
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q)
+                if (tc.vid[q] >= 0) atomicAdd(row + tc.vid[q] + 1, 1);
+            continue;
+        }
+        const int range = hi - lo + 1;
+        for (int i = threadIdx.x; i < range; i += kBlock) cnt[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            if (tc.vid[q] >= 0) atomicAdd(cnt + (tc.vid[q] - lo), 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < range; i += kBlock)
+            if (cnt[i]) atomicAdd(row + lo + i + 1, cnt[i]);
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const MeshDesc* mesh, int B,
@@ -83,15 +161,38 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
                                                            const int* row, int* cursor,
                                                            int2* wedgeO, const int* ctrl) {
     if (gated(ctrl)) return;
-    for_tiles(fo3, B, F3, [&](long long x, int b) {
-        const int vo = mesh[b].v_off;
-        const long long lc = x - fo3[b];                 // corner inside the mesh
-        const long long t3 = 3 * mesh[b].f_in + (lc - lc % 3);
-        const int c = (int)(lc % 3);
-        const int v = vo + F[t3 + c];
-        const int slot = atomicAdd(cursor + v, 1);
-        wedgeO[row[v] + slot] = make_int2(vo + F[t3 + other1(c)], vo + F[t3 + other2(c)]);
-    });
+    __shared__ int cnt[kAgg];
+    __shared__ int red[8];
+    const long long ntiles = (F3 + kTile - 1) / kTile;
+    for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        TileCorners tc;
+        int lo, hi;
+        load_tile_corners(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
+        int slot[kTileItems];
+        const bool agg = hi - lo < kAgg;
+        if (agg) {
+            const int range = hi - lo + 1;
+            for (int i = threadIdx.x; i < range; i += kBlock) cnt[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q)
+                slot[q] = tc.vid[q] >= 0 ? atomicAdd(cnt + (tc.vid[q] - lo), 1) : 0;
+            __syncthreads();
+            // each vertex's slots in this tile follow the ones taken before
+            for (int i = threadIdx.x; i < range; i += kBlock)
+                if (cnt[i]) cnt[i] = atomicAdd(cursor + lo + i, cnt[i]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            const int v = tc.vid[q];
+            if (v < 0) continue;
+            const int s = agg ? cnt[v - lo] + slot[q] : atomicAdd(cursor + v, 1);
+            const int c = tc.c[q];
+            wedgeO[row[v] + s] = make_int2(tc.vo[q] + F[tc.t3[q] + other1(c)], tc.vo[q] + F[tc.t3[q] + other2(c)]);
+        }
+        if (agg) __syncthreads();       // cnt is rewritten by the next tile
+    }
 }
 
 // ---- in-place inclusive scan of a[0..len) (three passes) ----------------
@@ -913,6 +1014,11 @@ __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const in
     }
 }
 
+int tile_grid(long long total) {
+    const long long t = (total + kTile - 1) / kTile;
+    return (int)(t < 1 ? 1 : (t > 8192 ? 8192 : t));
+}
+
 int grid_for(long long work) {
     long long g = (work + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -935,11 +1041,11 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     hipLaunchKernelGGL(k_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, w.cursor, N, 0);
     hipLaunchKernelGGL(k_validate, dim3(grid_for(F3 > N ? F3 : N)), dim3(kBlock), 0, st, V, F, S,
                        w.mesh, z.B, w.vo, w.fo3, w.so, N, F3, z.S, w.state, w.ctrl);
-    hipLaunchKernelGGL(k_count, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B, w.fo3, F3,
+    hipLaunchKernelGGL(k_count, dim3(tile_grid(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B, w.fo3, F3,
                        w.rowO, w.ctrl);
     hipError_t e = scan_inplace(w.rowO + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_incidence, dim3(grid_for(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
+    hipLaunchKernelGGL(k_fill_incidence, dim3(tile_grid(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
                        w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
     hipLaunchKernelGGL(k_fan_global, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.fanO,
                        w.fanlen, w.ellO, w.ctrl);

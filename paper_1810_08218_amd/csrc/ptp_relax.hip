@@ -115,6 +115,7 @@ struct RelaxArgs {
     int* retire;
     int* ctrl;
     unsigned* bar;
+    int* mark;             // [N] per position: 1 + the last iteration in which a fan neighbour changed
     long long N;
     float* out_d;
     double* out_d64;
@@ -257,66 +258,112 @@ __device__ inline bool converged(R dv, R dn, float tol) {
     return dv < inf_of<R>() && (dn == dv || absr(dn - dv) / dv < (R)tol);
 }
 
-// Band positions p, p + gsz, ... (< be) of one thread, software-pipelined:
-// while the neighbour data of position p are in flight, the fan entries of
-// the next position and the fan row of the one after are loaded, so a thread
-// that owns several band vertices waits for about one memory round per
-// vertex instead of three.  Returns the "not converged" vote of the
-// positions below tb.
-// Positions below bprev were updated in the previous iteration, so they may
-// keep their value when no neighbour changed (see ld_s); *evals counts the
-// positions whose triangles were evaluated.
+// Marks a changed position's fan entries (its neighbours: a vertex is in the
+// fan of each of its neighbours) for iteration k1.
+template <int C>
+__device__ inline void mark_fan(const RelaxArgs& a, const int* e, int f0, int L, int k1, bool local) {
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (q < L) st_g(a.mark + (e[q] & kFanId), k1, local);
+    for (int q = C; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k1, local);
+}
+
+// Band positions p0, p0 + gsz, ... (< be) of one thread, in batches of
+// kBatch.  The marks and distances of a batch are loaded together (coalesced
+// across the group's threads).  A position updated in the previous iteration
+// (below bprev) that no neighbour marked for this iteration (mark < k) keeps
+// its value (see ld_s): it only rewrites this iteration's buffer when the
+// value changed in the previous iteration (the buffer then holds the one
+// before).  The other positions are evaluated, software-pipelined: while the
+// neighbour data of one are in flight, the fan entries of the next and the
+// fan row of the one after are loaded.  A position whose value changes marks
+// its neighbours for the next iteration.  Returns the "not converged" vote of
+// the positions below tb; *evals counts the evaluated positions.
+constexpr int kBatch = 8;
+
 template <typename R, int C>
-__device__ inline unsigned relax_band_pipelined(const RelaxArgs& a, int vo, long long p, long long be,
-                                                long long tb, long long gsz, long long bprev, const R* sold,
-                                                R* snew, bool local, int* evals) {
+__device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, long long p0, long long be, long long tb,
+                                             long long gsz, long long bprev, int k, const R* sold, R* snew,
+                                             bool local, int* evals) {
     unsigned notconv = 0;
-    if (p >= be) return 0;
-    int f0 = a.fanrow[vo + p];
-    int L = a.fanrow[vo + p + 1] - f0;
-    int e[C];
-    load_fan<C>(a, vo + (int)p, f0, L, e);
-    long long pn = p + gsz;
-    int fn0 = 0, fn1 = 0;
-    if (pn < be) {
-        fn0 = a.fanrow[vo + pn];
-        fn1 = a.fanrow[vo + pn + 1];
-    }
-    for (;;) {
-        const int v = vo + (int)p;
-        const float4 x0 = a.xyz[v];
-        const R dv = mag(ld_s(sold, v));
-        R d[C];
-        float4 x[C];
-        const bool chg = gather_fan<R, C>(a, e, sold, d, x);
-        // the next position's fan entries and the fan row of the one after
-        const long long pnn = pn + gsz;
-        const int Ln = fn1 - fn0;
-        int en[C];
-        int fnn0 = 0, fnn1 = 0;
-        if (pn < be) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
-        if (pnn < be) {
-            fnn0 = a.fanrow[vo + pnn];
-            fnn1 = a.fanrow[vo + pnn + 1];
+    for (long long pb = p0; pb < be; pb += kBatch * gsz) {
+        int mk[kBatch];
+        R raw[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const long long p = pb + i * gsz;
+            mk[i] = 0;
+            raw[i] = (R)0;
+            if (p < be) {
+                mk[i] = ld_c(a.mark + vo + p);
+                raw[i] = ld_s(sold, vo + (int)p);
+            }
         }
-        R best = inf_of<R>();
-        if (chg || p >= bprev || L > C) {
+        unsigned todo = 0;
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const long long p = pb + i * gsz;
+            if (p >= be) continue;
+            if (p >= bprev || mk[i] >= k) {
+                todo |= 1u << i;
+            } else {
+                if (flagged(raw[i])) st_g(snew + vo + p, mag(raw[i]), local);
+                if (p < tb && !(mag(raw[i]) < inf_of<R>())) notconv = 1;
+            }
+        }
+        if (!todo) continue;
+        long long p = pb + (long long)(__ffs(todo) - 1) * gsz;
+        todo &= todo - 1;
+        int f0 = a.fanrow[vo + p];
+        int L = a.fanrow[vo + p + 1] - f0;
+        int e[C];
+        load_fan<C>(a, vo + (int)p, f0, L, e);
+        long long pn = -1;
+        int fn0 = 0, fn1 = 0;
+        if (todo) {
+            pn = pb + (long long)(__ffs(todo) - 1) * gsz;
+            todo &= todo - 1;
+            fn0 = a.fanrow[vo + pn];
+            fn1 = a.fanrow[vo + pn + 1];
+        }
+        for (;;) {
+            const int v = vo + (int)p;
+            const float4 x0 = a.xyz[v];
+            const R dv = mag(ld_s(sold, v));
+            R d[C];
+            float4 x[C];
+            (void)gather_fan<R, C>(a, e, sold, d, x);
+            // the next position's fan entries and the fan row of the one after
+            const int Ln = fn1 - fn0;
+            int en[C];
+            if (pn >= 0) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
+            long long pnn = -1;
+            int fnn0 = 0, fnn1 = 0;
+            if (todo) {
+                pnn = pb + (long long)(__ffs(todo) - 1) * gsz;
+                todo &= todo - 1;
+                fnn0 = a.fanrow[vo + pnn];
+                fnn1 = a.fanrow[vo + pnn + 1];
+            }
+            R best = inf_of<R>();
             eval_fan_first<R, C>(x0, e, d, x, L, best);
             if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
             ++*evals;
-        }
-        const R dn = best < dv ? best : dv;
-        st_g(snew + v, tagged(dn, dn != dv), local);
-        if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
-        if (pn >= be) break;
-        p = pn;
-        pn = pnn;
-        f0 = fn0;
-        L = Ln;
+            const R dn = best < dv ? best : dv;
+            const bool changed = dn != dv;
+            st_g(snew + v, tagged(dn, changed), local);
+            if (changed) mark_fan<C>(a, e, f0, L, k + 1, local);
+            if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
+            if (pn < 0) break;
+            p = pn;
+            pn = pnn;
+            f0 = fn0;
+            L = Ln;
 #pragma unroll
-        for (int q = 0; q < C; ++q) e[q] = en[q];
-        fn0 = fnn0;
-        fn1 = fnn1;
+            for (int q = 0; q < C; ++q) e[q] = en[q];
+            fn0 = fnn0;
+            fn1 = fnn1;
+        }
     }
     return notconv;
 }
@@ -495,6 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
 
         const int reach = a.state[b].reach;
         for (long long p = g0; p < n; p += gsz) {
+            st_g(a.mark + vo + p, 0, local);
             R d = p < m0 ? (R)0 : kInfR;
             if (WARM && p >= m0 && p < reach) {      // warm start: the caller's bound
                 const int v = a.perm[vo + p];
@@ -575,8 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 for (long long pp = first; pp < bb; pp += gsz)
                     st_g(snew + vo + pp, mag(ld_s(sold, vo + (int)pp)), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_pipelined<R, kChunk>(a, vo, firstb, be, tb, gsz, bprev, sold, snew, local,
-                                                           &evals);
+                notconv |= relax_band_marked<R, kChunk>(a, vo, firstb, be, tb, gsz, bprev, k, sold, snew, local,
+                                                        &evals);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
@@ -593,23 +641,35 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                const R dv = mag(ld_s(sold, v));
+                const R raw = ld_s(sold, v);
+                const R dv = mag(raw);
+                if (pp < bprev && ld_c(a.mark + v) < k) {     // no neighbour changed: keep (see ld_s)
+                    if (flagged(raw)) st_g(snew + v, dv, local);
+                    if (pp < tb && !(dv < kInfR)) notconv = 1;
+                    continue;
+                }
                 R best = kInfR;
                 if (cached && cv == v) {
                     R d[kCache];
                     float4 x[kCache];
-                    const bool chg = gather_fan<R, kCache>(a, ce, sold, d, x);
-                    if (chg || pp >= bprev) {
-                        eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
-                        ++evals;
-                    }
+                    (void)gather_fan<R, kCache>(a, ce, sold, d, x);
+                    eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
                     best_update<R, kChunk>(a, v, x0, sold, best);
-                    ++evals;
                 }
+                ++evals;
                 const R dn = best < dv ? best : dv;
-                st_g(snew + v, tagged(dn, dn != dv), local);
+                const bool changed = dn != dv;
+                st_g(snew + v, tagged(dn, changed), local);
+                if (changed) {
+                    if (cached && cv == v) {
+                        mark_fan<kCache>(a, ce, 0, cL, k + 1, local);
+                    } else {
+                        const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
+                        for (int q = 0; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k + 1, local);
+                    }
+                }
                 if (pp < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             }
             upd += be - bb;
@@ -829,6 +889,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.retire = w.retire;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
+    a.mark = w.mark;
     a.N = p.N;
     a.out_d = p.out_d;
     a.out_d64 = p.out_d64;
