@@ -279,19 +279,19 @@ __device__ inline void mark_fan(const RelaxArgs& a, const int* e, int f0, int L,
 // fan row of the one after are loaded.  A position whose value changes marks
 // its neighbours for the next iteration.  Returns the "not converged" vote of
 // the positions below tb; *evals counts the evaluated positions.
-constexpr int kBatch = 8;
+constexpr int kBatch = 4;
 
 template <typename R, int C>
-__device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, long long p0, long long be, long long tb,
-                                             long long gsz, long long bprev, int k, const R* sold, R* snew,
+__device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0, int be, int tb, int gsz,
+                                             int bprev, int k, const R* sold, R* snew,
                                              bool local, int* evals) {
     unsigned notconv = 0;
-    for (long long pb = p0; pb < be; pb += kBatch * gsz) {
+    for (int pb = p0; pb < be; pb += kBatch * gsz) {
         int mk[kBatch];
         R raw[kBatch];
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
-            const long long p = pb + i * gsz;
+            const int p = pb + i * gsz;
             mk[i] = 0;
             raw[i] = (R)0;
             if (p < be) {
@@ -302,7 +302,7 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, long lo
         unsigned todo = 0;
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
-            const long long p = pb + i * gsz;
+            const int p = pb + i * gsz;
             if (p >= be) continue;
             if (p >= bprev || mk[i] >= k) {
                 todo |= 1u << i;
@@ -312,13 +312,13 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, long lo
             }
         }
         if (!todo) continue;
-        long long p = pb + (long long)(__ffs(todo) - 1) * gsz;
+        int p = pb + (long long)(__ffs(todo) - 1) * gsz;
         todo &= todo - 1;
         int f0 = a.fanrow[vo + p];
         int L = a.fanrow[vo + p + 1] - f0;
         int e[C];
         load_fan<C>(a, vo + (int)p, f0, L, e);
-        long long pn = -1;
+        int pn = -1;
         int fn0 = 0, fn1 = 0;
         if (todo) {
             pn = pb + (long long)(__ffs(todo) - 1) * gsz;
@@ -337,7 +337,7 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, long lo
             const int Ln = fn1 - fn0;
             int en[C];
             if (pn >= 0) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
-            long long pnn = -1;
+            int pnn = -1;
             int fnn0 = 0, fnn1 = 0;
             if (todo) {
                 pnn = pb + (long long)(__ffs(todo) - 1) * gsz;
@@ -445,14 +445,21 @@ constexpr int kOffsLds = 4096;
 // vertex stays on one CU across iterations and its incidence and coordinates
 // stay in that CU's caches.  For each vertex it first gathers up to kChunk
 // wedges, then every neighbour distance and coordinate of those wedges at
-// once (independent loads), then evaluates the planar updates.  Distances and
+// once (independent loads), then evaluates the planar updates.  Distances
 // are exchanged between workgroups through coherent loads and stores.
 // R = double: the same iteration in float64 (no warm start or cache).
 // RULES: the band rule is read at run time (fixed half band, Jacobi);
 // otherwise it is the paper's, fixed at compile time, which keeps the band
 // loop's registers for the common case.
+// The float kernels of the paper's rule without the register cache (the
+// batch) are held to 128 VGPRs, four workgroups per CU: the band loop waits
+// on memory, and a fourth wave per SIMD hides more of it than the registers
+// it costs (only per-mesh values spill).
+constexpr int relax_waves(bool f32, bool cache, bool rules) { return f32 && !cache && !rules ? 4 : 1; }
+
 template <typename R, bool WARM, bool CACHE, bool RULES = false>
-__global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(relax_waves(sizeof(R) == 4, CACHE, RULES))))
+void k_relax(RelaxArgs a) {
     static_assert(sizeof(R) == 4 || (!WARM && !CACHE), "float64 runs plain only");
     const WgInfo me = a.wg[blockIdx.x];
     if (me.group < 0) return;                 // an unused launch slot
@@ -623,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RelaxArgs a) {
                 for (long long pp = first; pp < bb; pp += gsz)
                     st_g(snew + vo + pp, mag(ld_s(sold, vo + (int)pp)), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_marked<R, kChunk>(a, vo, firstb, be, tb, gsz, bprev, k, sold, snew, local,
+                notconv |= relax_band_marked<R, kChunk>(a, vo, (int)firstb, be, tb, gsz32, bprev, k, sold, snew, local,
                                                         &evals);
                 cv = -1;
             }
