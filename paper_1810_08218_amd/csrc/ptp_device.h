@@ -196,6 +196,26 @@ __device__ inline int mesh_of(const int* prefix, int B, long long x) {
     return lo;
 }
 
+// mesh_of by one whole wave (every lane calls it and gets the result): each
+// round the 64 lanes test 64 evenly spaced prefix entries of the remaining
+// range and a ballot keeps the last one at or below x, so 512 meshes take two
+// dependent loads instead of nine.
+__device__ inline int mesh_of_wave(const int* prefix, int B, long long x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int lo = 0, len = B;         // invariant: prefix[lo] <= x < prefix[lo + len]
+    while (len > 1) {
+        const int step = (len + kWave - 1) / kWave;
+        const int i = lo + lane * step;
+        const bool le = i < lo + len && (long long)prefix[i] <= x;
+        const unsigned long long m = __ballot(le);      // lane 0 always set
+        const int last = 63 - __clzll((long long)m);
+        const int nlo = lo + last * step;
+        len = min(step, lo + len - nlo);
+        lo = nlo;
+    }
+    return lo;
+}
+
 // Element loops over the concatenation take tiles of kTile consecutive
 // elements per workgroup.  The mesh of a tile's first element is found once
 // (binary search over the prefix) and each thread advances it across the
@@ -210,7 +230,10 @@ __device__ inline void for_tiles(const int* prefix, int B, long long total, Fn f
     const long long ntiles = (total + kTile - 1) / kTile;
     for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const long long base = t * kTile;
-        if (threadIdx.x == 0) tile_mesh = mesh_of(prefix, B, base);
+        if (threadIdx.x < kWave) {
+            const int b0 = mesh_of_wave(prefix, B, base);
+            if (threadIdx.x == 0) tile_mesh = b0;
+        }
         __syncthreads();
         int b = tile_mesh;
         __syncthreads();        // tile_mesh is rewritten for the next tile
@@ -220,6 +243,34 @@ __device__ inline void for_tiles(const int* prefix, int B, long long total, Fn f
             while ((long long)prefix[b + 1] <= x) ++b;
             f(x, b);
         }
+    }
+}
+
+// The meshes of this thread's elements of tile t (element base + q kBlock +
+// threadIdx.x of the tile, q < kTileItems) into bq[q], for loops that load
+// all their elements before using any (so that the loads overlap).  When the
+// tile lies inside one mesh, the usual case, no thread reads the prefix.
+__device__ inline void tile_meshes(const int* prefix, int B, long long total, long long t, int* bq) {
+    __shared__ int tile_b, tile_whole;
+    const long long base = t * kTile;
+    if (threadIdx.x < kWave) {
+        const int b0 = mesh_of_wave(prefix, B, base);
+        const long long end = base + kTile < total ? base + kTile : total;
+        if (threadIdx.x == 0) {
+            tile_b = b0;
+            tile_whole = (long long)prefix[b0 + 1] >= end;
+        }
+    }
+    __syncthreads();
+    int b = tile_b;
+    const bool whole = tile_whole != 0;
+    __syncthreads();        // both are rewritten for the next tile
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const long long x = base + (long long)q * kBlock + threadIdx.x;
+        if (!whole && x < total)
+            while ((long long)prefix[b + 1] <= x) ++b;
+        bq[q] = b;
     }
 }
 

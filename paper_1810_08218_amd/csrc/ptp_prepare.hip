@@ -38,26 +38,58 @@ __global__ __launch_bounds__(kBlock) void k_zero_lines(unsigned* p, long long le
 // their mesh.  Bad meshes are flagged in their state and in the batch word.
 // Loops run over the internal (concatenated) index spaces and read the
 // caller's rows.
-__global__ __launch_bounds__(kBlock) void k_validate(const float* V, const int* F, const int* S,
-                                                     const MeshDesc* mesh, int B, const int* vo,
-                                                     const int* fo3, const int* so, long long N,
-                                                     long long F3, long long Stot, MeshState* state,
-                                                     int* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_validate(const float* __restrict__ V, const int* __restrict__ F,
+                                                     const int* __restrict__ S, const MeshDesc* mesh, int B,
+                                                     const int* vo, const int* fo3, const int* so, long long N,
+                                                     long long F3, long long Stot, MeshState* state, int* ctrl) {
     int bad = 0;
-    for_tiles(fo3, B, F3, [&](long long x, int b) {
-        const int v = F[3 * mesh[b].f_in + (x - fo3[b])];
-        if (v < 0 || v >= mesh[b].n) {
-            atomicOr(&state[b].status, ST_BAD_FACE);
-            bad |= ST_BAD_FACE;
+    // face corners and coordinates: every element of a tile loaded, then checked
+    for (long long t = blockIdx.x; t < (F3 + kTile - 1) / kTile; t += gridDim.x) {
+        int bq[kTileItems], v[kTileItems], nq[kTileItems];
+        long long at[kTileItems];
+        tile_meshes(fo3, B, F3, t, bq);
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            at[q] = 3 * (long long)mesh[bq[q]].f_in + (t * kTile + (long long)q * kBlock + threadIdx.x - fo3[bq[q]]);
+            nq[q] = mesh[bq[q]].n;
         }
-    });
-    for_tiles(vo, B, N, [&](long long p, int b) {
-        const float* c = V + 3 * (mesh[b].v_in + (p - vo[b]));
-        if (!(fabsf(c[0]) <= 3.0e38f) || !(fabsf(c[1]) <= 3.0e38f) || !(fabsf(c[2]) <= 3.0e38f)) {
-            atomicOr(&state[b].status, ST_BAD_COORD);
-            bad |= ST_BAD_COORD;
+        if (t * kTile + kTile <= F3) {
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q) v[q] = F[at[q]];
+        } else {
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q)
+                v[q] = t * kTile + (long long)q * kBlock + threadIdx.x < F3 ? F[at[q]] : 0;
         }
-    });
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            if (t * kTile + (long long)q * kBlock + threadIdx.x < F3 && (v[q] < 0 || v[q] >= nq[q])) {
+                atomicOr(&state[bq[q]].status, ST_BAD_FACE);
+                bad |= ST_BAD_FACE;
+            }
+    }
+    for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
+        int bq[kTileItems];
+        long long at[kTileItems];
+        float c[kTileItems][3];
+        tile_meshes(vo, B, N, t, bq);
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            at[q] = 3 * ((long long)mesh[bq[q]].v_in + (t * kTile + (long long)q * kBlock + threadIdx.x - vo[bq[q]]));
+        const bool full = t * kTile + kTile <= N;
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) {
+            const bool ok = full || t * kTile + (long long)q * kBlock + threadIdx.x < N;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) c[q][k] = ok ? V[at[q] + k] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            if (!(fabsf(c[q][0]) <= 3.0e38f) || !(fabsf(c[q][1]) <= 3.0e38f) || !(fabsf(c[q][2]) <= 3.0e38f)) {
+                atomicOr(&state[bq[q]].status, ST_BAD_COORD);
+                bad |= ST_BAD_COORD;
+            }
+    }
     for_tiles(so, B, Stot, [&](long long x, int b) {
         const int s = S[mesh[b].s_in + (x - so[b])];
         if (s < 0 || s >= mesh[b].n) {
@@ -84,30 +116,37 @@ struct TileCorners {
 };
 
 // Loads this thread's corners of tile t and returns the tile's id range
-// [*lo, *hi] (block-wide; lo > hi when the tile is empty).
+// [*lo, *hi] (block-wide; lo > hi when the tile is empty).  The corners'
+// meshes are found first, then every corner is loaded before any is used.
 __device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int B, const int* fo3, long long F3,
                                          long long t, TileCorners& tc, int* lo, int* hi, int* red) {
-    __shared__ int tile_mesh;
     const long long base = t * kTile;
-    if (threadIdx.x == 0) tile_mesh = mesh_of(fo3, B, base);
-    __syncthreads();
-    int b = tile_mesh;
-    int mn = 0x7fffffff, mx = -1;
+    int bq[kTileItems];
+    tile_meshes(fo3, B, F3, t, bq);
 #pragma unroll
     for (int q = 0; q < kTileItems; ++q) {
         const long long x = base + (long long)q * kBlock + threadIdx.x;
-        tc.vid[q] = -1;
-        if (x < F3) {
-            while ((long long)fo3[b + 1] <= x) ++b;
-            const long long lc = x - fo3[b];
-            tc.t3[q] = 3 * mesh[b].f_in + (lc - lc % 3);
-            tc.c[q] = (int)(lc % 3);
-            tc.vo[q] = mesh[b].v_off;
-            tc.vid[q] = tc.vo[q] + F[tc.t3[q] + tc.c[q]];
+        const int b = bq[q];
+        const long long lc = x - fo3[b];
+        tc.t3[q] = 3 * (long long)mesh[b].f_in + (lc - lc % 3);
+        tc.c[q] = (int)(lc % 3);
+        tc.vo[q] = mesh[b].v_off;
+    }
+    if (base + kTile <= F3) {       // a full tile: no guards, so the loads issue together
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q) tc.vid[q] = tc.vo[q] + F[tc.t3[q] + tc.c[q]];
+    } else {
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            tc.vid[q] = base + (long long)q * kBlock + threadIdx.x < F3 ? tc.vo[q] + F[tc.t3[q] + tc.c[q]] : -1;
+    }
+    int mn = 0x7fffffff, mx = -1;
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q)
+        if (tc.vid[q] >= 0) {
             mn = min(mn, tc.vid[q]);
             mx = max(mx, tc.vid[q]);
         }
-    }
     for (int o = kWave / 2; o > 0; o >>= 1) {
         mn = min(mn, __shfl_xor(mn, o, kWave));
         mx = max(mx, __shfl_xor(mx, o, kWave));
@@ -122,7 +161,7 @@ __device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int
     mx = max(max(red[4], red[5]), max(red[6], red[7]));
     *lo = mn;
     *hi = mx;
-    __syncthreads();        // red and tile_mesh are rewritten by the next tile
+    __syncthreads();        // red is rewritten by the next tile
 }
 
 // degree of each internal vertex, counted into row[v + 1]
@@ -183,13 +222,28 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
                 if (cnt[i]) cnt[i] = atomicAdd(cursor + lo + i, cnt[i]);
             __syncthreads();
         }
+        if (agg && t * kTile + kTile <= F3) {
+            // a full tile: every corner's incidence row and wedge loaded, then stored
+            int at[kTileItems];
+            int2 wd[kTileItems];
 #pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            const int v = tc.vid[q];
-            if (v < 0) continue;
-            const int s = agg ? cnt[v - lo] + slot[q] : atomicAdd(cursor + v, 1);
-            const int c = tc.c[q];
-            wedgeO[row[v] + s] = make_int2(tc.vo[q] + F[tc.t3[q] + other1(c)], tc.vo[q] + F[tc.t3[q] + other2(c)]);
+            for (int q = 0; q < kTileItems; ++q) {
+                const int v = tc.vid[q], c = tc.c[q];
+                at[q] = row[v] + cnt[v - lo] + slot[q];
+                wd[q] = make_int2(tc.vo[q] + F[tc.t3[q] + other1(c)], tc.vo[q] + F[tc.t3[q] + other2(c)]);
+            }
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q) wedgeO[at[q]] = wd[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < kTileItems; ++q) {
+                const int v = tc.vid[q];
+                if (v < 0) continue;
+                const int s = agg ? cnt[v - lo] + slot[q] : atomicAdd(cursor + v, 1);
+                const int c = tc.c[q];
+                wedgeO[row[v] + s] =
+                    make_int2(tc.vo[q] + F[tc.t3[q] + other1(c)], tc.vo[q] + F[tc.t3[q] + other2(c)]);
+            }
         }
         if (agg) __syncthreads();       // cnt is rewritten by the next tile
     }
@@ -898,24 +952,71 @@ __global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const in
 // that neighbour's position (flags kept).  The loop runs over vertex ids, so
 // the fans are read in storage order and the neighbours' positions are
 // looked up around the vertex's own id (meshes number neighbours closely);
-// only the writes scatter, one row per vertex.
-__global__ __launch_bounds__(kBlock) void k_reorder(const float* V, const MeshDesc* mesh, int B,
-                                                    const int* vo, const int* iperm, const int* rowO,
-                                                    const int* fanO, const int* fanlen, const int* fanrow,
-                                                    long long N, float4* xyz, int* fan, const int* ctrl) {
+// only the writes scatter, one row per vertex.  A thread takes kReItems
+// vertices at a time through three rounds of loads (position, coordinates and
+// fan offset; fan row and the first kReFan fan entries; the neighbours'
+// positions), each round issued for all of them before any result is used.
+constexpr int kReItems = 4;
+constexpr int kReFan = 8;
+
+__global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V, const MeshDesc* mesh, int B,
+                                                    const int* vo, const int* __restrict__ iperm,
+                                                    const int* __restrict__ rowO, const int* __restrict__ fanO,
+                                                    const int* __restrict__ fanlen, const int* __restrict__ fanrow,
+                                                    long long N, float4* __restrict__ xyz, int* __restrict__ fan,
+                                                    const int* ctrl) {
     if (gated(ctrl)) return;
-    for_tiles(vo, B, N, [&](long long v, int b) {
-        const int p = iperm[v];                 // a position of the same mesh
-        const float* c = V + 3 * (mesh[b].v_in + (v - vo[b]));
-        xyz[p] = make_float4(c[0], c[1], c[2], 0.f);
-        const int* src = fanO + 2 * (long long)rowO[v];
-        int* dst = fan + fanrow[p];
-        const int len = fanlen[v];
-        for (int q = 0; q < len; ++q) {
-            const int e = src[q];
-            dst[q] = iperm[e & kFanId] | (e & ~kFanId);
+    for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
+        int bq[kTileItems];
+        tile_meshes(vo, B, N, t, bq);
+#pragma unroll
+        for (int h = 0; h < kTileItems; h += kReItems) {
+            int p[kReItems], r0[kReItems], len[kReItems], fr[kReItems], e[kReItems][kReFan];
+            float c[kReItems][3];
+#pragma unroll
+            for (int i = 0; i < kReItems; ++i) {
+                const long long v = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
+                p[i] = 0;
+                r0[i] = 0;
+                len[i] = 0;
+                c[i][0] = c[i][1] = c[i][2] = 0.f;
+                if (v < N) {
+                    const int b = bq[h + i];
+                    const float* cp = V + 3 * ((long long)mesh[b].v_in + (v - vo[b]));
+                    p[i] = iperm[v];
+                    c[i][0] = cp[0];
+                    c[i][1] = cp[1];
+                    c[i][2] = cp[2];
+                    r0[i] = rowO[v];
+                    len[i] = fanlen[v];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kReItems; ++i) {
+                fr[i] = len[i] > 0 ? fanrow[p[i]] : 0;
+#pragma unroll
+                for (int q = 0; q < kReFan; ++q) e[i][q] = q < len[i] ? fanO[2 * (long long)r0[i] + q] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < kReItems; ++i)
+#pragma unroll
+                for (int q = 0; q < kReFan; ++q)
+                    if (q < len[i]) e[i][q] = iperm[e[i][q] & kFanId] | (e[i][q] & ~kFanId);
+#pragma unroll
+            for (int i = 0; i < kReItems; ++i) {
+                const long long v = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
+                if (v >= N) continue;
+                xyz[p[i]] = make_float4(c[i][0], c[i][1], c[i][2], 0.f);
+#pragma unroll
+                for (int q = 0; q < kReFan; ++q)
+                    if (q < len[i]) fan[fr[i] + q] = e[i][q];
+                for (int q = kReFan; q < len[i]; ++q) {
+                    const int x = fanO[2 * (long long)r0[i] + q];
+                    fan[fr[i] + q] = iperm[x & kFanId] | (x & ~kFanId);
+                }
+            }
         }
-    });
+    }
 }
 
 // The chains of one vertex's wedges wd(0..c) (see kFanStart): a chain starts
@@ -990,12 +1091,28 @@ __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const in
                                                        int* fanO, int* fanlen, int* ellO, const int* ctrl) {
     if (gated(ctrl)) return;
     __shared__ int2 wd_s[kFanChainMax * kBlock];
+    __shared__ int row_s[kEll * kBlock];       // the first kEll fan entries, for the BFS row
     const int tid = threadIdx.x;
     const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long v = blockIdx.x * (long long)kBlock + tid; v < N; v += gsz) {
-        const int r0 = rowO[v], c = rowO[v + 1] - r0;
+    long long v = blockIdx.x * (long long)kBlock + tid;
+    int r0 = 0, c = 0;
+    if (v < N) {
+        r0 = rowO[v];
+        c = rowO[v + 1] - r0;
+    }
+    for (; v < N; v += gsz) {
+        // the next vertex's incidence row is loaded while this one is built
+        const long long vn = v + gsz;
+        int r0n = 0, cn = 0;
+        if (vn < N) {
+            r0n = rowO[vn];
+            cn = rowO[vn + 1] - r0n;
+        }
         int* out = fanO + 2 * (long long)r0;
-        auto emit = [&](int q, int x) { out[q] = x; };
+        auto emit = [&](int q, int x) {
+            out[q] = x;
+            if (q < kEll) row_s[q * kBlock + tid] = x;
+        };
         int len;
         if (c <= kFanChainMax) {
             for (int q = 0; q < c; ++q) wd_s[q * kBlock + tid] = wedgeO[r0 + q];
@@ -1006,11 +1123,13 @@ __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const in
         fanlen[v] = len;
         int nb[kEll];
 #pragma unroll
-        for (int q = 0; q < kEll; ++q) nb[q] = q < len ? (out[q] & kFanId) : -1;
+        for (int q = 0; q < kEll; ++q) nb[q] = q < len ? (row_s[q * kBlock + tid] & kFanId) : -1;
         if (len > kEll) nb[kEll - 1] = kEllMore;
         int4* er = reinterpret_cast<int4*>(ellO + kEll * v);
         er[0] = make_int4(nb[0], nb[1], nb[2], nb[3]);
         er[1] = make_int4(nb[4], nb[5], nb[6], nb[7]);
+        r0 = r0n;
+        c = cn;
     }
 }
 
