@@ -127,24 +127,26 @@ constexpr int kChunk = 6;
 constexpr int kCertifyRounds = 4096;   // cap on the certification closure
 
 // The iteration state of a position: its distance (float, or double in the
-// float64 run), exchanged between workgroups with coherent loads.  The sign
-// bit of a stored distance (distances are never negative) records whether
-// the update that wrote it changed the value.  A band vertex that was
-// updated in the previous iteration and none of whose neighbours changed
-// there keeps its value without evaluating its triangles: the update is a
-// function of the neighbours' values alone, so it would give the result the
-// previous iteration already folded in (d_k = min(d_{k-1}, U(d_{k-1})) with
-// U(d_{k-1}) = U(d_{k-2}) >= d_{k-1}).  The results are bit-identical.
+// float64 run), exchanged between workgroups with coherent loads.
+//
+// Skipping unchanged work.  A band vertex that was updated in the previous
+// iteration and none of whose neighbours changed there keeps its value
+// without evaluating its triangles: the update is a function of the
+// neighbours' values alone, so it would give the result the previous
+// iteration already folded in (d_k = min(d_{k-1}, U(d_{k-1})) with
+// U(d_{k-1}) = U(d_{k-2}) >= d_{k-1}).  A position whose value changes in
+// iteration k stamps k + 1 on its own mark and on those of its fan entries
+// (its neighbours); a band position of the previous band whose mark is below
+// k is skipped without touching its distance: it did not change in the
+// previous iteration, so this iteration's buffer, written two iterations
+// ago, already holds its value.  Such a position is finite (its topleset
+// entered the band after the one before it, whose values were finite) and
+// unchanged, hence converged.  The results are bit-identical to evaluating
+// the whole band.
 template <typename R>
 __device__ inline R ld_s(const R* s, int id) {
     return ld_c(s + id);
 }
-__device__ inline float mag(float x) { return fabsf(x); }
-__device__ inline double mag(double x) { return fabs(x); }
-__device__ inline bool flagged(float x) { return (__float_as_uint(x) >> 31) != 0u; }
-__device__ inline bool flagged(double x) { return __double_as_longlong(x) < 0; }
-template <typename R>
-__device__ inline R tagged(R d, bool changed) { return changed ? -d : d; }
 
 // Planar update of x0 from one triangle, folded into the minimum `best`
 // (which does not depend on the order in which the triangles come).
@@ -188,7 +190,7 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             const int id = e[q] & kFanId;
-            d[q] = mag(ld_s(sold, id));
+            d[q] = ld_s(sold, id);
             x[q] = a.xyz[id];
         }
 #pragma unroll
@@ -196,7 +198,7 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
             fold_update<R>(x0, x[q - 1], x[q], d[q - 1], d[q], best, q < cnt && (e[q] & kFanStart) == 0);
         if (closed && base + cnt == L) {      // entry L - 1, loaded again (rare path)
             const int id = a.fan[f0 + L - 1] & kFanId;
-            const R dl = mag(ld_s(sold, id));
+            const R dl = ld_s(sold, id);
             const float4 xl = a.xyz[id];
             fold_update<R>(x0, xl, xf, dl, d0, best);
         }
@@ -212,23 +214,15 @@ __device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e
     for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
 }
 
-// Distances (magnitudes) and coordinates of the first C fan entries;
-// returns whether any of them changed in the iteration that wrote it.
+// Distances and coordinates of the first C fan entries.
 template <typename R, int C>
-__device__ inline bool gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int id = e[q] & kFanId;
         d[q] = ld_s(sold, id);
         x[q] = a.xyz[id];
     }
-    bool chg = false;
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        chg |= flagged(d[q]);
-        d[q] = mag(d[q]);
-    }
-    return chg;
 }
 
 // Smallest planar update of position v over all its incident triangles.
@@ -258,10 +252,11 @@ __device__ inline bool converged(R dv, R dn, float tol) {
     return dv < inf_of<R>() && (dn == dv || absr(dn - dv) / dv < (R)tol);
 }
 
-// Marks a changed position's fan entries (its neighbours: a vertex is in the
-// fan of each of its neighbours) for iteration k1.
+// Marks a changed position v and its fan entries (its neighbours: a vertex is
+// in the fan of each of its neighbours) for iteration k1.
 template <int C>
-__device__ inline void mark_fan(const RelaxArgs& a, const int* e, int f0, int L, int k1, bool local) {
+__device__ inline void mark_fan(const RelaxArgs& a, int v, const int* e, int f0, int L, int k1, bool local) {
+    st_g(a.mark + v, k1, local);
 #pragma unroll
     for (int q = 0; q < C; ++q)
         if (q < L) st_g(a.mark + (e[q] & kFanId), k1, local);
@@ -269,17 +264,15 @@ __device__ inline void mark_fan(const RelaxArgs& a, const int* e, int f0, int L,
 }
 
 // Band positions p0, p0 + gsz, ... (< be) of one thread, in batches of
-// kBatch.  The marks and distances of a batch are loaded together (coalesced
-// across the group's threads).  A position updated in the previous iteration
-// (below bprev) that no neighbour marked for this iteration (mark < k) keeps
-// its value (see ld_s): it only rewrites this iteration's buffer when the
-// value changed in the previous iteration (the buffer then holds the one
-// before).  The other positions are evaluated, software-pipelined: while the
-// neighbour data of one are in flight, the fan entries of the next and the
-// fan row of the one after are loaded.  A position whose value changes marks
+// kBatch.  The marks of a batch are loaded together (coalesced across the
+// group's threads).  A position updated in the previous iteration (below
+// bprev) and not marked for this one (mark < k) keeps its value (see ld_s).
+// The other positions are evaluated, software-pipelined: while the neighbour
+// data of one are in flight, the fan entries of the next and the fan row of
+// the one after are loaded.  A position whose value changes marks itself and
 // its neighbours for the next iteration.  Returns the "not converged" vote of
 // the positions below tb; *evals counts the evaluated positions.
-constexpr int kBatch = 4;
+constexpr int kBatch = 8;
 
 template <typename R, int C>
 __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0, int be, int tb, int gsz,
@@ -288,29 +281,15 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
     unsigned notconv = 0;
     for (int pb = p0; pb < be; pb += kBatch * gsz) {
         int mk[kBatch];
-        R raw[kBatch];
 #pragma unroll
         for (int i = 0; i < kBatch; ++i) {
             const int p = pb + i * gsz;
-            mk[i] = 0;
-            raw[i] = (R)0;
-            if (p < be) {
-                mk[i] = ld_c(a.mark + vo + p);
-                raw[i] = ld_s(sold, vo + (int)p);
-            }
+            mk[i] = p < be && p < bprev ? ld_c(a.mark + vo + p) : k;
         }
         unsigned todo = 0;
 #pragma unroll
-        for (int i = 0; i < kBatch; ++i) {
-            const int p = pb + i * gsz;
-            if (p >= be) continue;
-            if (p >= bprev || mk[i] >= k) {
-                todo |= 1u << i;
-            } else {
-                if (flagged(raw[i])) st_g(snew + vo + p, mag(raw[i]), local);
-                if (p < tb && !(mag(raw[i]) < inf_of<R>())) notconv = 1;
-            }
-        }
+        for (int i = 0; i < kBatch; ++i)
+            if (pb + i * gsz < be && mk[i] >= k) todo |= 1u << i;
         if (!todo) continue;
         int p = pb + (long long)(__ffs(todo) - 1) * gsz;
         todo &= todo - 1;
@@ -329,10 +308,10 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
         for (;;) {
             const int v = vo + (int)p;
             const float4 x0 = a.xyz[v];
-            const R dv = mag(ld_s(sold, v));
+            const R dv = ld_s(sold, v);
             R d[C];
             float4 x[C];
-            (void)gather_fan<R, C>(a, e, sold, d, x);
+            gather_fan<R, C>(a, e, sold, d, x);
             // the next position's fan entries and the fan row of the one after
             const int Ln = fn1 - fn0;
             int en[C];
@@ -351,8 +330,8 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
             ++*evals;
             const R dn = best < dv ? best : dv;
             const bool changed = dn != dv;
-            st_g(snew + v, tagged(dn, changed), local);
-            if (changed) mark_fan<C>(a, e, f0, L, k + 1, local);
+            st_g(snew + v, dn, local);
+            if (changed) mark_fan<C>(a, v, e, f0, L, k + 1, local);
             if (p < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             if (pn < 0) break;
             p = pn;
@@ -628,7 +607,7 @@ void k_relax(RelaxArgs a) {
             const bool pipe = !(CACHE && be - cb <= gsz);
             if (pipe) {
                 for (long long pp = first; pp < bb; pp += gsz)
-                    st_g(snew + vo + pp, mag(ld_s(sold, vo + (int)pp)), local);
+                    st_g(snew + vo + pp, ld_s(sold, vo + (int)pp), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
                 notconv |= relax_band_marked<R, kChunk>(a, vo, (int)firstb, be, tb, gsz32, bprev, k, sold, snew, local,
                                                         &evals);
@@ -637,7 +616,7 @@ void k_relax(RelaxArgs a) {
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
                 const int v = vo + (int)pp;
                 if (pp < bb) {
-                    st_g(snew + v, mag(ld_s(sold, v)), local);
+                    st_g(snew + v, ld_s(sold, v), local);
                     continue;
                 }
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
@@ -648,18 +627,13 @@ void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                const R raw = ld_s(sold, v);
-                const R dv = mag(raw);
-                if (pp < bprev && ld_c(a.mark + v) < k) {     // no neighbour changed: keep (see ld_s)
-                    if (flagged(raw)) st_g(snew + v, dv, local);
-                    if (pp < tb && !(dv < kInfR)) notconv = 1;
-                    continue;
-                }
+                if (pp < bprev && ld_c(a.mark + v) < k) continue;    // not marked: keep (see ld_s)
+                const R dv = ld_s(sold, v);
                 R best = kInfR;
                 if (cached && cv == v) {
                     R d[kCache];
                     float4 x[kCache];
-                    (void)gather_fan<R, kCache>(a, ce, sold, d, x);
+                    gather_fan<R, kCache>(a, ce, sold, d, x);
                     eval_fan_first<R, kCache>(cx0, ce, d, x, cL, best);
                 } else {
                     const float4 x0 = cached ? cx0 : a.xyz[v];
@@ -668,12 +642,13 @@ void k_relax(RelaxArgs a) {
                 ++evals;
                 const R dn = best < dv ? best : dv;
                 const bool changed = dn != dv;
-                st_g(snew + v, tagged(dn, changed), local);
+                st_g(snew + v, dn, local);
                 if (changed) {
                     if (cached && cv == v) {
-                        mark_fan<kCache>(a, ce, 0, cL, k + 1, local);
+                        mark_fan<kCache>(a, v, ce, 0, cL, k + 1, local);
                     } else {
                         const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
+                        st_g(a.mark + v, k + 1, local);
                         for (int q = 0; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k + 1, local);
                     }
                 }
@@ -714,7 +689,7 @@ void k_relax(RelaxArgs a) {
         const R* sfin = (k & 1) ? sB : sA;
         for (long long p = g0; p < n; p += gsz) {
             const int v = a.perm[vo + p];
-            const R df = mag(ld_s(sfin, vo + (int)p));
+            const R df = ld_s(sfin, vo + (int)p);
             if (sizeof(R) == 8) a.out_d64[md.out_off + (v - vo)] = (double)df;
             else a.out_d[md.out_off + (v - vo)] = (float)df;
         }
