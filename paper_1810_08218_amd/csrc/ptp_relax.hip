@@ -573,6 +573,9 @@ void k_relax(RelaxArgs a) {
         int i = 1, lo_prev = 1, k = 0, runstat = 0;
         long long upd = 0;
         int bprev = 0;        // end of the previous iteration's band (none before the first)
+        // whether the previous iteration kept the marks (the register-cached
+        // loop neither reads nor writes them)
+        bool marks_kept = false;
         int evals = 0;        // this thread's evaluated positions
         // CACHE: the fan of the vertex this thread handled last.  While the
         // band is no wider than the group's threads, a band vertex keeps its
@@ -609,8 +612,8 @@ void k_relax(RelaxArgs a) {
                 for (long long pp = first; pp < bb; pp += gsz)
                     st_g(snew + vo + pp, ld_s(sold, vo + (int)pp), local);
                 const long long firstb = first_owned(bb, g032, gsz32);
-                notconv |= relax_band_marked<R, kChunk>(a, vo, (int)firstb, be, tb, gsz32, bprev, k, sold, snew, local,
-                                                        &evals);
+                notconv |= relax_band_marked<R, kChunk>(a, vo, (int)firstb, be, tb, gsz32, marks_kept ? bprev : 0, k,
+                                                        sold, snew, local, &evals);
                 cv = -1;
             }
             for (long long pp = pipe ? be : first; pp < be; pp += gsz) {
@@ -627,7 +630,9 @@ void k_relax(RelaxArgs a) {
                     cv = cL <= kCache ? v : -1;
                     if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
-                if (pp < bprev && ld_c(a.mark + v) < k) continue;    // not marked: keep (see ld_s)
+                // every band vertex is evaluated here (at most one per thread):
+                // the neighbours' loads need not wait for a mark, and no marks
+                // are stored (the next pipelined iteration evaluates its whole band)
                 const R dv = ld_s(sold, v);
                 R best = kInfR;
                 if (cached && cv == v) {
@@ -641,21 +646,12 @@ void k_relax(RelaxArgs a) {
                 }
                 ++evals;
                 const R dn = best < dv ? best : dv;
-                const bool changed = dn != dv;
                 st_g(snew + v, dn, local);
-                if (changed) {
-                    if (cached && cv == v) {
-                        mark_fan<kCache>(a, v, ce, 0, cL, k + 1, local);
-                    } else {
-                        const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
-                        st_g(a.mark + v, k + 1, local);
-                        for (int q = 0; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k + 1, local);
-                    }
-                }
                 if (pp < tb) notconv |= converged<R>(dv, dn, a.tol) ? 0u : 1u;
             }
             upd += be - bb;
             bprev = be;
+            marks_kept = pipe;
             if (!gb.sync(notconv, &any)) return;
             if (leader)
                 for (int r = i; r < lo; ++r) st_g(retire + r, k - 1, local);   // pushed out of the band
