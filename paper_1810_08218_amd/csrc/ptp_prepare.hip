@@ -744,6 +744,40 @@ __device__ inline int kth_bit(unsigned w, int k) {
     return bit;
 }
 
+// Expansion of vertex u (mesh-local) of a level of bfs_big from its
+// neighbour row (r0, r1): each neighbour not yet visited is marked visited
+// and joins the next topleset (global bitmap word, LDS summary bit); a row
+// that ends in kEllMore is expanded from the vertex's wedges instead.
+__device__ inline void bfs_big_expand(const BfsLdsArgs& a, int vo, int u, int4 r0, int4 r1, unsigned* vis,
+                                      unsigned* nxt, unsigned* summ) {
+    auto visit = [&](int x) {
+        const unsigned bit = 1u << (x & 31);
+        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
+            atomicOr(nxt + (x >> 5), bit);
+            atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
+        }
+    };
+    const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    if (ev[kEll - 1] != kEllMore) {
+#pragma unroll
+        for (int q = 0; q < kEll; ++q)
+            if (ev[q] >= 0) visit(ev[q] - vo);
+        return;
+    }
+    const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
+    for (int eb = e0; eb < e1; eb += kExpand) {
+        const int cnt = min(kExpand, e1 - eb);
+        int2 nb[kExpand];
+#pragma unroll
+        for (int q = 0; q < kExpand; ++q) nb[q] = q < cnt ? a.wedgeO[eb + q] : make_int2(vo + u, vo + u);
+#pragma unroll
+        for (int q = 0; q < kExpand; ++q) {
+            visit(nb[q].x - vo);
+            visit(nb[q].y - vo);
+        }
+    }
+}
+
 __device__ void bfs_big(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
@@ -795,6 +829,10 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
         if (totw == 0) break;
         if (tid == 0) offs[r] = base;
         int total = 0;
+        // a level staged in one round keeps each thread's vertices (at most
+        // two) in registers for its expansion
+        const bool one_round = totw <= kBigWl;
+        int um0 = -1, um1 = -1;
         for (int w0 = 0; w0 < totw; w0 += kBigWl) {
             const int cnt = min(kBigWl, totw - w0);
             int k = wbase;
@@ -812,9 +850,9 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
             // completed in L2 before the last barrier)
             const unsigned v0 = tid < cnt ? ld_c(nxt + wl[tid]) : 0u;
             const unsigned v1 = tid + kLdsBlock < cnt ? ld_c(nxt + wl[tid + kLdsBlock]) : 0u;
-            int t0, t1;
+            int t0, t1 = 0;
             const int p0 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v0), &t0);
-            const int p1 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v1), &t1);
+            const int p1 = cnt > kLdsBlock ? block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v1), &t1) : 0;
             if (tid < cnt) {
                 wpre[tid] = p0;
                 wv[tid] = v0;
@@ -838,6 +876,8 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
                 a.perm[vo + pos] = vo + u;
                 a.iperm[vo + u] = vo + pos;
                 a.level[vo + u] = r;
+                if (t == tid) um0 = u;
+                else if (t == tid + kLdsBlock) um1 = u;
             }
             total += tv;
             lds_barrier();                          // the stage is rewritten by the next round
@@ -853,42 +893,26 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
         }
         wait_memory();                              // perm stores and cleared words landed
         __syncthreads();
-        for (int t = tid; t < total; t += kLdsBlock) {
-            const int u = ld_c(a.perm + vo + base + t) - vo;
-            const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + u));
-            const int4 r0 = er[0], r1 = er[1];
-            const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-            if (ev[kEll - 1] != kEllMore) {
-#pragma unroll
-                for (int q = 0; q < kEll; ++q) {
-                    if (ev[q] < 0) continue;
-                    const int x = ev[q] - vo;
-                    const unsigned bit = 1u << (x & 31);
-                    if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
-                        atomicOr(nxt + (x >> 5), bit);
-                        atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
-                    }
-                }
-                continue;
+        if (one_round && total <= 2 * kLdsBlock) {
+            // both neighbour rows loaded before either is expanded
+            int4 ra0 = make_int4(-1, -1, -1, -1), rb0 = ra0, ra1 = ra0, rb1 = ra0;
+            if (um0 >= 0) {
+                const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + um0));
+                ra0 = er[0];
+                rb0 = er[1];
             }
-            const int e0 = a.row[vo + u], e1 = a.row[vo + u + 1];
-            for (int eb = e0; eb < e1; eb += kExpand) {
-                const int cnt = min(kExpand, e1 - eb);
-                int2 nb[kExpand];
-#pragma unroll
-                for (int q = 0; q < kExpand; ++q) nb[q] = q < cnt ? a.wedgeO[eb + q] : make_int2(vo + u, vo + u);
-#pragma unroll
-                for (int q = 0; q < kExpand; ++q) {
-                    const int xs[2] = {nb[q].x - vo, nb[q].y - vo};
-                    for (int z = 0; z < 2; ++z) {
-                        const int x = xs[z];
-                        const unsigned bit = 1u << (x & 31);
-                        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
-                            atomicOr(nxt + (x >> 5), bit);
-                            atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
-                        }
-                    }
-                }
+            if (um1 >= 0) {
+                const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + um1));
+                ra1 = er[0];
+                rb1 = er[1];
+            }
+            if (um0 >= 0) bfs_big_expand(a, vo, um0, ra0, rb0, vis, nxt, summ);
+            if (um1 >= 0) bfs_big_expand(a, vo, um1, ra1, rb1, vis, nxt, summ);
+        } else {
+            for (int t = tid; t < total; t += kLdsBlock) {
+                const int u = ld_c(a.perm + vo + base + t) - vo;
+                const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + u));
+                bfs_big_expand(a, vo, u, er[0], er[1], vis, nxt, summ);
             }
         }
         wait_memory();                              // the frontier's atomics completed
