@@ -716,16 +716,17 @@ __device__ void bfs_lds(const BfsLdsArgs& a) {
 }
 
 // ---- BFS of one larger mesh in one workgroup -----------------------------
-// For a mesh whose visited bitmap fits in LDS but whose next-topleset bitmap
-// and rank table do not: the next topleset is a bitmap in global memory
-// (this workgroup's share of the frontier bitmaps, served from L2), and a
-// summary bitmap in LDS marks its non-empty words, so a level visits only the
-// words that hold vertices instead of scanning the whole bitmap.  Per level:
-// the non-empty words are staged in ascending order in rounds of kBigWl (word,
-// its bits, the rank of its first vertex), each vertex is found by a binary
-// search over the ranks (one vertex per thread), emitted in canonical order,
-// then the level is cleared and expanded as in bfs_lds, the new vertices'
-// bits set with global atomics (their summary bits with LDS atomics).
+// For a mesh whose visited bitmap fits in LDS but whose topleset bitmaps and
+// rank table do not.  The expansion marks new vertices in the visited bitmap
+// and the words it touches in a summary bitmap, both in LDS; the vertices of
+// the previous levels are a bitmap `done` in global memory (this workgroup's
+// share of the frontier bitmaps, served from L2).  Per level the touched
+// words are staged in ascending order in rounds of kBigWl; a staged word's
+// new topleset is visited & ~done, and done takes the visited word (one load
+// and one store per staged word, by one thread: no global atomics, which
+// serialise on the words a level shares).  Each vertex is then found by a
+// binary search over the ranks (one vertex per thread), emitted in canonical
+// order, and expanded with LDS atomics only.
 constexpr int kBigWl = 2048;
 
 __device__ inline int kth_bit(unsigned w, int k) {
@@ -746,16 +747,14 @@ __device__ inline int kth_bit(unsigned w, int k) {
 
 // Expansion of vertex u (mesh-local) of a level of bfs_big from its
 // neighbour row (r0, r1): each neighbour not yet visited is marked visited
-// and joins the next topleset (global bitmap word, LDS summary bit); a row
-// that ends in kEllMore is expanded from the vertex's wedges instead.
+// and its word in the summary (LDS atomics only); a row that ends in
+// kEllMore is expanded from the vertex's wedges instead.
 __device__ inline void bfs_big_expand(const BfsLdsArgs& a, int vo, int u, int4 r0, int4 r1, unsigned* vis,
-                                      unsigned* nxt, unsigned* summ) {
+                                      unsigned* summ) {
     auto visit = [&](int x) {
         const unsigned bit = 1u << (x & 31);
-        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit)) {
-            atomicOr(nxt + (x >> 5), bit);
+        if (!(vis[x >> 5] & bit) && !(atomicOr(vis + (x >> 5), bit) & bit))
             atomicOr(summ + (x >> 10), 1u << ((x >> 5) & 31));
-        }
     };
     const int ev[kEll] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
     if (ev[kEll - 1] != kEllMore) {
@@ -790,11 +789,11 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
     int* wl = reinterpret_cast<int*>(summ + SW);                 // [kBigWl]
     int* wpre = wl + kBigWl;                                     // [kBigWl + 1]
     unsigned* wv = reinterpret_cast<unsigned*>(wpre + kBigWl + 1);   // [kBigWl]
-    unsigned* nxt = a.bits + 2ll * d.w_off;                      // [W], global
+    unsigned* done = a.bits + 2ll * d.w_off;                     // [W], global
     int* offs = a.offsets + vo + b;
     for (int x = tid; x < W; x += kLdsBlock) {
         vis[x] = 0u;
-        nxt[x] = 0u;
+        done[x] = 0u;
     }
     for (int x = tid; x < SW; x += kLdsBlock) summ[x] = 0u;
     wait_memory();                                               // cleared before the atomics
@@ -803,12 +802,8 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
     for (int s = tid; s < d.m; s += kLdsBlock) {
         const int v = a.S[d.s_in + s];
         const unsigned bit = 1u << (v & 31);
-        if (atomicOr(vis + (v >> 5), bit) & bit) {
-            dup = 1;
-        } else {
-            atomicOr(nxt + (v >> 5), bit);
-            atomicOr(summ + (v >> 10), 1u << ((v >> 5) & 31));
-        }
+        if (atomicOr(vis + (v >> 5), bit) & bit) dup = 1;
+        else atomicOr(summ + (v >> 10), 1u << ((v >> 5) & 31));
     }
     wait_memory();
     if (__syncthreads_or(dup)) {
@@ -846,10 +841,19 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
                 }
             }
             lds_barrier();
-            // the staged words' bits: coherent loads (the expansion's atomics
-            // completed in L2 before the last barrier)
-            const unsigned v0 = tid < cnt ? ld_c(nxt + wl[tid]) : 0u;
-            const unsigned v1 = tid + kLdsBlock < cnt ? ld_c(nxt + wl[tid + kLdsBlock]) : 0u;
+            // the staged words' new vertices: visited, not done (coherent
+            // loads: the stores of done completed before the level's barrier)
+            unsigned v0 = 0u, v1 = 0u;
+            if (tid < cnt) {
+                const unsigned vw = vis[wl[tid]];
+                v0 = vw & ~ld_c(done + wl[tid]);
+                done[wl[tid]] = vw;
+            }
+            if (tid + kLdsBlock < cnt) {
+                const unsigned vw = vis[wl[tid + kLdsBlock]];
+                v1 = vw & ~ld_c(done + wl[tid + kLdsBlock]);
+                done[wl[tid + kLdsBlock]] = vw;
+            }
             int t0, t1 = 0;
             const int p0 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v0), &t0);
             const int p1 = cnt > kLdsBlock ? block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v1), &t1) : 0;
@@ -882,16 +886,10 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
             total += tv;
             lds_barrier();                          // the stage is rewritten by the next round
         }
-        // clear the level's words (global) and its summary
-        for (int x = s0; x < s1; ++x) {
-            unsigned sm = summ[x];
-            while (sm) {
-                nxt[x * 32 + __ffs(sm) - 1] = 0u;
-                sm &= sm - 1;
-            }
-            summ[x] = 0u;
-        }
-        wait_memory();                              // perm stores and cleared words landed
+        // the summary collects the next level's words; the level's stores of
+        // done and perm complete before the next level reads them
+        for (int x = s0; x < s1; ++x) summ[x] = 0u;
+        wait_memory();
         __syncthreads();
         if (one_round && total <= 2 * kLdsBlock) {
             // both neighbour rows loaded before either is expanded
@@ -906,17 +904,16 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
                 ra1 = er[0];
                 rb1 = er[1];
             }
-            if (um0 >= 0) bfs_big_expand(a, vo, um0, ra0, rb0, vis, nxt, summ);
-            if (um1 >= 0) bfs_big_expand(a, vo, um1, ra1, rb1, vis, nxt, summ);
+            if (um0 >= 0) bfs_big_expand(a, vo, um0, ra0, rb0, vis, summ);
+            if (um1 >= 0) bfs_big_expand(a, vo, um1, ra1, rb1, vis, summ);
         } else {
             for (int t = tid; t < total; t += kLdsBlock) {
                 const int u = ld_c(a.perm + vo + base + t) - vo;
                 const int4* er = reinterpret_cast<const int4*>(a.ellO + (size_t)kEll * (vo + u));
-                bfs_big_expand(a, vo, u, er[0], er[1], vis, nxt, summ);
+                bfs_big_expand(a, vo, u, er[0], er[1], vis, summ);
             }
         }
-        wait_memory();                              // the frontier's atomics completed
-        __syncthreads();
+        __syncthreads();                            // the expansion's LDS atomics completed
         base += total;
     }
     const int rho = r, reach = base;
