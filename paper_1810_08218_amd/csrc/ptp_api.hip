@@ -286,6 +286,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(int) * (G + 8 + B),             // glist_run64
         sizeof(double) * (size_t)z.S * (kCvtChunks * 6 + 4),   // cvt partial sums, centroids
         sizeof(int) * N,                       // mark
+        sizeof(int) * kFan6 * N,               // fan6
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -336,6 +337,7 @@ Work carve(void* base, const Layout& L) {
     w.glist_run64 = reinterpret_cast<int*>(b + L.off[34]);
     w.cvt = reinterpret_cast<double*>(b + L.off[35]);
     w.mark = reinterpret_cast<int*>(b + L.off[36]);
+    w.fan6 = reinterpret_cast<int*>(b + L.off[37]);
     return w;
 }
 

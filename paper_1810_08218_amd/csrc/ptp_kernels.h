@@ -80,9 +80,10 @@ struct Work {
     int* glist_run64;   // [gmax + 8 + B]
     double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
     int* mark;          // [N]     per position: the last iteration + 1 in which a neighbour changed
+    int* fan6;          // [6N]    per position its first kFan6 fan entries in a fixed-size record
 };
 
-constexpr int kLayoutParts = 37;
+constexpr int kLayoutParts = 38;
 
 // Lloyd step: every cell's sums are split over this many chunks of the
 // faces (or vertices), each reduced in a fixed order.
@@ -104,7 +105,15 @@ constexpr int kEllMore = -2;
 // entries (every wedge a chain of its own).
 constexpr int kFanStart = (int)0x80000000u;
 constexpr int kFanClosed = 1 << 30;
-constexpr int kFanId = kFanClosed - 1;
+constexpr int kFanId = (1 << 29) - 1;    // positions stay below 2^29
+
+// The same fans as records of kFan6 entries per position (fan6), read by
+// position without the fan row: entries past the fan's length carry kFan6Pad
+// and entry 0's id; a fan longer than kFan6 has kFan6Pad on its entry 0 and
+// continues in the row form; an empty fan is the position itself without
+// kFanStart (every non-empty fan opens with kFanStart).
+constexpr int kFan6 = 6;
+constexpr int kFan6Pad = 1 << 29;
 constexpr int kFanChainMax = 16;     // above this degree every wedge is a chain of its own
 
 struct Sizes {

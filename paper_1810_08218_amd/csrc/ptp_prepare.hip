@@ -979,13 +979,14 @@ __global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const in
 // positions), each round issued for all of them before any result is used.
 constexpr int kReItems = 4;
 constexpr int kReFan = 8;
+static_assert(kReFan >= kFan6, "the fan records are filled from the entries in registers");
 
 __global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V, const MeshDesc* mesh, int B,
                                                     const int* vo, const int* __restrict__ iperm,
                                                     const int* __restrict__ rowO, const int* __restrict__ fanO,
                                                     const int* __restrict__ fanlen, const int* __restrict__ fanrow,
                                                     long long N, float4* __restrict__ xyz, int* __restrict__ fan,
-                                                    const int* ctrl) {
+                                                    int* __restrict__ fan6, const int* ctrl) {
     if (gated(ctrl)) return;
     for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
         int bq[kTileItems];
@@ -1031,6 +1032,17 @@ __global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V,
 #pragma unroll
                 for (int q = 0; q < kReFan; ++q)
                     if (q < len[i]) fan[fr[i] + q] = e[i][q];
+                // the fixed-size record of the first kFan6 entries
+                int rec[kFan6];
+                const int first = len[i] > 0 ? e[i][0] : p[i];
+#pragma unroll
+                for (int q = 0; q < kFan6; ++q)
+                    rec[q] = q < len[i] ? e[i][q] : (q == 0 ? p[i] : (first & kFanId) | kFan6Pad);
+                if (len[i] > kFan6) rec[0] |= kFan6Pad;
+                int2* r6 = reinterpret_cast<int2*>(fan6 + (size_t)kFan6 * p[i]);
+                r6[0] = make_int2(rec[0], rec[1]);
+                r6[1] = make_int2(rec[2], rec[3]);
+                r6[2] = make_int2(rec[4], rec[5]);
                 for (int q = kReFan; q < len[i]; ++q) {
                     const int x = fanO[2 * (long long)r0[i] + q];
                     fan[fr[i] + q] = iperm[x & kFanId] | (x & ~kFanId);
@@ -1253,7 +1265,7 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
     e = scan_inplace(w.fanrow + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo, w.iperm,
-                       w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.ctrl);
+                       w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.fan6, w.ctrl);
     return hipGetLastError();
 }
 

@@ -116,6 +116,7 @@ struct RelaxArgs {
     int* ctrl;
     unsigned* bar;
     int* mark;             // [N] per position: 1 + the last iteration in which a fan neighbour changed
+    const int* fan6;       // [6N] fixed-size fan records by position
     long long N;
     float* out_d;
     double* out_d64;
@@ -263,21 +264,51 @@ __device__ inline void mark_fan(const RelaxArgs& a, int v, const int* e, int f0,
     for (int q = C; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k1, local);
 }
 
+// The fan record of position v (global), loaded as three 8-byte words.
+__device__ inline void load_fan6(const RelaxArgs& a, int v, int* e) {
+    const int2* r = reinterpret_cast<const int2*>(a.fan6 + (size_t)kFan6 * v);
+    const int2 x0 = r[0], x1 = r[1], x2 = r[2];
+    e[0] = x0.x;
+    e[1] = x0.y;
+    e[2] = x1.x;
+    e[3] = x1.y;
+    e[4] = x2.x;
+    e[5] = x2.y;
+}
+
+// Length of the fan whose record is e (and the start of its row, needed for
+// fans longer than the record, read from the row form then).
+__device__ inline void fan6_length(const RelaxArgs& a, int v, const int* e, int& L, int& f0) {
+    f0 = 0;
+    if (!(e[0] & kFanStart)) {
+        L = 0;
+    } else if (e[0] & kFan6Pad) {
+        f0 = a.fanrow[v];
+        L = a.fanrow[v + 1] - f0;
+    } else {
+        L = 1;
+#pragma unroll
+        for (int q = 1; q < kFan6; ++q) L += (e[q] & kFan6Pad) ? 0 : 1;
+    }
+}
+
 // Band positions p0, p0 + gsz, ... (< be) of one thread, in batches of
 // kBatch.  The marks of a batch are loaded together (coalesced across the
 // group's threads).  A position updated in the previous iteration (below
 // bprev) and not marked for this one (mark < k) keeps its value (see ld_s).
 // The other positions are evaluated, software-pipelined: while the neighbour
-// data of one are in flight, the fan entries of the next and the fan row of
-// the one after are loaded.  A position whose value changes marks itself and
-// its neighbours for the next iteration.  Returns the "not converged" vote of
-// the positions below tb; *evals counts the evaluated positions.
+// data of one are in flight, the fan record of the next is loaded (read by
+// position: no fan row in front of it).  A position whose value changes
+// marks itself and its neighbours for the next iteration.  Returns the "not
+// converged" vote of the positions below tb; *evals counts the evaluated
+// positions.
 constexpr int kBatch = 8;
 
 template <typename R, int C>
 __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0, int be, int tb, int gsz,
                                              int bprev, int k, const R* sold, R* snew,
                                              bool local, int* evals) {
+    static_assert(C == kFan6, "the band loop reads the fixed-size fan records");
     unsigned notconv = 0;
     for (int pb = p0; pb < be; pb += kBatch * gsz) {
         int mk[kBatch];
@@ -291,39 +322,32 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
         for (int i = 0; i < kBatch; ++i)
             if (pb + i * gsz < be && mk[i] >= k) todo |= 1u << i;
         if (!todo) continue;
-        int p = pb + (long long)(__ffs(todo) - 1) * gsz;
+        int p = pb + (__ffs(todo) - 1) * gsz;
         todo &= todo - 1;
-        int f0 = a.fanrow[vo + p];
-        int L = a.fanrow[vo + p + 1] - f0;
         int e[C];
-        load_fan<C>(a, vo + (int)p, f0, L, e);
+        load_fan6(a, vo + p, e);
         int pn = -1;
-        int fn0 = 0, fn1 = 0;
         if (todo) {
-            pn = pb + (long long)(__ffs(todo) - 1) * gsz;
+            pn = pb + (__ffs(todo) - 1) * gsz;
             todo &= todo - 1;
-            fn0 = a.fanrow[vo + pn];
-            fn1 = a.fanrow[vo + pn + 1];
         }
         for (;;) {
-            const int v = vo + (int)p;
+            const int v = vo + p;
             const float4 x0 = a.xyz[v];
             const R dv = ld_s(sold, v);
             R d[C];
             float4 x[C];
             gather_fan<R, C>(a, e, sold, d, x);
-            // the next position's fan entries and the fan row of the one after
-            const int Ln = fn1 - fn0;
+            // the next position's fan record
             int en[C];
-            if (pn >= 0) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
+            if (pn >= 0) load_fan6(a, vo + pn, en);
             int pnn = -1;
-            int fnn0 = 0, fnn1 = 0;
             if (todo) {
-                pnn = pb + (long long)(__ffs(todo) - 1) * gsz;
+                pnn = pb + (__ffs(todo) - 1) * gsz;
                 todo &= todo - 1;
-                fnn0 = a.fanrow[vo + pnn];
-                fnn1 = a.fanrow[vo + pnn + 1];
             }
+            int L, f0;
+            fan6_length(a, v, e, L, f0);
             R best = inf_of<R>();
             eval_fan_first<R, C>(x0, e, d, x, L, best);
             if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
@@ -336,12 +360,8 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
             if (pn < 0) break;
             p = pn;
             pn = pnn;
-            f0 = fn0;
-            L = Ln;
 #pragma unroll
             for (int q = 0; q < C; ++q) e[q] = en[q];
-            fn0 = fnn0;
-            fn1 = fnn1;
         }
     }
     return notconv;
@@ -868,6 +888,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     a.ctrl = w.ctrl;
     a.bar = w.bar;
     a.mark = w.mark;
+    a.fan6 = w.fan6;
     a.N = p.N;
     a.out_d = p.out_d;
     a.out_d64 = p.out_d64;
