@@ -452,9 +452,10 @@ def bench_grids(P, I, stream):
     return out
 
 
-def bench_bumpy9(P, I, stream, args):
-    """Level-9 bumpy icosphere, 32 sources: labelled run; learned warm start
-    (distances only); Lloyd steps on its Voronoi cells."""
+def bench_bumpy9(P, I, stream, args, full=True):
+    """Level-9 bumpy icosphere, 32 sources: labelled run; unless `full` is
+    false, the learned warm start (distances only) and Lloyd steps on its
+    Voronoi cells."""
     import torch
     mesh = I.bumpy_icosphere(level=9, seed=3, n_sources=32)
     V, F, S = (torch.from_numpy(x).cuda() for x in (mesh.V, mesh.F, mesh.S))
@@ -472,6 +473,9 @@ def bench_bumpy9(P, I, stream, args):
            "iterations": st["iterations"], "toplesets": st["n_toplesets"], "vertex_updates": U,
            "vertex_updates_per_s_run": round(U / (ms * 1e-3), 1), "workgroups": st["workgroups"],
            "alg_GBps": round(U * BYTES_PER_UPDATE / (ms * 1e-3) / 1e9, 1)}   # label passes timed, not counted
+    if not full:
+        plan.close()
+        return out
     # Lloyd steps on the Voronoi cells (a few iterations: prepare, labelled run, step)
     Sg = S.clone()
     t0 = time.perf_counter()
@@ -587,8 +591,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "batch"], default="all",
-                    help="batch: the timed batch steps only (for profiling the timed launch)")
+    ap.add_argument("--only", choices=["all", "batch", "l9"], default="all",
+                    help="batch: the timed batch steps only (for profiling the timed launch); "
+                         "l9: the labelled runs of the level-9 bumpy icosphere only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start legs")
     ap.add_argument("--no-autotune", action="store_true")
@@ -615,6 +620,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.only == "l9":
+        note("bumpy icosphere level 9 (labelled runs only)")
+        out = bench_bumpy9(P, I, stream, args, full=False)
+        gc.collect()
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": out["workload"], "bumpy_icosphere_l9": out}), flush=True)
+        return
 
     W = BatchWorkload(P, I)
     H = bench_batch_steps(P, W, args.steps, args.warmup, stream)
