@@ -73,8 +73,8 @@ struct Work {
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
-    int* fanrow;        // [N + 1] fan CSR over positions
-    int* fan;           // [6F]    fans of the incident triangles, positions and flags
+    int* fanrow;        // [N + 1] row form over positions of the fans longer than kFan6 (others empty)
+    int* fan;           // [6F]    those fans' entries, positions and flags
     int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
     WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation
     int* glist_run64;   // [gmax + 8 + B]

@@ -956,21 +956,26 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_one(BfsLdsArgs a) {
     else bfs_lds(a);
 }
 
-// Fan length of each position, into fanrow[p + 1] (the fans themselves are
-// built once per prepare by vertex id, independent of the sources).
+// Row-form length of each position, into fanrow[p + 1]: its fan's length if
+// the fan is longer than a fixed-size record holds, else 0 (the fans
+// themselves are built once per prepare by vertex id, independent of the
+// sources).
 __global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const int* fanlen, long long N,
                                                        int* fanrow, const int* ctrl) {
     if (gated(ctrl)) return;
     const long long gsz = (long long)gridDim.x * kBlock;
     for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        fanrow[p + 1] = fanlen[perm[p]];
+        const int len = fanlen[perm[p]];
+        fanrow[p + 1] = len > kFan6 ? len : 0;      // the row form holds the longer fans only
         if (p == 0) fanrow[0] = 0;
     }
 }
 
 // Coordinates and fans in topleset order: the position of each vertex takes
 // its coordinates and a copy of its fan with every neighbour id turned into
-// that neighbour's position (flags kept).  The loop runs over vertex ids, so
+// that neighbour's position (flags kept): the first kFan6 entries in its
+// fixed-size record, the whole fan in the row form as well when it is longer.
+// The loop runs over vertex ids, so
 // the fans are read in storage order and the neighbours' positions are
 // looked up around the vertex's own id (meshes number neighbours closely);
 // only the writes scatter, one row per vertex.  A thread takes kReItems
@@ -1015,7 +1020,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V,
             }
 #pragma unroll
             for (int i = 0; i < kReItems; ++i) {
-                fr[i] = len[i] > 0 ? fanrow[p[i]] : 0;
+                fr[i] = len[i] > kFan6 ? fanrow[p[i]] : 0;
 #pragma unroll
                 for (int q = 0; q < kReFan; ++q) e[i][q] = q < len[i] ? fanO[2 * (long long)r0[i] + q] : 0;
             }
@@ -1029,9 +1034,11 @@ __global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V,
                 const long long v = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
                 if (v >= N) continue;
                 xyz[p[i]] = make_float4(c[i][0], c[i][1], c[i][2], 0.f);
+                if (len[i] > kFan6) {     // a longer fan: also in the row form
 #pragma unroll
-                for (int q = 0; q < kReFan; ++q)
-                    if (q < len[i]) fan[fr[i] + q] = e[i][q];
+                    for (int q = 0; q < kReFan; ++q)
+                        if (q < len[i]) fan[fr[i] + q] = e[i][q];
+                }
                 // the fixed-size record of the first kFan6 entries
                 int rec[kFan6];
                 const int first = len[i] > 0 ? e[i][0] : p[i];

@@ -206,64 +206,6 @@ __device__ inline void eval_fan_rest(const RelaxArgs& a, int v, const float4 x0,
     }
 }
 
-// First C entries of the fan at [f0, f0 + L) of position v, padded with
-// entry 0 (with v for an empty fan).
-template <int C>
-__device__ inline void load_fan(const RelaxArgs& a, int v, int f0, int L, int* e) {
-    e[0] = L > 0 ? a.fan[f0] : v;
-#pragma unroll
-    for (int q = 1; q < C; ++q) e[q] = q < L ? a.fan[f0 + q] : e[0];
-}
-
-// Distances and coordinates of the first C fan entries.
-template <typename R, int C>
-__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        const int id = e[q] & kFanId;
-        d[q] = ld_s(sold, id);
-        x[q] = a.xyz[id];
-    }
-}
-
-// Smallest planar update of position v over all its incident triangles.
-template <typename R, int C>
-__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const R* sold, R& best) {
-    best = inf_of<R>();
-    const int f0 = a.fanrow[v], L = a.fanrow[v + 1] - f0;
-    int e[C];
-    R d[C];
-    float4 x[C];
-    load_fan<C>(a, v, f0, L, e);
-    gather_fan<R, C>(a, e, sold, d, x);
-    eval_fan_first<R, C>(x0, e, d, x, L, best);
-    if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
-}
-
-// Convergence of one position between two iterations (Eq. lower_band): a
-// value that was +inf is not converged, an unchanged one is (no 0/0 at
-// coincident vertices), otherwise |dn - dv| / dv < tol.  The Jacobi rule runs
-// it with tol = 0: "finite and unchanged" (once its band holds every
-// topleset, each reachable value is finite, so this is "unchanged").
-__device__ inline float absr(float x) { return fabsf(x); }
-__device__ inline double absr(double x) { return fabs(x); }
-
-template <typename R>
-__device__ inline bool converged(R dv, R dn, float tol) {
-    return dv < inf_of<R>() && (dn == dv || absr(dn - dv) / dv < (R)tol);
-}
-
-// Marks a changed position v and its fan entries (its neighbours: a vertex is
-// in the fan of each of its neighbours) for iteration k1.
-template <int C>
-__device__ inline void mark_fan(const RelaxArgs& a, int v, const int* e, int f0, int L, int k1, bool local) {
-    st_g(a.mark + v, k1, local);
-#pragma unroll
-    for (int q = 0; q < C; ++q)
-        if (q < L) st_g(a.mark + (e[q] & kFanId), k1, local);
-    for (int q = C; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k1, local);
-}
-
 // The fan record of position v (global), loaded as three 8-byte words.
 __device__ inline void load_fan6(const RelaxArgs& a, int v, int* e) {
     const int2* r = reinterpret_cast<const int2*>(a.fan6 + (size_t)kFan6 * v);
@@ -290,6 +232,58 @@ __device__ inline void fan6_length(const RelaxArgs& a, int v, const int* e, int&
 #pragma unroll
         for (int q = 1; q < kFan6; ++q) L += (e[q] & kFan6Pad) ? 0 : 1;
     }
+}
+
+
+// Distances and coordinates of the first C fan entries.
+template <typename R, int C>
+__device__ inline void gather_fan(const RelaxArgs& a, const int* e, const R* sold, R* d, float4* x) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int id = e[q] & kFanId;
+        d[q] = ld_s(sold, id);
+        x[q] = a.xyz[id];
+    }
+}
+
+// Smallest planar update of position v over all its incident triangles.
+template <typename R, int C>
+__device__ inline void best_update(const RelaxArgs& a, int v, const float4 x0, const R* sold, R& best) {
+    static_assert(C == kFan6, "fans are read from the fixed-size records");
+    best = inf_of<R>();
+    int e[C];
+    R d[C];
+    float4 x[C];
+    load_fan6(a, v, e);
+    gather_fan<R, C>(a, e, sold, d, x);
+    int L, f0;
+    fan6_length(a, v, e, L, f0);
+    eval_fan_first<R, C>(x0, e, d, x, L, best);
+    if (L > C) eval_fan_rest<R, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, d[0], x[0], sold, best);
+}
+
+// Convergence of one position between two iterations (Eq. lower_band): a
+// value that was +inf is not converged, an unchanged one is (no 0/0 at
+// coincident vertices), otherwise |dn - dv| / dv < tol.  The Jacobi rule runs
+// it with tol = 0: "finite and unchanged" (once its band holds every
+// topleset, each reachable value is finite, so this is "unchanged").
+__device__ inline float absr(float x) { return fabsf(x); }
+__device__ inline double absr(double x) { return fabs(x); }
+
+template <typename R>
+__device__ inline bool converged(R dv, R dn, float tol) {
+    return dv < inf_of<R>() && (dn == dv || absr(dn - dv) / dv < (R)tol);
+}
+
+// Marks a changed position v and its fan entries (its neighbours: a vertex is
+// in the fan of each of its neighbours) for iteration k1.
+template <int C>
+__device__ inline void mark_fan(const RelaxArgs& a, int v, const int* e, int f0, int L, int k1, bool local) {
+    st_g(a.mark + v, k1, local);
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (q < L) st_g(a.mark + (e[q] & kFanId), k1, local);
+    for (int q = C; q < L; ++q) st_g(a.mark + (a.fan[f0 + q] & kFanId), k1, local);
 }
 
 // Band positions p0, p0 + gsz, ... (< be) of one thread, in batches of
@@ -368,41 +362,32 @@ __device__ inline unsigned relax_band_marked(const RelaxArgs& a, int vo, int p0,
 }
 
 // One certification sweep over positions p, p + gsz, ... (< end) of one
-// thread, pipelined like relax_band_pipelined: a bound below the planar
-// update from the neighbours' bounds is withdrawn (+inf), in place.  Returns
-// whether this thread withdrew any; counts them into *rejected.
+// thread, pipelined like the band loop (the next position's fan record is
+// loaded while the neighbour data of the current one are in flight): a bound
+// below the planar update from the neighbours' bounds is withdrawn (+inf),
+// in place.  Returns whether this thread withdrew any; counts them into
+// *rejected.
 template <int C>
 __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long long p, long long end,
                                              long long gsz, float* d, bool local, int* rejected) {
+    static_assert(C == kFan6, "fans are read from the fixed-size records");
     unsigned changed = 0;
     if (p >= end) return 0;
-    int f0 = a.fanrow[vo + p];
-    int L = a.fanrow[vo + p + 1] - f0;
     int e[C];
-    load_fan<C>(a, vo + (int)p, f0, L, e);
-    long long pn = p + gsz;
-    int fn0 = 0, fn1 = 0;
-    if (pn < end) {
-        fn0 = a.fanrow[vo + pn];
-        fn1 = a.fanrow[vo + pn + 1];
-    }
+    load_fan6(a, vo + (int)p, e);
     for (;;) {
         const int v = vo + (int)p;
         const float4 x0 = a.xyz[v];
         const float wv = ld_c(d + v);
         float dd[C];
         float4 x[C];
-        (void)gather_fan<float, C>(a, e, d, dd, x);
-        const long long pnn = pn + gsz;
-        const int Ln = fn1 - fn0;
+        gather_fan<float, C>(a, e, d, dd, x);
+        const long long pn = p + gsz;
         int en[C];
-        int fnn0 = 0, fnn1 = 0;
-        if (pn < end) load_fan<C>(a, vo + (int)pn, fn0, Ln, en);
-        if (pnn < end) {
-            fnn0 = a.fanrow[vo + pnn];
-            fnn1 = a.fanrow[vo + pnn + 1];
-        }
+        if (pn < end) load_fan6(a, vo + (int)pn, en);
         if (wv < kInf) {
+            int L, f0;
+            fan6_length(a, v, e, L, f0);
             float best = kInf;
             eval_fan_first<float, C>(x0, e, dd, x, L, best);
             if (L > C) eval_fan_rest<float, C>(a, v, x0, f0, L, (e[0] & kFanClosed) != 0, dd[0], x[0], d, best);
@@ -414,13 +399,8 @@ __device__ inline unsigned certify_pipelined(const RelaxArgs& a, int vo, long lo
         }
         if (pn >= end) break;
         p = pn;
-        pn = pnn;
-        f0 = fn0;
-        L = Ln;
 #pragma unroll
         for (int q = 0; q < C; ++q) e[q] = en[q];
-        fn0 = fnn0;
-        fn1 = fnn1;
     }
     return changed;
 }
@@ -645,10 +625,10 @@ void k_relax(RelaxArgs a) {
                 const bool cached = CACHE && be - cb <= gsz;   // one position per thread
                 if (cached && v != cv) {        // a vertex new to this thread
                     cx0 = a.xyz[v];
-                    const int f0 = a.fanrow[v];
-                    cL = a.fanrow[v + 1] - f0;
+                    load_fan6(a, v, ce);
+                    int f0;
+                    fan6_length(a, v, ce, cL, f0);
                     cv = cL <= kCache ? v : -1;
-                    if (cv >= 0) load_fan<kCache>(a, v, f0, cL, ce);
                 }
                 // every band vertex is evaluated here (at most one per thread):
                 // the neighbours' loads need not wait for a mark, and no marks
@@ -755,6 +735,7 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
 __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const MeshState* state, int B,
                                                     const int* vo_prefix, long long N, const int* perm,
                                                     const int* level, const int* fanrow, const int* fan,
+                                                    const int* fan6,
                                                     const float4* xyz, const float* dist, int* parent,
                                                     int* root) {
     for_tiles(vo_prefix, B, N, [&](long long p, int b) {
@@ -787,16 +768,28 @@ __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const 
                     bq = g == i1 ? q1 : q2;
                 }
             };
-            const int f0 = fanrow[p], L = fanrow[p + 1] - f0;
+            // the fan: its fixed-size record, or the row form for a longer fan
+            const int2* r6 = reinterpret_cast<const int2*>(fan6 + (size_t)kFan6 * p);
+            const int2 w0 = r6[0], w1 = r6[1], w2 = r6[2];
+            const int rec[kFan6] = {w0.x, w0.y, w1.x, w1.y, w2.x, w2.y};
+            const bool longf = (rec[0] & kFanStart) && (rec[0] & kFan6Pad);
+            int L = 0, f0 = 0;
+            if (longf) {
+                f0 = fanrow[p];
+                L = fanrow[p + 1] - f0;
+            } else if (rec[0] & kFanStart) {
+                L = 1;
+                for (int q = 1; q < kFan6; ++q) L += (rec[q] & kFan6Pad) ? 0 : 1;
+            }
             int first = -1, prev = -1;
             for (int q = 0; q < L; ++q) {
-                const int e = fan[f0 + q];
+                const int e = longf ? fan[f0 + q] : rec[q];
                 const int id = e & kFanId;
                 if (q == 0) first = id;
                 else if (!(e & kFanStart)) tri(prev, id);
                 prev = id;
             }
-            if (L > 1 && (fan[f0] & kFanClosed)) tri(prev, first);
+            if (L > 1 && (rec[0] & kFanClosed)) tri(prev, first);
         }
         parent[p] = bq;
         root[p] = bq;
@@ -915,7 +908,7 @@ hipError_t launch_run(const Work& w, const RunParams& p, bool labels, bool cache
     hipLaunchKernelGGL(k_source_index, dim3(tile_grid(p.Stot)), dim3(kBlock), 0, st, w.mesh, p.B, w.so, p.Stot,
                        p.S, w.iperm, srcidx);
     hipLaunchKernelGGL(k_parents, dim3(gN), dim3(kBlock), 0, st, w.mesh, w.state, p.B, w.vo, p.N, w.perm,
-                       w.level, w.fanrow, w.fan, w.xyz, w.dist, w.cursor, root);
+                       w.level, w.fanrow, w.fan, w.fan6, w.xyz, w.dist, w.cursor, root);
     for (int r = 0; r < p.jump_rounds; ++r)
         hipLaunchKernelGGL(k_jump, dim3(gN), dim3(kBlock), 0, st, p.N, root);
     hipLaunchKernelGGL(k_label_out, dim3(gN), dim3(kBlock), 0, st, w.mesh, p.B, w.vo, p.N, w.perm, root, srcidx,
