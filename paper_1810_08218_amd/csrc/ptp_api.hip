@@ -490,8 +490,8 @@ struct Solver {
         p.workgroups = std::min(max_run, 4 * cus);
         p.small_limit = 32768;
         p.large_limit = 524288;
-        p.medium_group = 16;
-        p.large_group = 32;
+        p.medium_group = 8;
+        p.large_group = 24;
         p.xcd_pack = 1;
         return p;
     }

@@ -857,25 +857,49 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
             int t0, t1 = 0;
             const int p0 = block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v0), &t0);
             const int p1 = cnt > kLdsBlock ? block_exclusive_scan_n<kLdsBlock, int, true>(__popc(v1), &t1) : 0;
-            if (tid < cnt) {
-                wpre[tid] = p0;
-                wv[tid] = v0;
-            }
-            if (tid + kLdsBlock < cnt) {
-                wpre[tid + kLdsBlock] = t0 + p1;
-                wv[tid + kLdsBlock] = v1;
-            }
             const int tv = t0 + t1;
-            if (tid == 0) wpre[cnt] = tv;
+            // a round of at most 2 kBigWl + 1 vertices: each staged word's
+            // thread writes its vertices into a list in rank order (over wpre
+            // and wv, which this form does not use); larger rounds find each
+            // vertex by a binary search over the words' ranks
+            const bool listed = tv <= 2 * kBigWl + 1;
+            int* ul = wpre;
+            if (listed) {
+                if (tid < cnt) {
+                    const int wb = wl[tid] * 32;
+                    int k = p0;
+                    for (unsigned m = v0; m; m &= m - 1) ul[k++] = wb + __ffs(m) - 1;
+                }
+                if (tid + kLdsBlock < cnt) {
+                    const int wb = wl[tid + kLdsBlock] * 32;
+                    int k = t0 + p1;
+                    for (unsigned m = v1; m; m &= m - 1) ul[k++] = wb + __ffs(m) - 1;
+                }
+            } else {
+                if (tid < cnt) {
+                    wpre[tid] = p0;
+                    wv[tid] = v0;
+                }
+                if (tid + kLdsBlock < cnt) {
+                    wpre[tid + kLdsBlock] = t0 + p1;
+                    wv[tid + kLdsBlock] = v1;
+                }
+                if (tid == 0) wpre[cnt] = tv;
+            }
             lds_barrier();
             for (int t = tid; t < tv; t += kLdsBlock) {
-                int lo = 0, hi = cnt;               // wpre[lo] <= t < wpre[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (wpre[mid] <= t) lo = mid;
-                    else hi = mid;
+                int u;
+                if (listed) {
+                    u = ul[t];
+                } else {
+                    int lo = 0, hi = cnt;           // wpre[lo] <= t < wpre[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (wpre[mid] <= t) lo = mid;
+                        else hi = mid;
+                    }
+                    u = wl[lo] * 32 + kth_bit(wv[lo], t - wpre[lo]);
                 }
-                const int u = wl[lo] * 32 + kth_bit(wv[lo], t - wpre[lo]);
                 const int pos = base + total + t;
                 a.perm[vo + pos] = vo + u;
                 a.iperm[vo + u] = vo + pos;
