@@ -1144,17 +1144,20 @@ __device__ inline int build_fan(Get wd, int c, Emit emit) {
     return len;
 }
 
-// Fans by vertex id.  A vertex's wedges (staged in LDS, one column per
-// thread, when there are at most kFanChainMax) are chained into fanO at
+// Fans by vertex id.  A vertex's wedges (loaded together and staged in LDS,
+// one column per thread, when there are at most kFanStage; 24 KB of LDS per
+// workgroup leave room for six workgroups per CU) are chained into fanO at
 // twice the vertex's incidence offset (a fan has at most two entries per
 // triangle), the length goes to fanlen, and the BFS neighbour row to ellO:
 // the fan's ids (each neighbour named once per chain) padded with -1, or
 // kEllMore in the last entry when the fan has more than kEll entries (the
 // BFS then expands the vertex from its wedges).
+constexpr int kFanStage = 8;
+
 __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const int2* wedgeO, long long N,
                                                        int* fanO, int* fanlen, int* ellO, const int* ctrl) {
     if (gated(ctrl)) return;
-    __shared__ int2 wd_s[kFanChainMax * kBlock];
+    __shared__ int2 wd_s[kFanStage * kBlock];
     __shared__ int row_s[kEll * kBlock];       // the first kEll fan entries, for the BFS row
     const int tid = threadIdx.x;
     const long long gsz = (long long)gridDim.x * kBlock;
@@ -1178,8 +1181,13 @@ __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const in
             if (q < kEll) row_s[q * kBlock + tid] = x;
         };
         int len;
-        if (c <= kFanChainMax) {
-            for (int q = 0; q < c; ++q) wd_s[q * kBlock + tid] = wedgeO[r0 + q];
+        if (c <= kFanStage) {
+            int2 w[kFanStage];
+#pragma unroll
+            for (int q = 0; q < kFanStage; ++q) w[q] = q < c ? wedgeO[r0 + q] : make_int2(0, 0);
+#pragma unroll
+            for (int q = 0; q < kFanStage; ++q)
+                if (q < c) wd_s[q * kBlock + tid] = w[q];
             len = build_fan([&](int q) { return wd_s[q * kBlock + tid]; }, c, emit);
         } else {
             len = build_fan([&](int q) { return wedgeO[r0 + q]; }, c, emit);
