@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(const float* __restrict__ V
 // instead of one per corner (a vertex appears in about six corners, mostly of
 // nearby faces).  Tiles whose id range exceeds kAgg fall back to per-corner
 // global atomics.
-constexpr int kAgg = 8192;
+constexpr int kAgg = 4096;
 
 struct TileCorners {
     int vid[kTileItems];   // global vertex id of each of this thread's corners, -1 past the end
