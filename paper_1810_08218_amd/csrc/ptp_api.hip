@@ -279,7 +279,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(float4) * N,                    // feat
         sizeof(unsigned long long) * 2 * B,    // edge_acc (sums, maxima)
         sizeof(int) * B,                       // lds_mesh
-        sizeof(int) * (N + 1),                 // fanrow
+        sizeof(int2) * N,                      // fanrow
         sizeof(int) * (2 * F3 + 1),            // fan
         sizeof(int) * kEll * N,                // ellO
         sizeof(WgInfo) * G,                    // wg_run64
@@ -287,6 +287,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(double) * (size_t)z.S * (kCvtChunks * 6 + 4),   // cvt partial sums, centroids
         sizeof(int) * N,                       // mark
         sizeof(int) * kFan6 * N,               // fan6
+        sizeof(int) * (kRqWords + 9 * B),       // rq
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {
@@ -330,7 +331,7 @@ Work carve(void* base, const Layout& L) {
     w.feat = reinterpret_cast<float4*>(b + L.off[27]);
     w.edge_acc = reinterpret_cast<unsigned long long*>(b + L.off[28]);
     w.lds_mesh = reinterpret_cast<int*>(b + L.off[29]);
-    w.fanrow = reinterpret_cast<int*>(b + L.off[30]);
+    w.fanrow = reinterpret_cast<int2*>(b + L.off[30]);
     w.fan = reinterpret_cast<int*>(b + L.off[31]);
     w.ellO = reinterpret_cast<int*>(b + L.off[32]);
     w.wg_run64 = reinterpret_cast<WgInfo*>(b + L.off[33]);
@@ -338,6 +339,7 @@ Work carve(void* base, const Layout& L) {
     w.cvt = reinterpret_cast<double*>(b + L.off[35]);
     w.mark = reinterpret_cast<int*>(b + L.off[36]);
     w.fan6 = reinterpret_cast<int*>(b + L.off[37]);
+    w.rq = reinterpret_cast<int*>(b + L.off[38]);
     return w;
 }
 

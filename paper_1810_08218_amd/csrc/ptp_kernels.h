@@ -73,17 +73,28 @@ struct Work {
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
-    int* fanrow;        // [N + 1] row form over positions of the fans longer than kFan6 (others empty)
-    int* fan;           // [6F]    those fans' entries, positions and flags
+    int2* fanrow;       // [N]     (start in fan, length) of each position whose fan is longer than kFan6
+    int* fan;           // [6F]    those fans' entries, positions and flags, at twice the vertex's incidence offset
     int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
     WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation
     int* glist_run64;   // [gmax + 8 + B]
     double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
     int* mark;          // [N]     per position: the last iteration + 1 in which a neighbour changed
     int* fan6;          // [6N]    per position its first kFan6 fan entries in a fixed-size record
+    int* rq;            // [kRqWords + 9B] queues of the reorder inside the one-workgroup BFS
 };
 
-constexpr int kLayoutParts = 38;
+constexpr int kLayoutParts = 39;
+
+// The reorder of a batch inside its one-workgroup BFS launch.  A workgroup
+// that has finished its mesh's BFS publishes the mesh in the queue of the XCD
+// it runs on, then reorders chunks of the meshes published on that XCD (the
+// positions were written through that XCD's L2).  rq: kRqWords control words
+// (RQ_STARTED, RQ_FINISHED, RQ_SLOTS + x: slots taken in the queue of XCD x),
+// then eight queues of B slots (mesh + 1; 0 until published), then per mesh
+// the number of its chunks claimed.  Zeroed before the launch.
+constexpr int kRqWords = 16;
+enum RqWord : int { RQ_STARTED = 0, RQ_FINISHED = 1, RQ_SLOTS = 8 };
 
 // Lloyd step: every cell's sums are split over this many chunks of the
 // faces (or vertices), each reduced in a fixed order.

@@ -551,6 +551,21 @@ constexpr int kLdsBlock = 1024;
 constexpr int kLdsList = 4096;
 constexpr int kExpand = 8;     // wedges loaded together per expanded vertex
 
+// Inputs and outputs of the reorder into topleset order.
+struct ReorderArgs {
+    const float* V;
+    const MeshDesc* mesh;
+    const int* vo;
+    const int* iperm;
+    const int* rowO;
+    const int* fanO;
+    const int* fanlen;
+    int2* fanrow;
+    float4* xyz;
+    int* fan;
+    int* fan6;
+};
+
 struct BfsLdsArgs {
     const int* lmesh;      // mesh ids, one per workgroup: the n_big large ones first
     int n_big;
@@ -566,9 +581,14 @@ struct BfsLdsArgs {
     int* iperm;
     int* offsets;
     int* ctrl;
+    int fuse;              // reorder inside this launch (bfs_reorder_tail)
+    int n_one;             // workgroups of the launch
+    int B;                 // meshes of the batch
+    int* rq;               // queues of the reorder
+    ReorderArgs ro;
 };
 
-__device__ void bfs_lds(const BfsLdsArgs& a) {
+__device__ bool bfs_lds(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
     const int b = a.lmesh[blockIdx.x];
@@ -594,7 +614,7 @@ __device__ void bfs_lds(const BfsLdsArgs& a) {
             atomicOr(&a.state[b].status, ST_DUP_SOURCE);
             atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
         }
-        return;
+        return false;
     }
     const int q = (W + kLdsBlock - 1) / kLdsBlock;
     const int my0 = min(tid * q, W), my1 = min(my0 + q, W);
@@ -713,6 +733,7 @@ __device__ void bfs_lds(const BfsLdsArgs& a) {
         a.state[b].rho = rho;
         a.state[b].reach = reach;
     }
+    return true;
 }
 
 // ---- BFS of one larger mesh in one workgroup -----------------------------
@@ -777,7 +798,7 @@ __device__ inline void bfs_big_expand(const BfsLdsArgs& a, int vo, int u, int4 r
     }
 }
 
-__device__ void bfs_big(const BfsLdsArgs& a) {
+__device__ bool bfs_big(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
     const int b = a.lmesh[blockIdx.x];
@@ -811,7 +832,7 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
             atomicOr(&a.state[b].status, ST_DUP_SOURCE);
             atomicOr(a.ctrl + C_STATUS, ST_DUP_SOURCE);
         }
-        return;
+        return false;
     }
     const int sq = (SW + kLdsBlock - 1) / kLdsBlock;
     const int s0 = min(tid * sq, SW), s1 = min(s0 + sq, SW);
@@ -970,36 +991,16 @@ __device__ void bfs_big(const BfsLdsArgs& a) {
         a.state[b].rho = rho;
         a.state[b].reach = reach;
     }
-}
-
-// One workgroup per mesh: the larger meshes (first n_big blocks) with the
-// frontier in global memory, the others with every bitmap in LDS.
-__global__ __launch_bounds__(kLdsBlock) void k_bfs_one(BfsLdsArgs a) {
-    if (gated(a.ctrl)) return;
-    if ((int)blockIdx.x < a.n_big) bfs_big(a);
-    else bfs_lds(a);
-}
-
-// Row-form length of each position, into fanrow[p + 1]: its fan's length if
-// the fan is longer than a fixed-size record holds, else 0 (the fans
-// themselves are built once per prepare by vertex id, independent of the
-// sources).
-__global__ __launch_bounds__(kBlock) void k_fanrow_new(const int* perm, const int* fanlen, long long N,
-                                                       int* fanrow, const int* ctrl) {
-    if (gated(ctrl)) return;
-    const long long gsz = (long long)gridDim.x * kBlock;
-    for (long long p = blockIdx.x * (long long)kBlock + threadIdx.x; p < N; p += gsz) {
-        const int len = fanlen[perm[p]];
-        fanrow[p + 1] = len > kFan6 ? len : 0;      // the row form holds the longer fans only
-        if (p == 0) fanrow[0] = 0;
-    }
+    return true;
 }
 
 // Coordinates and fans in topleset order: the position of each vertex takes
 // its coordinates and a copy of its fan with every neighbour id turned into
 // that neighbour's position (flags kept): the first kFan6 entries in its
-// fixed-size record, the whole fan in the row form as well when it is longer.
-// The loop runs over vertex ids, so
+// fixed-size record, the whole fan in the row form as well when it is longer
+// (at twice the vertex's incidence offset, the room fanO gives it, so no scan
+// over the positions is needed; fanrow holds its start and length).
+// The loops run over vertex ids, so
 // the fans are read in storage order and the neighbours' positions are
 // looked up around the vertex's own id (meshes number neighbours closely);
 // only the writes scatter, one row per vertex.  A thread takes kReItems
@@ -1010,77 +1011,179 @@ constexpr int kReItems = 4;
 constexpr int kReFan = 8;
 static_assert(kReFan >= kFan6, "the fan records are filled from the entries in registers");
 
-__global__ __launch_bounds__(kBlock) void k_reorder(const float* __restrict__ V, const MeshDesc* mesh, int B,
-                                                    const int* vo, const int* __restrict__ iperm,
-                                                    const int* __restrict__ rowO, const int* __restrict__ fanO,
-                                                    const int* __restrict__ fanlen, const int* __restrict__ fanrow,
-                                                    long long N, float4* __restrict__ xyz, int* __restrict__ fan,
-                                                    int* __restrict__ fan6, const int* ctrl) {
+// The vertices v[i] (internal ids, -1 for none) of meshes bq[i].  kCoh: the
+// positions were written in the same launch and are read with coherent loads.
+template <bool kCoh>
+__device__ inline void reorder_items(const float* __restrict__ V, const MeshDesc* mesh, const int* vo,
+                                     const int* __restrict__ iperm, const int* __restrict__ rowO,
+                                     const int* __restrict__ fanO, const int* __restrict__ fanlen,
+                                     int2* __restrict__ fanrow, float4* __restrict__ xyz, int* __restrict__ fan,
+                                     int* __restrict__ fan6, const long long* v, const int* bq) {
+    auto pos = [&](long long x) { return kCoh ? ld_c(iperm + x) : iperm[x]; };
+    int p[kReItems], r0[kReItems], len[kReItems], e[kReItems][kReFan];
+    float c[kReItems][3];
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+        p[i] = 0;
+        r0[i] = 0;
+        len[i] = 0;
+        c[i][0] = c[i][1] = c[i][2] = 0.f;
+        if (v[i] >= 0) {
+            const int b = bq[i];
+            const float* cp = V + 3 * ((long long)mesh[b].v_in + (v[i] - vo[b]));
+            p[i] = pos(v[i]);
+            c[i][0] = cp[0];
+            c[i][1] = cp[1];
+            c[i][2] = cp[2];
+            r0[i] = rowO[v[i]];
+            len[i] = fanlen[v[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+#pragma unroll
+        for (int q = 0; q < kReFan; ++q) e[i][q] = q < len[i] ? fanO[2 * (long long)r0[i] + q] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i)
+#pragma unroll
+        for (int q = 0; q < kReFan; ++q)
+            if (q < len[i]) e[i][q] = pos(e[i][q] & kFanId) | (e[i][q] & ~kFanId);
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+        if (v[i] < 0) continue;
+        xyz[p[i]] = make_float4(c[i][0], c[i][1], c[i][2], 0.f);
+        const int fr = 2 * r0[i];     // the row's start: twice the incidence offset, as in fanO
+        if (len[i] > kFan6) {         // a longer fan: also in the row form
+            fanrow[p[i]] = make_int2(fr, len[i]);
+#pragma unroll
+            for (int q = 0; q < kReFan; ++q)
+                if (q < len[i]) fan[fr + q] = e[i][q];
+        }
+        // the fixed-size record of the first kFan6 entries
+        int rec[kFan6];
+        const int first = len[i] > 0 ? e[i][0] : p[i];
+#pragma unroll
+        for (int q = 0; q < kFan6; ++q)
+            rec[q] = q < len[i] ? e[i][q] : (q == 0 ? p[i] : (first & kFanId) | kFan6Pad);
+        if (len[i] > kFan6) rec[0] |= kFan6Pad;
+        int2* r6 = reinterpret_cast<int2*>(fan6 + (size_t)kFan6 * p[i]);
+        r6[0] = make_int2(rec[0], rec[1]);
+        r6[1] = make_int2(rec[2], rec[3]);
+        r6[2] = make_int2(rec[4], rec[5]);
+        for (int q = kReFan; q < len[i]; ++q) {
+            const int x = fanO[2 * (long long)r0[i] + q];
+            fan[fr + q] = pos(x & kFanId) | (x & ~kFanId);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reorder(ReorderArgs r, int B, long long N, const int* ctrl) {
     if (gated(ctrl)) return;
     for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
         int bq[kTileItems];
-        tile_meshes(vo, B, N, t, bq);
+        tile_meshes(r.vo, B, N, t, bq);
 #pragma unroll
         for (int h = 0; h < kTileItems; h += kReItems) {
-            int p[kReItems], r0[kReItems], len[kReItems], fr[kReItems], e[kReItems][kReFan];
-            float c[kReItems][3];
+            long long v[kReItems];
 #pragma unroll
             for (int i = 0; i < kReItems; ++i) {
-                const long long v = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
-                p[i] = 0;
-                r0[i] = 0;
-                len[i] = 0;
-                c[i][0] = c[i][1] = c[i][2] = 0.f;
-                if (v < N) {
-                    const int b = bq[h + i];
-                    const float* cp = V + 3 * ((long long)mesh[b].v_in + (v - vo[b]));
-                    p[i] = iperm[v];
-                    c[i][0] = cp[0];
-                    c[i][1] = cp[1];
-                    c[i][2] = cp[2];
-                    r0[i] = rowO[v];
-                    len[i] = fanlen[v];
-                }
+                v[i] = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
+                if (v[i] >= N) v[i] = -1;
             }
-#pragma unroll
-            for (int i = 0; i < kReItems; ++i) {
-                fr[i] = len[i] > kFan6 ? fanrow[p[i]] : 0;
-#pragma unroll
-                for (int q = 0; q < kReFan; ++q) e[i][q] = q < len[i] ? fanO[2 * (long long)r0[i] + q] : 0;
-            }
-#pragma unroll
-            for (int i = 0; i < kReItems; ++i)
-#pragma unroll
-                for (int q = 0; q < kReFan; ++q)
-                    if (q < len[i]) e[i][q] = iperm[e[i][q] & kFanId] | (e[i][q] & ~kFanId);
-#pragma unroll
-            for (int i = 0; i < kReItems; ++i) {
-                const long long v = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
-                if (v >= N) continue;
-                xyz[p[i]] = make_float4(c[i][0], c[i][1], c[i][2], 0.f);
-                if (len[i] > kFan6) {     // a longer fan: also in the row form
-#pragma unroll
-                    for (int q = 0; q < kReFan; ++q)
-                        if (q < len[i]) fan[fr[i] + q] = e[i][q];
-                }
-                // the fixed-size record of the first kFan6 entries
-                int rec[kFan6];
-                const int first = len[i] > 0 ? e[i][0] : p[i];
-#pragma unroll
-                for (int q = 0; q < kFan6; ++q)
-                    rec[q] = q < len[i] ? e[i][q] : (q == 0 ? p[i] : (first & kFanId) | kFan6Pad);
-                if (len[i] > kFan6) rec[0] |= kFan6Pad;
-                int2* r6 = reinterpret_cast<int2*>(fan6 + (size_t)kFan6 * p[i]);
-                r6[0] = make_int2(rec[0], rec[1]);
-                r6[1] = make_int2(rec[2], rec[3]);
-                r6[2] = make_int2(rec[4], rec[5]);
-                for (int q = kReFan; q < len[i]; ++q) {
-                    const int x = fanO[2 * (long long)r0[i] + q];
-                    fan[fr[i] + q] = iperm[x & kFanId] | (x & ~kFanId);
-                }
-            }
+            reorder_items<false>(r.V, r.mesh, r.vo, r.iperm, r.rowO, r.fanO, r.fanlen, r.fanrow, r.xyz, r.fan,
+                                 r.fan6, v, bq + h);
         }
     }
+}
+
+// The reorder of a batch inside its one-workgroup BFS launch (see kRqWords).
+// The mesh's positions are in this XCD's L2 once every thread's stores have
+// completed; the mesh then goes into this XCD's queue (a coherent store,
+// completed before the workgroup counts itself finished).  Thread 0 claims
+// chunks of kReChunk vertices from the queue's meshes in turn; with none left
+// it waits, but only while some BFS is still running and every workgroup of
+// the launch has started (so a waiting workgroup never holds the place of one
+// that has yet to run), and leaves otherwise.  The positions are read with
+// coherent loads: another CU of this XCD wrote them.
+constexpr int kReChunk = kReItems * kLdsBlock;
+constexpr int kFuseMinMeshes = 256;     // one workgroup per CU of the device
+
+__device__ void bfs_reorder_tail(const BfsLdsArgs& a, bool ok) {
+    __shared__ int job[2];
+    const int tid = threadIdx.x;
+    const int x = (int)(xcc_id() & 7u);
+    int* slots = a.rq + kRqWords + x * a.B;
+    int* claimed = a.rq + kRqWords + 8 * a.B;
+    wait_memory();
+    __syncthreads();
+    if (tid == 0) {
+        if (ok) {
+            const int s = atomicAdd(a.rq + RQ_SLOTS + x, 1);
+            st_c(slots + s, a.lmesh[blockIdx.x] + 1);
+            wait_memory();
+        }
+        atomicAdd(a.rq + RQ_FINISHED, 1);
+    }
+    int cur = 0;    // thread 0: the next slot of the queue that may have chunks left
+    for (;;) {
+        if (tid == 0) {
+            int b = -1, c = 0;
+            const long long t0 = wall_clock64();
+            for (;;) {
+                const int fin = ld_c(a.rq + RQ_FINISHED);
+                const int taken = ld_c(a.rq + RQ_SLOTS + x);
+                while (cur < taken) {
+                    const int mb = ld_c(slots + cur);
+                    if (mb == 0) break;           // taken, not yet published
+                    const int nc = (a.mesh[mb - 1].n + kReChunk - 1) / kReChunk;
+                    const int k = atomicAdd(claimed + mb - 1, 1);
+                    if (k < nc) {
+                        b = mb - 1;
+                        c = k;
+                        break;
+                    }
+                    ++cur;
+                }
+                if (b >= 0) break;
+                // nothing to claim: leave when every BFS has finished (all
+                // published meshes are claimed) or when waiting is not safe
+                if (cur >= taken && (fin >= a.n_one || ld_c(a.rq + RQ_STARTED) < a.n_one)) break;
+                if (wall_clock64() - t0 > FlagBarrier::kTimeoutTicks) {     // cannot happen: fail, not hang
+                    __hip_atomic_fetch_or(a.ctrl + C_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(32);
+            }
+            job[0] = b;
+            job[1] = c;
+        }
+        __syncthreads();
+        const int b = job[0], c = job[1];
+        __syncthreads();
+        if (b < 0) return;
+        const long long v0 = a.mesh[b].v_off + (long long)c * kReChunk, v1 = a.mesh[b].v_off + a.mesh[b].n;
+        long long v[kReItems];
+        int bq[kReItems];
+#pragma unroll
+        for (int i = 0; i < kReItems; ++i) {
+            v[i] = v0 + (long long)i * kLdsBlock + tid;
+            if (v[i] >= v1) v[i] = -1;
+            bq[i] = b;
+        }
+        const ReorderArgs& r = a.ro;
+        reorder_items<true>(r.V, r.mesh, r.vo, r.iperm, r.rowO, r.fanO, r.fanlen, r.fanrow, r.xyz, r.fan, r.fan6,
+                            v, bq);
+    }
+}
+
+// One workgroup per mesh: the larger meshes (first n_big blocks) with the
+// frontier in global memory, the others with every bitmap in LDS.
+__global__ __launch_bounds__(kLdsBlock) void k_bfs_one(BfsLdsArgs a) {
+    if (gated(a.ctrl)) return;
+    if (a.fuse && threadIdx.x == 0) atomicAdd(a.rq + RQ_STARTED, 1);
+    const bool ok = (int)blockIdx.x < a.n_big ? bfs_big(a) : bfs_lds(a);
+    if (a.fuse) bfs_reorder_tail(a, ok);
 }
 
 // The chains of one vertex's wedges wd(0..c) (see kFanStart): a chain starts
@@ -1271,6 +1374,21 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
     a.cnt = w.cnt;
     a.ctrl = w.ctrl;
     a.bar = w.bar;
+    ReorderArgs ro;
+    ro.V = V;
+    ro.mesh = w.mesh;
+    ro.vo = w.vo;
+    ro.iperm = w.iperm;
+    ro.rowO = w.rowO;
+    ro.fanO = w.fanO;
+    ro.fanlen = w.fanlen;
+    ro.fanrow = w.fanrow;
+    ro.xyz = w.xyz;
+    ro.fan = w.fan;
+    ro.fan6 = w.fan6;
+    // the reorder runs inside the one-workgroup BFS when every mesh takes it
+    // and the finished workgroups can cover the device
+    const bool fuse = g_prep == 0 && n_one >= kFuseMinMeshes;
     if (n_one > 0) {
         BfsLdsArgs l;
         l.lmesh = w.lds_mesh;
@@ -1287,6 +1405,14 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
         l.iperm = w.iperm;
         l.offsets = w.offsets;
         l.ctrl = w.ctrl;
+        l.fuse = fuse ? 1 : 0;
+        l.n_one = n_one;
+        l.B = z.B;
+        l.rq = w.rq;
+        l.ro = ro;
+        if (fuse)
+            hipLaunchKernelGGL(k_fill, dim3(grid_for(kRqWords + 9ll * z.B)), dim3(kBlock), 0, st, w.rq,
+                               kRqWords + 9ll * z.B, 0);
         hipLaunchKernelGGL(k_bfs_one, dim3(n_one), dim3(kLdsBlock), bfs_one_bytes(z.lds_words, z.big_words), st,
                            l);
         e = hipGetLastError();
@@ -1299,12 +1425,7 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
                                        args, 0, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fanrow_new, dim3(grid_for(N)), dim3(kBlock), 0, st, w.perm, w.fanlen, N, w.fanrow,
-                       w.ctrl);
-    e = scan_inplace(w.fanrow + 1, N, w.scan_tmp, w.ctrl, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, V, w.mesh, z.B, w.vo, w.iperm,
-                       w.rowO, w.fanO, w.fanlen, w.fanrow, N, w.xyz, w.fan, w.fan6, w.ctrl);
+    if (!fuse) hipLaunchKernelGGL(k_reorder, dim3(grid_for(N)), dim3(kBlock), 0, st, ro, z.B, N, w.ctrl);
     return hipGetLastError();
 }
 

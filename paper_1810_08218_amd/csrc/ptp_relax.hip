@@ -107,7 +107,7 @@ struct RelaxArgs {
     const int* perm;
     const int* iperm;
     const int* offsets;
-    const int* fanrow;
+    const int2* fanrow;    // (start, length) of the longer fans' rows in fan
     const int* fan;
     const float4* xyz;
     float* dist;           // [2N]
@@ -225,8 +225,9 @@ __device__ inline void fan6_length(const RelaxArgs& a, int v, const int* e, int&
     if (!(e[0] & kFanStart)) {
         L = 0;
     } else if (e[0] & kFan6Pad) {
-        f0 = a.fanrow[v];
-        L = a.fanrow[v + 1] - f0;
+        const int2 r = a.fanrow[v];
+        f0 = r.x;
+        L = r.y;
     } else {
         L = 1;
 #pragma unroll
@@ -734,7 +735,7 @@ __global__ void k_run_reset(int* ctrl, MeshState* state, int B) {
 // `root` into roots.
 __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const MeshState* state, int B,
                                                     const int* vo_prefix, long long N, const int* perm,
-                                                    const int* level, const int* fanrow, const int* fan,
+                                                    const int* level, const int2* fanrow, const int* fan,
                                                     const int* fan6,
                                                     const float4* xyz, const float* dist, int* parent,
                                                     int* root) {
@@ -775,8 +776,9 @@ __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const 
             const bool longf = (rec[0] & kFanStart) && (rec[0] & kFan6Pad);
             int L = 0, f0 = 0;
             if (longf) {
-                f0 = fanrow[p];
-                L = fanrow[p + 1] - f0;
+                const int2 r = fanrow[p];
+                f0 = r.x;
+                L = r.y;
             } else if (rec[0] & kFanStart) {
                 L = 1;
                 for (int q = 1; q < kFan6; ++q) L += (rec[q] & kFan6Pad) ? 0 : 1;
