@@ -73,7 +73,7 @@ struct Work {
     float4* feat;       // [N]     warm-start network inputs and scale per position
     unsigned long long* edge_acc;   // [2B] fixed-point edge-length sums, then maxima
     int* lds_mesh;      // [B]     meshes of the one-workgroup BFS
-    int2* fanrow;       // [N]     (start in fan, length) of each position whose fan is longer than kFan6
+    int2* fanrow;       // [N]     (start, end) in fan of each position whose fan is longer than kFan6
     int* fan;           // [6F]    those fans' entries, positions and flags, at twice the vertex's incidence offset
     int* ellO;          // [kEll * N] distinct neighbours by global vertex id (BFS)
     WgInfo* wg_run64;   // [gmax]  group layout of the double-precision relaxation

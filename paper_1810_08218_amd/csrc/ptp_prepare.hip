@@ -999,7 +999,7 @@ __device__ bool bfs_big(const BfsLdsArgs& a) {
 // that neighbour's position (flags kept): the first kFan6 entries in its
 // fixed-size record, the whole fan in the row form as well when it is longer
 // (at twice the vertex's incidence offset, the room fanO gives it, so no scan
-// over the positions is needed; fanrow holds its start and length).
+// over the positions is needed; fanrow holds its start and end).
 // The loops run over vertex ids, so
 // the fans are read in storage order and the neighbours' positions are
 // looked up around the vertex's own id (meshes number neighbours closely);
@@ -1055,7 +1055,7 @@ __device__ inline void reorder_items(const float* __restrict__ V, const MeshDesc
         xyz[p[i]] = make_float4(c[i][0], c[i][1], c[i][2], 0.f);
         const int fr = 2 * r0[i];     // the row's start: twice the incidence offset, as in fanO
         if (len[i] > kFan6) {         // a longer fan: also in the row form
-            fanrow[p[i]] = make_int2(fr, len[i]);
+            fanrow[p[i]] = make_int2(fr, fr + len[i]);
 #pragma unroll
             for (int q = 0; q < kReFan; ++q)
                 if (q < len[i]) fan[fr + q] = e[i][q];

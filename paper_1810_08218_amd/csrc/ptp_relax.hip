@@ -107,7 +107,7 @@ struct RelaxArgs {
     const int* perm;
     const int* iperm;
     const int* offsets;
-    const int2* fanrow;    // (start, length) of the longer fans' rows in fan
+    const int2* fanrow;    // (start, end) of the longer fans' rows in fan
     const int* fan;
     const float4* xyz;
     float* dist;           // [2N]
@@ -227,7 +227,7 @@ __device__ inline void fan6_length(const RelaxArgs& a, int v, const int* e, int&
     } else if (e[0] & kFan6Pad) {
         const int2 r = a.fanrow[v];
         f0 = r.x;
-        L = r.y;
+        L = r.y - r.x;
     } else {
         L = 1;
 #pragma unroll
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_parents(const MeshDesc* mesh, const 
             if (longf) {
                 const int2 r = fanrow[p];
                 f0 = r.x;
-                L = r.y;
+                L = r.y - r.x;
             } else if (rec[0] & kFanStart) {
                 L = 1;
                 for (int q = 1; q < kFan6; ++q) L += (rec[q] & kFan6Pad) ? 0 : 1;
