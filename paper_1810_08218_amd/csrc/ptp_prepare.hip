@@ -34,8 +34,9 @@ __global__ __launch_bounds__(kBlock) void k_zero_lines(unsigned* p, long long le
         p[x] = 0u;
 }
 
-// Face ids must lie in their mesh, coordinates be finite, sources lie in
-// their mesh.  Bad meshes are flagged in their state and in the batch word.
+// Coordinates must be finite, sources lie in their mesh (face ids are
+// checked by k_count).  Bad meshes are flagged in their state and in the
+// batch word.
 // Loops run over the internal (concatenated) index spaces and read the
 // caller's rows.
 __global__ __launch_bounds__(kBlock) void k_validate(const float* __restrict__ V, const int* __restrict__ F,
@@ -43,31 +44,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(const float* __restrict__ V
                                                      const int* vo, const int* fo3, const int* so, long long N,
                                                      long long F3, long long Stot, MeshState* state, int* ctrl) {
     int bad = 0;
-    // face corners and coordinates: every element of a tile loaded, then checked
-    for (long long t = blockIdx.x; t < (F3 + kTile - 1) / kTile; t += gridDim.x) {
-        int bq[kTileItems], v[kTileItems], nq[kTileItems];
-        long long at[kTileItems];
-        tile_meshes(fo3, B, F3, t, bq);
-#pragma unroll
-        for (int q = 0; q < kTileItems; ++q) {
-            at[q] = 3 * (long long)mesh[bq[q]].f_in + (t * kTile + (long long)q * kBlock + threadIdx.x - fo3[bq[q]]);
-            nq[q] = mesh[bq[q]].n;
-        }
-        if (t * kTile + kTile <= F3) {
-#pragma unroll
-            for (int q = 0; q < kTileItems; ++q) v[q] = F[at[q]];
-        } else {
-#pragma unroll
-            for (int q = 0; q < kTileItems; ++q)
-                v[q] = t * kTile + (long long)q * kBlock + threadIdx.x < F3 ? F[at[q]] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < kTileItems; ++q)
-            if (t * kTile + (long long)q * kBlock + threadIdx.x < F3 && (v[q] < 0 || v[q] >= nq[q])) {
-                atomicOr(&state[bq[q]].status, ST_BAD_FACE);
-                bad |= ST_BAD_FACE;
-            }
-    }
+    // coordinates: every element of a tile loaded, then checked (the face
+    // corners are checked by k_count, which reads them anyway)
     for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
         int bq[kTileItems];
         long long at[kTileItems];
@@ -108,8 +86,12 @@ __global__ __launch_bounds__(kBlock) void k_validate(const float* __restrict__ V
 // global atomics.
 constexpr int kAgg = 4096;
 
+constexpr int kBadCorner = -2;
+
 struct TileCorners {
-    int vid[kTileItems];   // global vertex id of each of this thread's corners, -1 past the end
+    int vid[kTileItems];   // global vertex id of each of this thread's corners, -1 past the end,
+                           // kBadCorner for an id outside the corner's mesh
+    int b[kTileItems];     // the corner's mesh
     long long t3[kTileItems];   // caller row of the corner's face
     int c[kTileItems];     // corner inside the face
     int vo[kTileItems];    // vertex offset of the corner's mesh
@@ -118,10 +100,13 @@ struct TileCorners {
 // Loads this thread's corners of tile t and returns the tile's id range
 // [*lo, *hi] (block-wide; lo > hi when the tile is empty).  The corners'
 // meshes are found first, then every corner is loaded before any is used.
+// kCheck: ids outside the corner's mesh become kBadCorner (else they are
+// known to be valid).
+template <bool kCheck>
 __device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int B, const int* fo3, long long F3,
                                          long long t, TileCorners& tc, int* lo, int* hi, int* red) {
     const long long base = t * kTile;
-    int bq[kTileItems];
+    int bq[kTileItems], nq[kTileItems];
     tile_meshes(fo3, B, F3, t, bq);
 #pragma unroll
     for (int q = 0; q < kTileItems; ++q) {
@@ -131,14 +116,21 @@ __device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int
         tc.t3[q] = 3 * (long long)mesh[b].f_in + (lc - lc % 3);
         tc.c[q] = (int)(lc % 3);
         tc.vo[q] = mesh[b].v_off;
+        tc.b[q] = b;
+        nq[q] = kCheck ? mesh[b].n : 0x7fffffff;
     }
+    int f[kTileItems];
     if (base + kTile <= F3) {       // a full tile: no guards, so the loads issue together
 #pragma unroll
-        for (int q = 0; q < kTileItems; ++q) tc.vid[q] = tc.vo[q] + F[tc.t3[q] + tc.c[q]];
+        for (int q = 0; q < kTileItems; ++q) f[q] = F[tc.t3[q] + tc.c[q]];
     } else {
 #pragma unroll
-        for (int q = 0; q < kTileItems; ++q)
-            tc.vid[q] = base + (long long)q * kBlock + threadIdx.x < F3 ? tc.vo[q] + F[tc.t3[q] + tc.c[q]] : -1;
+        for (int q = 0; q < kTileItems; ++q) f[q] = base + (long long)q * kBlock + threadIdx.x < F3 ? F[tc.t3[q] + tc.c[q]] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const bool past = base + (long long)q * kBlock + threadIdx.x >= F3;
+        tc.vid[q] = past ? -1 : (!kCheck || (f[q] >= 0 && f[q] < nq[q])) ? tc.vo[q] + f[q] : kBadCorner;
     }
     int mn = 0x7fffffff, mx = -1;
 #pragma unroll
@@ -164,18 +156,27 @@ __device__ inline void load_tile_corners(const int* F, const MeshDesc* mesh, int
     __syncthreads();        // red is rewritten by the next tile
 }
 
-// degree of each internal vertex, counted into row[v + 1]
+// Degree of each internal vertex, counted into row[v + 1]; a face id outside
+// its mesh flags the mesh (ST_BAD_FACE) and is not counted (the passes after
+// this one are gated on the flag).
 __global__ __launch_bounds__(kBlock) void k_count(const int* F, const MeshDesc* mesh, int B,
                                                   const int* fo3, long long F3, int* row,
-                                                  const int* ctrl) {
+                                                  MeshState* state, int* ctrl) {
     if (gated(ctrl)) return;
     __shared__ int cnt[kAgg];
     __shared__ int red[8];
     const long long ntiles = (F3 + kTile - 1) / kTile;
+    int bad = 0;
     for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
         TileCorners tc;
         int lo, hi;
-        load_tile_corners(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
+        load_tile_corners<true>(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
+#pragma unroll
+        for (int q = 0; q < kTileItems; ++q)
+            if (tc.vid[q] == kBadCorner) {
+                atomicOr(&state[tc.b[q]].status, ST_BAD_FACE);
+                bad = ST_BAD_FACE;
+            }
         if (hi - lo >= kAgg) {
 #pragma unroll
             for (int q = 0; q < kTileItems; ++q)
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const int* F, const MeshDesc* 
             if (cnt[i]) atomicAdd(row + lo + i + 1, cnt[i]);
         __syncthreads();
     }
+    if (bad) atomicOr(ctrl + C_STATUS, bad);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const MeshDesc* mesh, int B,
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_incidence(const int* F, const M
     for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
         TileCorners tc;
         int lo, hi;
-        load_tile_corners(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
+        load_tile_corners<false>(F, mesh, B, fo3, F3, t, tc, &lo, &hi, red);
         int slot[kTileItems];
         const bool agg = hi - lo < kAgg;
         if (agg) {
@@ -1333,10 +1335,10 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kBlock), 0, st, w.ctrl, (long long)C_WORDS, 0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(N + 1)), dim3(kBlock), 0, st, w.rowO, N + 1, 0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, w.cursor, N, 0);
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(F3 > N ? F3 : N)), dim3(kBlock), 0, st, V, F, S,
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(N)), dim3(kBlock), 0, st, V, F, S,
                        w.mesh, z.B, w.vo, w.fo3, w.so, N, F3, z.S, w.state, w.ctrl);
     hipLaunchKernelGGL(k_count, dim3(tile_grid(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B, w.fo3, F3,
-                       w.rowO, w.ctrl);
+                       w.rowO, w.state, w.ctrl);
     hipError_t e = scan_inplace(w.rowO + 1, N, w.scan_tmp, w.ctrl, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_incidence, dim3(tile_grid(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
