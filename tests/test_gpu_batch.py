@@ -192,6 +192,90 @@ def test_invalid_mesh_in_batch(cuda):
     assert status[2] == P.PTP_EINVAL and sum(s != P.PTP_OK for s in status) == 1
 
 
+def _many_small_meshes(count=300):
+    """More meshes than the device has CUs, so the reorder into topleset
+    order runs inside the one-workgroup BFS launch: the small batch, the
+    irregular-fan mesh (fans longer than the fixed-size record, a non-manifold
+    vertex, a duplicated face), a mesh with a part no source reaches, and
+    small jittered grids and tori with 1-3 sources up to `count`."""
+    from test_gpu_parity import _irregular_fans_mesh
+    meshes, share = small_batch()
+    meshes.append(_irregular_fans_mesh())
+    share.append(None)
+    g = I.flat_grid(6)
+    V = np.concatenate([g.V, np.array([[5, 5, 0], [6, 5, 0], [5, 6, 0]], np.float32)])
+    F = np.concatenate([g.F, np.array([[36, 37, 38]], np.int32)])
+    meshes.append(I.Mesh(V, F, np.array([0], np.int32), name="grid6_island"))
+    share.append(None)
+    rng = np.random.default_rng(91)
+    while len(meshes) < count:
+        if rng.random() < 0.7:
+            s = int(rng.integers(5, 41))
+            V, F = I.jittered_grid(s, rng)
+            name = f"jgrid{s}"
+        else:
+            k = int(rng.integers(3, 6))
+            V, F = I.torus(2 ** k, 2 ** (k - 1), 0.3)
+            name = f"torus{k}"
+        S = rng.choice(V.shape[0], int(rng.integers(1, 4)), replace=False)
+        meshes.append(_mesh(V, F, S, name))
+        share.append(None)
+    return meshes, share
+
+
+def test_reorder_inside_bfs_launch(cuda):
+    """A batch of 300 meshes (reorder inside the BFS launch) equals the
+    single-mesh plans bit for bit, distances, labels, K, rho and U; the
+    unreachable vertices stay at infinity with label -1."""
+    meshes, share = _many_small_meshes()
+    b, dist, lab, descs, rc, stats, status = run_batch(meshes, share, 1e-4)
+    say(f"[batch] {len(meshes)} meshes rc={rc}")
+    assert rc == P.PTP_OK and all(s == P.PTP_OK for s in status)
+    d = dist.cpu().numpy()
+    l = lab.cpu().numpy()
+    for m, (a, z), st in zip(meshes, _slices(descs), stats):
+        g = gpu_run(m, 1e-4, labels=True, want_order=False)
+        assert np.array_equal(d[a:z], g.dist), m.name
+        assert np.array_equal(l[a:z], g.label), m.name
+        assert (st["iterations"], st["n_toplesets"], st["vertex_updates"]) == \
+               (g.iterations, g.rho, g.updates), m.name
+    island = [i for i, m in enumerate(meshes) if m.name == "grid6_island"][0]
+    a, z = _slices(descs)[island]
+    assert np.isinf(d[a:z][36:]).all() and (l[a:z][36:] == -1).all()
+
+
+def test_reorder_inside_bfs_launch_duplicate_source(cuda):
+    """A duplicate source in one mesh of such a batch fails the prepare for
+    that mesh only (its BFS publishes nothing, the other workgroups still
+    finish); the batch prepared again with valid sources gives the results
+    of a fresh batch."""
+    import torch
+    meshes, share = _many_small_meshes()
+    V, F, S, descs, out_len = P.concat(meshes, share)
+    bad = 20
+    S2 = S.copy()
+    s0 = int(descs[bad].s_off)
+    assert int(descs[bad].n_sources) >= 1
+    if int(descs[bad].n_sources) == 1:
+        pytest.skip("mesh 20 has one source")
+    S2[s0 + 1] = S2[s0]
+    dV, dF = (torch.from_numpy(x).cuda() for x in (V, F))
+    b = P.Batch(descs, 1e-4, want_labels=True)
+    with pytest.raises(P.PTPError) as e:
+        b.prepare(dV, dF, torch.from_numpy(S2).cuda())
+    assert e.value.status == P.PTP_EINVAL
+    rc, stats, status = b.stats()
+    assert status[bad] == P.PTP_EINVAL and sum(s != P.PTP_OK for s in status) == 1
+    b.prepare(dV, dF, torch.from_numpy(S).cuda())
+    dist = torch.empty(out_len, dtype=torch.float32, device="cuda")
+    lab = torch.empty(out_len, dtype=torch.int32, device="cuda")
+    b.run(dist, lab)
+    assert b.stats()[0] == P.PTP_OK
+    ref = run_batch(meshes, share, 1e-4)
+    assert np.array_equal(dist.cpu().numpy(), ref[1].cpu().numpy())
+    assert np.array_equal(lab.cpu().numpy(), ref[2].cpu().numpy())
+
+
 def test_graph_replay_matches_eager(cuda):
     """The run enqueues kernel launches only; captured in a graph and replayed
     (with eager work and synchronisations between replays) it gives the eager
