@@ -562,6 +562,7 @@ struct ReorderArgs {
     const int* rowO;
     const int* fanO;
     const int* fanlen;
+    const int2* wedgeO;    // the incidence (the reorder inside the BFS launch builds the fans)
     int2* fanrow;
     float4* xyz;
     int* fan;
@@ -590,7 +591,7 @@ struct BfsLdsArgs {
     ReorderArgs ro;
 };
 
-__device__ bool bfs_lds(const BfsLdsArgs& a) {
+__device__ __forceinline__ bool bfs_lds(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
     const int b = a.lmesh[blockIdx.x];
@@ -800,7 +801,7 @@ __device__ inline void bfs_big_expand(const BfsLdsArgs& a, int vo, int u, int4 r
     }
 }
 
-__device__ bool bfs_big(const BfsLdsArgs& a) {
+__device__ __forceinline__ bool bfs_big(const BfsLdsArgs& a) {
     extern __shared__ unsigned lds[];
     const int tid = threadIdx.x;
     const int b = a.lmesh[blockIdx.x];
@@ -996,6 +997,69 @@ __device__ bool bfs_big(const BfsLdsArgs& a) {
     return true;
 }
 
+constexpr int kFanStage = 8;       // wedges of a vertex staged in LDS for its fan build
+
+// The chains of one vertex's wedges wd(0..c) (see kFanStart): a chain starts
+// at a wedge that no unused wedge leads into (the lowest unused one if every
+// unused wedge has a predecessor: a closed fan), and follows (a, b) -> (b, c)
+// while an unused wedge continues it.  Entry q goes to emit(q, value);
+// returns the number of entries.  Every wedge is used exactly once, as a
+// consecutive pair of one chain or as the closing pair.
+template <class Get, class Emit>
+__device__ __forceinline__ int build_fan(Get wd, int c, Emit emit) {
+    if (c > kFanChainMax) {
+        for (int q = 0; q < c; ++q) {
+            const int2 t = wd(q);
+            emit(2 * q, t.x | kFanStart);
+            emit(2 * q + 1, t.y);
+        }
+        return 2 * c;
+    }
+    unsigned left = c == 32 ? ~0u : (1u << c) - 1u;
+    int len = 0;
+    while (left) {
+        int s = __ffs(left) - 1;
+        for (unsigned m = left; m; m &= m - 1) {
+            const int i = __ffs(m) - 1;
+            const int ai = wd(i).x;
+            bool pred = false;
+            for (unsigned m2 = left; m2 && !pred; m2 &= m2 - 1) {
+                const int j = __ffs(m2) - 1;
+                pred = j != i && wd(j).y == ai;
+            }
+            if (!pred) {
+                s = i;
+                break;
+            }
+        }
+        left &= ~(1u << s);
+        const int first = wd(s).x;
+        const bool whole = len == 0;
+        emit(len++, first | kFanStart);
+        int cur = wd(s).y;
+        emit(len++, cur);
+        for (;;) {
+            int nx = -1;
+            for (unsigned m = left; m; m &= m - 1) {
+                const int j = __ffs(m) - 1;
+                if (wd(j).x == cur) {
+                    nx = j;
+                    break;
+                }
+            }
+            if (nx < 0) break;
+            left &= ~(1u << nx);
+            cur = wd(nx).y;
+            if (whole && !left && cur == first) {     // one closed chain: no repeat
+                emit(0, first | kFanStart | kFanClosed);
+                break;
+            }
+            emit(len++, cur);
+        }
+    }
+    return len;
+}
+
 // Coordinates and fans in topleset order: the position of each vertex takes
 // its coordinates and a copy of its fan with every neighbour id turned into
 // that neighbour's position (flags kept): the first kFan6 entries in its
@@ -1013,15 +1077,13 @@ constexpr int kReItems = 4;
 constexpr int kReFan = 8;
 static_assert(kReFan >= kFan6, "the fan records are filled from the entries in registers");
 
-// The vertices v[i] (internal ids, -1 for none) of meshes bq[i].  kCoh: the
-// positions were written in the same launch and are read with coherent loads.
-template <bool kCoh>
+// The vertices v[i] (internal ids, -1 for none) of meshes bq[i].
 __device__ inline void reorder_items(const float* __restrict__ V, const MeshDesc* mesh, const int* vo,
                                      const int* __restrict__ iperm, const int* __restrict__ rowO,
                                      const int* __restrict__ fanO, const int* __restrict__ fanlen,
                                      int2* __restrict__ fanrow, float4* __restrict__ xyz, int* __restrict__ fan,
                                      int* __restrict__ fan6, const long long* v, const int* bq) {
-    auto pos = [&](long long x) { return kCoh ? ld_c(iperm + x) : iperm[x]; };
+    auto pos = [&](long long x) { return iperm[x]; };
     int p[kReItems], r0[kReItems], len[kReItems], e[kReItems][kReFan];
     float c[kReItems][3];
 #pragma unroll
@@ -1080,6 +1142,102 @@ __device__ inline void reorder_items(const float* __restrict__ V, const MeshDesc
     }
 }
 
+// The reorder inside the BFS launch, which builds each vertex's fan from its
+// wedges itself (before the BFS only the BFS rows are built then): the
+// wedges of a vertex with at most kFanStage of them are staged in the
+// thread's LDS column wd_s, the first kReFan fan entries go to its column
+// row_s, later ones (raw ids) straight to the vertex's row in fan, converted
+// once this thread's stores have landed.  The vertices v[i] (-1 for none)
+// belong to mesh b; positions are read with coherent loads (written in the
+// same launch).
+__device__ __forceinline__ void reorder_items_build(const ReorderArgs& r, const long long* v, int b, int2* wd_s,
+                                           int* row_s) {
+    const int tid = threadIdx.x;
+    auto pos = [&](long long x) { return ld_c(r.iperm + x); };
+    int p[kReItems], r0[kReItems], c[kReItems], len[kReItems], e[kReItems][kReFan];
+    float x3[kReItems][3];
+    const long long vin = (long long)r.mesh[b].v_in - r.vo[b];
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+        p[i] = 0;
+        r0[i] = 0;
+        c[i] = 0;
+        x3[i][0] = x3[i][1] = x3[i][2] = 0.f;
+        if (v[i] >= 0) {
+            const float* cp = r.V + 3 * (vin + v[i]);
+            p[i] = pos(v[i]);
+            x3[i][0] = cp[0];
+            x3[i][1] = cp[1];
+            x3[i][2] = cp[2];
+            r0[i] = r.rowO[v[i]];
+            c[i] = r.rowO[v[i] + 1] - r0[i];
+        }
+    }
+    // one fan at a time through the thread's LDS columns; the next vertex's
+    // wedges are loaded while this one is built
+    int2 wn[kFanStage];
+#pragma unroll
+    for (int q = 0; q < kFanStage; ++q)
+        wn[q] = q < c[0] && c[0] <= kFanStage ? r.wedgeO[r0[0] + q] : make_int2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+#pragma unroll
+        for (int q = 0; q < kFanStage; ++q)
+            if (q < c[i] && c[i] <= kFanStage) wd_s[q * kLdsBlock + tid] = wn[q];
+        if (i + 1 < kReItems) {
+#pragma unroll
+            for (int q = 0; q < kFanStage; ++q)
+                wn[q] = q < c[i + 1] && c[i + 1] <= kFanStage ? r.wedgeO[r0[i + 1] + q] : make_int2(0, 0);
+        }
+        len[i] = 0;
+        if (v[i] >= 0) {
+            int* out = r.fan + 2 * (long long)r0[i];
+            auto emit = [&](int q, int x) {
+                if (q < kReFan) row_s[q * kLdsBlock + tid] = x;
+                else out[q] = x;
+            };
+            if (c[i] <= kFanStage)
+                len[i] = build_fan([&](int q) { return wd_s[q * kLdsBlock + tid]; }, c[i], emit);
+            else
+                len[i] = build_fan([&](int q) { return r.wedgeO[r0[i] + q]; }, c[i], emit);
+        }
+#pragma unroll
+        for (int q = 0; q < kReFan; ++q) e[i][q] = q < len[i] ? row_s[q * kLdsBlock + tid] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i)
+#pragma unroll
+        for (int q = 0; q < kReFan; ++q)
+            if (q < len[i]) e[i][q] = pos(e[i][q] & kFanId) | (e[i][q] & ~kFanId);
+    wait_memory();      // the raw entries past kReFan have landed before they are read back
+#pragma unroll
+    for (int i = 0; i < kReItems; ++i) {
+        if (v[i] < 0) continue;
+        r.xyz[p[i]] = make_float4(x3[i][0], x3[i][1], x3[i][2], 0.f);
+        const int fr = 2 * r0[i];
+        if (len[i] > kFan6) {
+            r.fanrow[p[i]] = make_int2(fr, fr + len[i]);
+#pragma unroll
+            for (int q = 0; q < kReFan; ++q)
+                if (q < len[i]) r.fan[fr + q] = e[i][q];
+            for (int q = kReFan; q < len[i]; ++q) {
+                const int x = r.fan[fr + q];
+                r.fan[fr + q] = pos(x & kFanId) | (x & ~kFanId);
+            }
+        }
+        int rec[kFan6];
+        const int first = len[i] > 0 ? e[i][0] : p[i];
+#pragma unroll
+        for (int q = 0; q < kFan6; ++q)
+            rec[q] = q < len[i] ? e[i][q] : (q == 0 ? p[i] : (first & kFanId) | kFan6Pad);
+        if (len[i] > kFan6) rec[0] |= kFan6Pad;
+        int2* r6 = reinterpret_cast<int2*>(r.fan6 + (size_t)kFan6 * p[i]);
+        r6[0] = make_int2(rec[0], rec[1]);
+        r6[1] = make_int2(rec[2], rec[3]);
+        r6[2] = make_int2(rec[4], rec[5]);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_reorder(ReorderArgs r, int B, long long N, const int* ctrl) {
     if (gated(ctrl)) return;
     for (long long t = blockIdx.x; t < (N + kTile - 1) / kTile; t += gridDim.x) {
@@ -1093,7 +1251,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(ReorderArgs r, int B, long l
                 v[i] = t * kTile + (long long)(h + i) * kBlock + threadIdx.x;
                 if (v[i] >= N) v[i] = -1;
             }
-            reorder_items<false>(r.V, r.mesh, r.vo, r.iperm, r.rowO, r.fanO, r.fanlen, r.fanrow, r.xyz, r.fan,
+            reorder_items(r.V, r.mesh, r.vo, r.iperm, r.rowO, r.fanO, r.fanlen, r.fanrow, r.xyz, r.fan,
                                  r.fan6, v, bq + h);
         }
     }
@@ -1110,8 +1268,15 @@ __global__ __launch_bounds__(kBlock) void k_reorder(ReorderArgs r, int B, long l
 // coherent loads: another CU of this XCD wrote them.
 constexpr int kReChunk = kReItems * kLdsBlock;
 constexpr int kFuseMinMeshes = 256;     // one workgroup per CU of the device
+// LDS of the reorder inside the BFS launch: per thread kFanStage staged
+// wedges and kReFan fan entries
+constexpr size_t kTailLds = (sizeof(int2) * kFanStage + sizeof(int) * kReFan) * kLdsBlock;
 
-__device__ void bfs_reorder_tail(const BfsLdsArgs& a, bool ok) {
+// The reorder runs inside the one-workgroup BFS when every mesh takes it and
+// the finished workgroups can cover the device.
+bool fuse_reorder(int g_prep, int n_one) { return g_prep == 0 && n_one >= kFuseMinMeshes; }
+
+__device__ __forceinline__ void bfs_reorder_tail(const BfsLdsArgs& a, bool ok) {
     __shared__ int job[2];
     const int tid = threadIdx.x;
     const int x = (int)(xcc_id() & 7u);
@@ -1166,16 +1331,14 @@ __device__ void bfs_reorder_tail(const BfsLdsArgs& a, bool ok) {
         if (b < 0) return;
         const long long v0 = a.mesh[b].v_off + (long long)c * kReChunk, v1 = a.mesh[b].v_off + a.mesh[b].n;
         long long v[kReItems];
-        int bq[kReItems];
 #pragma unroll
         for (int i = 0; i < kReItems; ++i) {
             v[i] = v0 + (long long)i * kLdsBlock + tid;
             if (v[i] >= v1) v[i] = -1;
-            bq[i] = b;
         }
-        const ReorderArgs& r = a.ro;
-        reorder_items<true>(r.V, r.mesh, r.vo, r.iperm, r.rowO, r.fanO, r.fanlen, r.fanrow, r.xyz, r.fan, r.fan6,
-                            v, bq);
+        extern __shared__ unsigned lds[];     // free once the BFS is done: at least kTailLds bytes
+        int2* wd_s = reinterpret_cast<int2*>(lds);
+        reorder_items_build(a.ro, v, b, wd_s, reinterpret_cast<int*>(wd_s + kFanStage * kLdsBlock));
     }
 }
 
@@ -1188,67 +1351,6 @@ __global__ __launch_bounds__(kLdsBlock) void k_bfs_one(BfsLdsArgs a) {
     if (a.fuse) bfs_reorder_tail(a, ok);
 }
 
-// The chains of one vertex's wedges wd(0..c) (see kFanStart): a chain starts
-// at a wedge that no unused wedge leads into (the lowest unused one if every
-// unused wedge has a predecessor: a closed fan), and follows (a, b) -> (b, c)
-// while an unused wedge continues it.  Entry q goes to emit(q, value);
-// returns the number of entries.  Every wedge is used exactly once, as a
-// consecutive pair of one chain or as the closing pair.
-template <class Get, class Emit>
-__device__ inline int build_fan(Get wd, int c, Emit emit) {
-    if (c > kFanChainMax) {
-        for (int q = 0; q < c; ++q) {
-            const int2 t = wd(q);
-            emit(2 * q, t.x | kFanStart);
-            emit(2 * q + 1, t.y);
-        }
-        return 2 * c;
-    }
-    unsigned left = c == 32 ? ~0u : (1u << c) - 1u;
-    int len = 0;
-    while (left) {
-        int s = __ffs(left) - 1;
-        for (unsigned m = left; m; m &= m - 1) {
-            const int i = __ffs(m) - 1;
-            const int ai = wd(i).x;
-            bool pred = false;
-            for (unsigned m2 = left; m2 && !pred; m2 &= m2 - 1) {
-                const int j = __ffs(m2) - 1;
-                pred = j != i && wd(j).y == ai;
-            }
-            if (!pred) {
-                s = i;
-                break;
-            }
-        }
-        left &= ~(1u << s);
-        const int first = wd(s).x;
-        const bool whole = len == 0;
-        emit(len++, first | kFanStart);
-        int cur = wd(s).y;
-        emit(len++, cur);
-        for (;;) {
-            int nx = -1;
-            for (unsigned m = left; m; m &= m - 1) {
-                const int j = __ffs(m) - 1;
-                if (wd(j).x == cur) {
-                    nx = j;
-                    break;
-                }
-            }
-            if (nx < 0) break;
-            left &= ~(1u << nx);
-            cur = wd(nx).y;
-            if (whole && !left && cur == first) {     // one closed chain: no repeat
-                emit(0, first | kFanStart | kFanClosed);
-                break;
-            }
-            emit(len++, cur);
-        }
-    }
-    return len;
-}
-
 // Fans by vertex id.  A vertex's wedges (loaded together and staged in LDS,
 // one column per thread, when there are at most kFanStage; 24 KB of LDS per
 // workgroup leave room for six workgroups per CU) are chained into fanO at
@@ -1257,8 +1359,6 @@ __device__ inline int build_fan(Get wd, int c, Emit emit) {
 // the fan's ids (each neighbour named once per chain) padded with -1, or
 // kEllMore in the last entry when the fan has more than kEll entries (the
 // BFS then expands the vertex from its wedges).
-constexpr int kFanStage = 8;
-
 __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const int2* wedgeO, long long N,
                                                        int* fanO, int* fanlen, int* ellO, const int* ctrl) {
     if (gated(ctrl)) return;
@@ -1310,6 +1410,50 @@ __global__ __launch_bounds__(kBlock) void k_fan_global(const int* rowO, const in
     }
 }
 
+// The BFS rows alone (the fans are then built by the reorder inside the BFS
+// launch): each vertex's distinct neighbours, the ends of its wedges, padded
+// with -1, or kEllMore in the last entry when it has more than kEll of them
+// or more than kEll wedges (the BFS then expands it from its wedges).  The
+// neighbours are a set to the BFS, so their order does not matter.
+__global__ __launch_bounds__(kBlock) void k_ell_rows(const int* rowO, const int2* wedgeO, long long N, int* ellO,
+                                                     const int* ctrl) {
+    if (gated(ctrl)) return;
+    const long long gsz = (long long)gridDim.x * kBlock;
+    for (long long v = blockIdx.x * (long long)kBlock + threadIdx.x; v < N; v += gsz) {
+        const int r0 = rowO[v], c = rowO[v + 1] - r0;
+        int nb[kEll];
+#pragma unroll
+        for (int q = 0; q < kEll; ++q) nb[q] = -1;
+        if (c > kEll) {
+            nb[kEll - 1] = kEllMore;
+        } else {
+            int x[2 * kEll];
+#pragma unroll
+            for (int q = 0; q < kEll; ++q) {
+                const int2 w = q < c ? wedgeO[r0 + q] : make_int2(-1, -1);
+                x[2 * q] = w.x;
+                x[2 * q + 1] = w.y;
+            }
+            // rank of each first occurrence among the first occurrences
+            int rank = 0;
+#pragma unroll
+            for (int j = 0; j < 2 * kEll; ++j) {
+                bool first = x[j] >= 0;
+#pragma unroll
+                for (int k = 0; k < j; ++k) first = first && x[k] != x[j];
+#pragma unroll
+                for (int q = 0; q < kEll; ++q)
+                    if (first && rank == q) nb[q] = x[j];
+                rank += first ? 1 : 0;
+            }
+            if (rank > kEll) nb[kEll - 1] = kEllMore;
+        }
+        int4* er = reinterpret_cast<int4*>(ellO + kEll * v);
+        er[0] = make_int4(nb[0], nb[1], nb[2], nb[3]);
+        er[1] = make_int4(nb[4], nb[5], nb[6], nb[7]);
+    }
+}
+
 int tile_grid(long long total) {
     const long long t = (total + kTile - 1) / kTile;
     return (int)(t < 1 ? 1 : (t > 8192 ? 8192 : t));
@@ -1343,8 +1487,11 @@ hipError_t launch_prepare(const Work& w, const Sizes& z, const float* V, const i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_incidence, dim3(tile_grid(F3)), dim3(kBlock), 0, st, F, w.mesh, z.B,
                        w.fo3, F3, w.rowO, w.cursor, w.wedgeO, w.ctrl);
-    hipLaunchKernelGGL(k_fan_global, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.fanO,
-                       w.fanlen, w.ellO, w.ctrl);
+    if (fuse_reorder(g_prep, n_one))     // the fans are built by the reorder inside the BFS launch
+        hipLaunchKernelGGL(k_ell_rows, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.ellO, w.ctrl);
+    else
+        hipLaunchKernelGGL(k_fan_global, dim3(grid_for(N)), dim3(kBlock), 0, st, w.rowO, w.wedgeO, N, w.fanO,
+                           w.fanlen, w.ellO, w.ctrl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_prepare_bfs(w, z, V, S, g_prep, n_one, n_big, st);
@@ -1384,13 +1531,12 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
     ro.rowO = w.rowO;
     ro.fanO = w.fanO;
     ro.fanlen = w.fanlen;
+    ro.wedgeO = w.wedgeO;
     ro.fanrow = w.fanrow;
     ro.xyz = w.xyz;
     ro.fan = w.fan;
     ro.fan6 = w.fan6;
-    // the reorder runs inside the one-workgroup BFS when every mesh takes it
-    // and the finished workgroups can cover the device
-    const bool fuse = g_prep == 0 && n_one >= kFuseMinMeshes;
+    const bool fuse = fuse_reorder(g_prep, n_one);
     if (n_one > 0) {
         BfsLdsArgs l;
         l.lmesh = w.lds_mesh;
@@ -1415,8 +1561,9 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
         if (fuse)
             hipLaunchKernelGGL(k_fill, dim3(grid_for(kRqWords + 9ll * z.B)), dim3(kBlock), 0, st, w.rq,
                                kRqWords + 9ll * z.B, 0);
-        hipLaunchKernelGGL(k_bfs_one, dim3(n_one), dim3(kLdsBlock), bfs_one_bytes(z.lds_words, z.big_words), st,
-                           l);
+        size_t bytes = bfs_one_bytes(z.lds_words, z.big_words);
+        if (fuse && bytes < kTailLds) bytes = kTailLds;
+        hipLaunchKernelGGL(k_bfs_one, dim3(n_one), dim3(kLdsBlock), bytes, st, l);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
