@@ -287,7 +287,7 @@ size_t work_layout(const Sizes& z, Layout* L) {
         sizeof(double) * (size_t)z.S * (kCvtChunks * 6 + 4),   // cvt partial sums, centroids
         sizeof(int) * N,                       // mark
         sizeof(int) * kFan6 * N,               // fan6
-        sizeof(int) * (kRqWords + 9 * B),       // rq
+        sizeof(int) * (kRqWords + 10 * B),      // rq
     };
     size_t off = 0;
     for (int i = 0; i < kLayoutParts; ++i) {

@@ -81,20 +81,22 @@ struct Work {
     double* cvt;        // [S * kCvtChunks * 6] partial cell sums of the Lloyd step
     int* mark;          // [N]     per position: the last iteration + 1 in which a neighbour changed
     int* fan6;          // [6N]    per position its first kFan6 fan entries in a fixed-size record
-    int* rq;            // [kRqWords + 9B] queues of the reorder inside the one-workgroup BFS
+    int* rq;            // [kRqWords + 10B] queues of the reorder inside the one-workgroup BFS
 };
 
 constexpr int kLayoutParts = 39;
 
 // The reorder of a batch inside its one-workgroup BFS launch.  A workgroup
 // that has finished its mesh's BFS publishes the mesh in the queue of the XCD
-// it runs on, then reorders chunks of the meshes published on that XCD (the
-// positions were written through that XCD's L2).  rq: kRqWords control words
-// (RQ_STARTED, RQ_FINISHED, RQ_SLOTS + x: slots taken in the queue of XCD x),
-// then eight queues of B slots (mesh + 1; 0 until published), then per mesh
-// the number of its chunks claimed.  Zeroed before the launch.
+// it runs on (the positions were written through that XCD's L2), or, for the
+// last meshes to finish, in a queue shared by all XCDs after writing its L2
+// back; it then reorders chunks of published meshes.  rq: kRqWords control
+// words (RqWord; RQ_SLOTS + x: slots taken in the queue of XCD x), then eight
+// queues of B slots (mesh + 1; 0 until published), the shared queue of B
+// slots, then per mesh the number of its chunks claimed.  Zeroed before the
+// launch.
 constexpr int kRqWords = 16;
-enum RqWord : int { RQ_STARTED = 0, RQ_FINISHED = 1, RQ_SLOTS = 8 };
+enum RqWord : int { RQ_STARTED = 0, RQ_FINISHED = 1, RQ_FINISHING = 2, RQ_SHARED = 3, RQ_SLOTS = 8 };
 
 // Lloyd step: every cell's sums are split over this many chunks of the
 // faces (or vertices), each reduced in a fixed order.

@@ -1260,13 +1260,18 @@ __global__ __launch_bounds__(kBlock) void k_reorder(ReorderArgs r, int B, long l
 // The reorder of a batch inside its one-workgroup BFS launch (see kRqWords).
 // The mesh's positions are in this XCD's L2 once every thread's stores have
 // completed; the mesh then goes into this XCD's queue (a coherent store,
-// completed before the workgroup counts itself finished).  Thread 0 claims
-// chunks of kReChunk vertices from the queue's meshes in turn; with none left
+// completed before the workgroup counts itself finished).  The last
+// kShareLast meshes to finish (the deepest, whose reorder ends the launch)
+// go instead into a queue every XCD reads, after a release fence has
+// written this XCD's L2 back to memory.  Thread 0 claims chunks of kReChunk
+// vertices from its XCD's queue, then from the shared one; with none left
 // it waits, but only while some BFS is still running and every workgroup of
 // the launch has started (so a waiting workgroup never holds the place of one
 // that has yet to run), and leaves otherwise.  The positions are read with
-// coherent loads: another CU of this XCD wrote them.
+// coherent loads, which see what another CU of this XCD wrote or what a
+// fence wrote back.
 constexpr int kReChunk = kReItems * kLdsBlock;
+constexpr int kShareLast = 16;
 constexpr int kFuseMinMeshes = 256;     // one workgroup per CU of the device
 // LDS of the reorder inside the BFS launch: per thread kFanStage staged
 // wedges and kReFan fan entries
@@ -1280,42 +1285,56 @@ __device__ __forceinline__ void bfs_reorder_tail(const BfsLdsArgs& a, bool ok) {
     __shared__ int job[2];
     const int tid = threadIdx.x;
     const int x = (int)(xcc_id() & 7u);
-    int* slots = a.rq + kRqWords + x * a.B;
-    int* claimed = a.rq + kRqWords + 8 * a.B;
+    int* own = a.rq + kRqWords + x * a.B;
+    int* shared = a.rq + kRqWords + 8 * a.B;
+    int* claimed = a.rq + kRqWords + 9 * a.B;
     wait_memory();
     __syncthreads();
     if (tid == 0) {
         if (ok) {
-            const int s = atomicAdd(a.rq + RQ_SLOTS + x, 1);
-            st_c(slots + s, a.lmesh[blockIdx.x] + 1);
+            if (atomicAdd(a.rq + RQ_FINISHING, 1) >= a.n_one - kShareLast) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");     // this XCD's L2 to memory
+                const int s = atomicAdd(a.rq + RQ_SHARED, 1);
+                st_c(shared + s, a.lmesh[blockIdx.x] + 1);
+            } else {
+                const int s = atomicAdd(a.rq + RQ_SLOTS + x, 1);
+                st_c(own + s, a.lmesh[blockIdx.x] + 1);
+            }
             wait_memory();
         }
         atomicAdd(a.rq + RQ_FINISHED, 1);
     }
-    int cur = 0;    // thread 0: the next slot of the queue that may have chunks left
+    int cur0 = 0, cur1 = 0;    // thread 0: per queue, the next slot that may have chunks left
     for (;;) {
         if (tid == 0) {
             int b = -1, c = 0;
             const long long t0 = wall_clock64();
             for (;;) {
                 const int fin = ld_c(a.rq + RQ_FINISHED);
-                const int taken = ld_c(a.rq + RQ_SLOTS + x);
-                while (cur < taken) {
-                    const int mb = ld_c(slots + cur);
-                    if (mb == 0) break;           // taken, not yet published
-                    const int nc = (a.mesh[mb - 1].n + kReChunk - 1) / kReChunk;
-                    const int k = atomicAdd(claimed + mb - 1, 1);
-                    if (k < nc) {
-                        b = mb - 1;
-                        c = k;
-                        break;
+                bool drained = true;     // every slot taken so far is published and fully claimed
+                auto claim = [&](int* slots, int taken, int& cur) {
+                    while (b < 0 && cur < taken) {
+                        const int mb = ld_c(slots + cur);
+                        if (mb == 0) {           // taken, not yet published
+                            drained = false;
+                            return;
+                        }
+                        const int nc = (a.mesh[mb - 1].n + kReChunk - 1) / kReChunk;
+                        const int k = atomicAdd(claimed + mb - 1, 1);
+                        if (k < nc) {
+                            b = mb - 1;
+                            c = k;
+                            return;
+                        }
+                        ++cur;
                     }
-                    ++cur;
-                }
+                };
+                claim(own, ld_c(a.rq + RQ_SLOTS + x), cur0);
+                if (b < 0) claim(shared, ld_c(a.rq + RQ_SHARED), cur1);
                 if (b >= 0) break;
                 // nothing to claim: leave when every BFS has finished (all
                 // published meshes are claimed) or when waiting is not safe
-                if (cur >= taken && (fin >= a.n_one || ld_c(a.rq + RQ_STARTED) < a.n_one)) break;
+                if (drained && (fin >= a.n_one || ld_c(a.rq + RQ_STARTED) < a.n_one)) break;
                 if (wall_clock64() - t0 > FlagBarrier::kTimeoutTicks) {     // cannot happen: fail, not hang
                     __hip_atomic_fetch_or(a.ctrl + C_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
@@ -1559,8 +1578,8 @@ hipError_t launch_prepare_bfs(const Work& w, const Sizes& z, const float* V, con
         l.rq = w.rq;
         l.ro = ro;
         if (fuse)
-            hipLaunchKernelGGL(k_fill, dim3(grid_for(kRqWords + 9ll * z.B)), dim3(kBlock), 0, st, w.rq,
-                               kRqWords + 9ll * z.B, 0);
+            hipLaunchKernelGGL(k_fill, dim3(grid_for(kRqWords + 10ll * z.B)), dim3(kBlock), 0, st, w.rq,
+                               kRqWords + 10ll * z.B, 0);
         size_t bytes = bfs_one_bytes(z.lds_words, z.big_words);
         if (fuse && bytes < kTailLds) bytes = kTailLds;
         hipLaunchKernelGGL(k_bfs_one, dim3(n_one), dim3(kLdsBlock), bytes, st, l);
