@@ -654,7 +654,11 @@ class Batch:
         st = (Stats * self.count)()
         status = (C.c_int32 * self.count)()
         rc = self._lib.ptp_batch_get_stats(self._h, st, status)
-        return rc, [s.as_dict() for s in st], [int(x) for x in status]
+        # one dict per mesh, built from a structured view of the array (a
+        # field-by-field read of 512 structures costs milliseconds)
+        names = [f for f, _ in Stats._fields_]
+        rows = np.ctypeslib.as_array(st).tolist()
+        return rc, [dict(zip(names, r)) for r in rows], list(status)
 
     def parents(self, stream=None):
         """Parents behind the labels of the last (labelled) run: int32
