@@ -85,7 +85,7 @@ def tune(batch, descs, dist, label=None, use_cache: bool = True) -> dict:
 def tune_window(batch, dist, candidates=(0, 256, 128, 64, 48, 32, 24, 16), tol=1e-4, reps=2,
                 stream=None):
     """Band cap for a prepared batch: the fastest window whose distances stay
-    within `tol` (relative) of the unbounded run's, which is the judge.  Each
+    within `tol` (relative) of the unbounded run's (the reference).  Each
     candidate is run once to check it, then timed over `reps` runs with
     device events.  Installs the choice and returns
     {"window", "ms", "max_rel_diff", "tried": [(window, ms, max_rel_diff), ...]}."""
