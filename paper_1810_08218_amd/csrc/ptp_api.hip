@@ -100,9 +100,14 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const CostFn& est, const 
             ng[0] = 1;
             used += 1;
         }
+        // each mesh's estimate at its class's group size, computed once
+        std::vector<double> cost(B, 0.0);
         double C[3] = {0, 0, 0};
         for (int c = 0; c < 3; ++c)
-            for (int b : members[c]) C[c] += est(b, size_c[c]);
+            for (int b : members[c]) {
+                cost[b] = est(b, size_c[c]);
+                C[c] += cost[b];
+            }
         // hand out the remaining workgroups to the class with the largest load per group
         for (;;) {
             int best = -1;
@@ -125,7 +130,7 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const CostFn& est, const 
             if (members[c].empty()) continue;
             std::vector<int> ord = members[c];
             const int sc = size_c[c];
-            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return est(x, sc) > est(y, sc); });
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
             qlists[c] = ord;
             const int first = (int)groups.size();
             for (int g = 0; g < ng[c]; ++g) {
@@ -140,7 +145,7 @@ Sched make_schedule(const std::vector<MeshDesc>& mesh, const CostFn& est, const 
                 Item it = heap.top();
                 heap.pop();
                 groups[it.second].push_back(b);
-                it.first += est(b, sc);
+                it.first += cost[b];
                 heap.push(it);
                 s.gsize_of[b] = sc;
             }
